@@ -1,0 +1,163 @@
+"""FP64 CPU oracle for the stereo path (Sec. 2.2, Eq. 1-2) -- TEST INFRASTRUCTURE.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It wraps ``libbp_oracle.so`` (plain C, FP64, built from
+``bp_oracle.c`` by ``oracle/build.py``) with numpy arrays.  It imports nothing
+from the GPU library and the GPU library imports nothing from it.
+
+Message arrays use the layout [4][L][H][W]; slot k holds the message a pixel
+received from its neighbour on side k (0 left, 1 right, 2 up, 3 down).
+
+Parity pins: every function here is pinned by the ``-m "not gpu"`` tests
+(brute force, chain and tree dynamic programming, enumeration, closed forms,
+worked examples under tests/golden).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libbp_oracle.so")
+_lib = None
+
+STORE_F64, STORE_F16, STORE_BF16, STORE_F32 = 0, 1, 2, 3
+_dp = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    """Load (building first if absent) the oracle shared library."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        i = ctypes.c_int
+        d = ctypes.c_double
+        L.bpo_downsample.argtypes = [_u8p, i, i, i, i, _u8p]
+        L.bpo_cost_volume.argtypes = [_u8p, _u8p, i, i, i, i, d, i, _dp]
+        L.bpo_dt.argtypes = [_dp, i, d, d, _dp]
+        L.bpo_dt.restype = None
+        L.bpo_dt_brute.argtypes = [_dp, i, d, d, _dp]
+        L.bpo_dt_brute.restype = None
+        L.bpo_run.argtypes = [_dp, i, i, i, i, i, d, d, i, i, _u8p, _dp, _dp, _i32p, _dp, d, i]
+        L.bpo_pyramid.argtypes = [_dp, i, i, i, i, _dp]
+        L.bpo_upsample.argtypes = [_i32p, i, i, _u8p, i, i, i, d, d, i, _dp, i]
+        L.bpo_round_f16.argtypes = [d]
+        L.bpo_round_f16.restype = d
+        L.bpo_round_bf16.argtypes = [d]
+        L.bpo_round_bf16.restype = d
+        L.bpo_max_threads.restype = i
+        if hasattr(L, "bpo_backward"):
+            L.bpo_backward.argtypes = [_dp, i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, i]
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with status {rc}")
+
+
+def _img(a):
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    if a.ndim == 2:
+        return a, a.shape[0], a.shape[1], 1
+    return a, a.shape[0], a.shape[1], a.shape[2]
+
+
+def downsample(img, s: int):
+    a, H, W, C = _img(img)
+    out = np.empty((H // s, W // s) + ((C,) if img.ndim == 3 else ()), dtype=np.uint8)
+    _check(lib().bpo_downsample(_p(a, _u8p), W, H, C, s, _p(out, _u8p)), "downsample")
+    return out
+
+
+def cost_volume(left, right, num_labels: int, data_trunc: float = 20.0, rgb_mode: int = 0):
+    """Truncated absolute-difference cost [L][H][W] (float64)."""
+    a, H, W, C = _img(left)
+    b, _, _, _ = _img(right)
+    out = np.empty((num_labels, H, W), dtype=np.float64)
+    _check(lib().bpo_cost_volume(_p(a, _u8p), _p(b, _u8p), W, H, C, num_labels, float(data_trunc),
+                                 int(rgb_mode), _p(out, _dp)), "cost_volume")
+    return out
+
+
+def dt(h, lam: float, tau: float, brute: bool = False):
+    """One normalised message: min_g h(g) + lam*min(|f-g|, tau), minus its minimum."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    out = np.empty_like(h)
+    fn = lib().bpo_dt_brute if brute else lib().bpo_dt
+    fn(_p(h, _dp), h.shape[0], float(lam), float(tau), _p(out, _dp))
+    return out
+
+
+def pyramid(cost, level: int):
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    L, H, W = cost.shape
+    w, h = W, H
+    for _ in range(level):
+        w, h = (w + 1) // 2, (h + 1) // 2
+    out = np.empty((L, h, w), dtype=np.float64)
+    _check(lib().bpo_pyramid(_p(cost, _dp), W, H, L, level, _p(out, _dp)), "pyramid")
+    return out
+
+
+def run(cost, levels: int = 1, iters: int = 10, lam: float = 10.0, tau: float = 2.0, *,
+        store_mode: int = STORE_F64, brute: bool = False, edges=None, msgs_init=None,
+        want_msgs: bool = False, want_soft: bool = False, temperature: float = 0.5,
+        nthreads: int = 0):
+    """Hierarchical checkerboard BP.  Returns dict(disp, soft?, msgs?)."""
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    L, H, W = cost.shape
+    disp = np.empty((H, W), dtype=np.int32)
+    soft = np.empty((H, W), dtype=np.float64) if want_soft else None
+    msgs = np.empty((4, L, H, W), dtype=np.float64) if want_msgs else None
+    if edges is not None:
+        edges = np.ascontiguousarray(edges, dtype=np.uint8)
+    if msgs_init is not None:
+        msgs_init = np.ascontiguousarray(msgs_init, dtype=np.float64)
+    rc = lib().bpo_run(_p(cost, _dp), W, H, L, int(levels), int(iters), float(lam), float(tau),
+                       int(store_mode), 1 if brute else 0, _p(edges, _u8p), _p(msgs_init, _dp),
+                       _p(msgs, _dp), _p(disp, _i32p), _p(soft, _dp), float(temperature),
+                       int(nthreads))
+    _check(rc, "run")
+    out = {"disp": disp}
+    if want_soft:
+        out["soft"] = soft
+    if want_msgs:
+        out["msgs"] = msgs
+    return out
+
+
+def upsample(disp_lo, guide, sigma_s: float = 8.0, sigma_r: float = 12.0, radius: int = -1,
+             nthreads: int = 0):
+    """Joint bilateral upsampling (Eq. 2) -> float64 [H_hi][W_hi] in label units."""
+    d = np.ascontiguousarray(disp_lo, dtype=np.int32)
+    g, hh, wh, C = _img(guide)
+    hl, wl = d.shape
+    out = np.empty((hh, wh), dtype=np.float64)
+    _check(lib().bpo_upsample(_p(d, _i32p), wl, hl, _p(g, _u8p), wh, hh, C, float(sigma_s),
+                              float(sigma_r), int(radius), _p(out, _dp), int(nthreads)), "upsample")
+    return out
+
+
+def round_f16(x: float) -> float:
+    return lib().bpo_round_f16(float(x))
+
+
+def round_bf16(x: float) -> float:
+    return lib().bpo_round_bf16(float(x))
+
+
+def max_threads() -> int:
+    return lib().bpo_max_threads()

@@ -1,0 +1,31 @@
+"""Compile the FP64 oracle (plain C, OpenMP) into oracle/libbp_oracle.so.
+
+Test infrastructure: the resulting library is loaded only by the test suite,
+the smoke check and the benchmark's CPU-baseline leg.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["bp_oracle.c", "bp_oracle_adjoint.c"]
+LIB = os.path.join(HERE, "libbp_oracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    tmp = LIB + ".tmp"
+    # Generic x86-64 code: the library travels to other hosts with the tree.
+    cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
+           "-Wno-unused-parameter", "-o", tmp] + srcs + ["-lm"]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))
