@@ -307,8 +307,9 @@ static void pyramid_level(const double *fine, int Wf, int Hf, int L, double *coa
  *   levels       number of pyramid levels (1 = plain single-level BP)
  *   iters        half-sweeps per level; iteration t of every level updates
  *                the pixels with (x + y + t) mod 2 == 0
- *   store_mode   0 FP64 messages; 1/2 round every stored message to binary16 /
- *                bfloat16 except at the coarsest level; 3 round to binary32
+ *   store_mode   0 FP64 messages; 1/2 round every stored message (sent or
+ *                copied from the parent) to binary16 / bfloat16, except at the
+ *                coarsest level; 3 round to binary32
  *   dt_mode      0 two-pass distance transform, 1 O(L^2) definition
  *   edges        optional test-only edge mask at the finest level (levels must be 1)
  *   msgs_init    optional [4][L][H][W] initial messages (levels must be 1)
@@ -347,18 +348,20 @@ int bpo_run(const double *cost, int W, int H, int L, int levels, int iters, doub
         size_t n = (size_t)4 * L * g.H * g.W;
         double *m = (double *)calloc(n, sizeof(double));
         if (!m) return BPO_ENOMEM;
+        /* 16-bit storage never applies to the coarsest level. */
+        int sm = (l == levels - 1 && (store_mode == 1 || store_mode == 2)) ? 0 : store_mode;
         if (parent) {
+            /* The copy lands in this level's storage format. */
             for (int k = 0; k < 4; ++k)
                 for (int d = 0; d < L; ++d)
                     for (int y = 0; y < g.H; ++y)
                         for (int x = 0; x < g.W; ++x)
-                            MSG(m, &g, k, d, y, x) = parent[(((long)k * L + d) * Hp + y / 2) * Wp + x / 2];
+                            MSG(m, &g, k, d, y, x) =
+                                store_round(parent[(((long)k * L + d) * Hp + y / 2) * Wp + x / 2], sm);
             free(parent);
         } else if (msgs_init) {
             memcpy(m, msgs_init, n * sizeof(double));
         }
-        /* 16-bit storage never applies to the coarsest level. */
-        int sm = (l == levels - 1 && (store_mode == 1 || store_mode == 2)) ? 0 : store_mode;
         for (int t = 0; t < iters; ++t) half_sweep(&g, costs[l], m, t, lambda, tau, sm, dt_mode);
         if (l == 0) {
             readout(&g, costs[0], m, disp, soft, temperature);
