@@ -1,0 +1,213 @@
+/*
+ * bp.h -- C ABI of libbpstereo: dense two-view stereo by hierarchical min-sum
+ * loopy belief propagation with joint bilateral upsampling, for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method: "Towards Real-time 3D Reconstruction using Consumer UAVs", Sec. 2.2.
+ * A rectified pair is downsampled, matched by minimising the per-pixel energy
+ * of Eq. 1 (data term plus the messages of the four neighbours) with belief
+ * propagation, read out as the minimising label, and upsampled to the full
+ * resolution with the joint bilateral filter of Eq. 2.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers to images, volumes, disparities, workspaces and checkpoints are
+ *    DEVICE pointers owned by the caller.  Descriptor structs (bp_problem,
+ *    bp_params) live in HOST memory and are only read during the call.
+ *  - The library never allocates or frees device memory: scratch space comes
+ *    from a caller-provided workspace whose size is returned by a query.
+ *  - All work is enqueued on the given stream; no entry point except the
+ *    measurement call bp_run_profiled synchronises the host, so every other
+ *    call can be captured into a HIP graph.
+ *  - Arguments are validated on the host before anything is enqueued.  On an
+ *    error nothing is enqueued and a negative bp_status is returned.  A launch
+ *    failure reported by the HIP runtime returns BP_ERR_HIP.  Text for any
+ *    status: bp_status_string().
+ *  - Calls are thread-safe: the only process-wide state is a read-only
+ *    launch-shape table loaded at first use.
+ *  - Image layout: row-major [H][row_stride] bytes, pixels of `channels`
+ *    interleaved uint8 samples (1 = grey, 3 = RGB).  Volume layout: planar
+ *    [L][H][W] float32, label-major.  Disparities: [H][W].
+ *  - Left is the reference view: left pixel (x, y) at disparity d matches
+ *    right pixel (x - d, y).
+ */
+#ifndef BPSTEREO_BP_H
+#define BPSTEREO_BP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BP_OK = 0,
+    BP_ERR_INVALID_ARGUMENT = -1,   /* a size, pointer or parameter is out of range */
+    BP_ERR_UNSUPPORTED = -2,        /* valid but not supported (e.g. label count) */
+    BP_ERR_WORKSPACE_TOO_SMALL = -3,/* workspace or checkpoint buffer smaller than queried */
+    BP_ERR_HIP = -4                 /* the HIP runtime reported an error at launch */
+} bp_status;
+
+/* Storage format of BP messages.  Arithmetic is FP32 in every format; the
+ * coarsest pyramid level always stores FP32. */
+typedef enum { BP_MSG_F32 = 0, BP_MSG_F16 = 1, BP_MSG_BF16 = 2 } bp_msg_dtype;
+
+/* One rectified pair's BP problem at the matching (low) resolution. */
+typedef struct {
+    int32_t width, height;     /* finest BP grid, >= 1 each */
+    int32_t num_labels;        /* L in [2, 256] */
+    const float *cost;         /* [L][height][width] data term E_D of Eq. 1, finest level */
+    int32_t *disparity;        /* [height][width] argmin label output, or NULL */
+    float *soft_disparity;     /* [height][width] soft-argmin output (label units), or NULL */
+    float *messages_out;       /* [4][L][height][width] final finest-level messages, or NULL.
+                                  Slot k = message received from the neighbour on side k
+                                  (0 left, 1 right, 2 up, 3 down); 0 where there is none. */
+} bp_problem;
+
+/* Parameters of the method, shared by every problem of a call. */
+typedef struct {
+    int32_t levels;            /* pyramid levels n >= 1 (1 = single-level BP) */
+    int32_t iters_per_level;   /* half-sweeps per level K >= 0 */
+    float lambda;              /* smoothness weight >= 0: V(f,g) = lambda * min(|f-g|, tau) */
+    float tau;                 /* truncation in labels > 0 */
+    int32_t msg_dtype;         /* bp_msg_dtype */
+    float temperature;         /* soft-argmin temperature T > 0 (used when soft_disparity != NULL) */
+    int32_t checkpoint_every;  /* 0 = none; k > 0 saves the message state every k half-sweeps
+                                  of the finest level into the checkpoint buffer (adjoint) */
+    int32_t variant;           /* 0 = library choice (tuned table); otherwise a kernel variant
+                                  id from bp_variant_count() for testing and tuning */
+} bp_params;
+
+/*
+ * a1 + a2. Data term of Eq. 1 (the paper leaves its form open; this library
+ * uses the truncated absolute difference).
+ *   cost(d, x, y) = min(a(x, y, d), data_trunc)  if x - d >= 0, else data_trunc
+ * where a is |I_L - I_R| for grey input and the channel mean of the absolute
+ * differences for RGB: rounded to nearest, floor((sum + 1) / 3), when
+ * rgb_mode == 0 (every value stays an integer), the exact mean when 1.
+ * If downsample = s > 1 both images are first reduced by the s x s block mean
+ * rounded half up (Sec. 2.2 matches on downsampled frames); width and height
+ * must then be multiples of s and the output grid is (width/s) x (height/s).
+ *   left, right   device images [height][row_stride_bytes], channels 1 or 3
+ *   cost          device float32 [num_labels][height/s][width/s], written fully
+ * Errors: BP_ERR_INVALID_ARGUMENT for NULL pointers, non-positive sizes,
+ * channels not 1/3, stride < width*channels, s not dividing the sizes,
+ * num_labels outside [1, 256], data_trunc < 0.
+ */
+bp_status bp_cost_volume(const uint8_t *left, const uint8_t *right, int32_t width, int32_t height,
+                         int32_t channels, int64_t row_stride_bytes, int32_t downsample,
+                         int32_t num_labels, float data_trunc, int32_t rgb_mode, float *cost,
+                         hipStream_t stream);
+
+/*
+ * a1 alone: s x s block mean rounded half up, out [height/s][width/s][channels]
+ * packed.  Same argument rules as bp_cost_volume.
+ */
+bp_status bp_downsample(const uint8_t *in, int32_t width, int32_t height, int32_t channels,
+                        int64_t row_stride_bytes, int32_t downsample, uint8_t *out, hipStream_t stream);
+
+/* Workspace bytes bp_run needs for `count` problems with `params`; 0 on invalid input. */
+size_t bp_workspace_size(const bp_problem *probs, int32_t count, const bp_params *params);
+
+/* Checkpoint bytes bp_run writes when params->checkpoint_every > 0 (else 0). */
+size_t bp_checkpoint_size(const bp_problem *probs, int32_t count, const bp_params *params);
+
+/*
+ * a3-a6 (and the batched form when count > 1). Minimises Eq. 1 by
+ * coarse-to-fine min-sum BP and reads out the minimising label:
+ *  - pyramid: level l cost = sum of its (up to four) level l-1 children;
+ *    W_l = ceil(W_{l-1} / 2), likewise H;
+ *  - the coarsest level starts from zero messages, each finer level from a
+ *    copy of its parent's final messages (pixel (x,y) takes (x/2, y/2));
+ *  - half-sweep t of a level (t = 0..K-1) updates every pixel with
+ *    (x + y + t) mod 2 == 0: to each 4-neighbour q it sends the distance
+ *    transform of h(f) = cost(f) + sum of its incoming messages except q's,
+ *    m(f) = min_g h(g) + lambda * min(|f - g|, tau), minus min_f m(f);
+ *  - readout: b(f) = cost(f) + sum of the four incoming messages; disparity =
+ *    lowest f minimising b (Eq. 1's readout); soft = sum_f f w(f) / sum_f w(f)
+ *    with w(f) = exp(-(b(f) - min b) / T).
+ * probs     host array of `count` problems (count >= 1); each may differ in
+ *           size and label count
+ * workspace device scratch of at least bp_workspace_size() bytes, 256-byte aligned
+ * checkpoints device buffer of bp_checkpoint_size() bytes, or NULL when
+ *           checkpoint_every == 0 (used by bp_backward)
+ * Errors: BP_ERR_INVALID_ARGUMENT (bad sizes, NULL cost, lambda < 0,
+ * tau <= 0, soft output with T <= 0, misaligned workspace),
+ * BP_ERR_UNSUPPORTED (label count outside [2, 256], 16-bit messages with
+ * checkpointing), BP_ERR_WORKSPACE_TOO_SMALL, BP_ERR_HIP.
+ */
+bp_status bp_run(const bp_problem *probs, int32_t count, const bp_params *params, void *workspace,
+                 size_t ws_bytes, void *checkpoints, size_t ckpt_bytes, hipStream_t stream);
+
+/* One timed half-sweep launch (bp_run_profiled). */
+typedef struct {
+    int32_t level;          /* pyramid level of the launch (0 = finest) */
+    int32_t half_sweep;     /* t within the level */
+    int32_t readout_fused;  /* 1 if this launch also wrote the senders' labels */
+    int32_t msg_bytes;      /* bytes per stored message value at this level (4 or 2) */
+    double units;           /* pixel-label updates of this launch: W_l * H_l * L */
+    float ms;               /* kernel time from HIP events recorded on `stream` around the launch */
+} bp_launch_record;
+
+/*
+ * Measurement form of bp_run for one problem (count must be 1): the same
+ * launch sequence, with a HIP event pair recorded on `stream` around every
+ * half-sweep launch (up to `capacity` of them).  Unlike bp_run it
+ * synchronises `stream` before returning.  Writes the number of records to
+ * *n_records.  Errors as bp_run, plus BP_ERR_INVALID_ARGUMENT for NULL
+ * records/n_records or negative capacity.
+ */
+bp_status bp_run_profiled(const bp_problem *probs, int32_t count, const bp_params *params, void *workspace,
+                          size_t ws_bytes, hipStream_t stream, bp_launch_record *records, int32_t capacity,
+                          int32_t *n_records);
+
+/*
+ * a7. Joint bilateral upsampling, Eq. 2:
+ *   D_p = (1/K_p) sum_{q in window} D'(q) s(|p_lo - q|) g(|I_p - I_q|)
+ * with Gaussian s (sigma_s in full-resolution pixels) and g (sigma_r in
+ * 0..255 units, Euclidean over channels); p_lo = (p + 0.5)/scale - 0.5;
+ * window = low-resolution pixels within radius_lo of floor(p/scale) (clipped
+ * to the grid); I_q is the guide at scale*q + floor(scale/2); scale =
+ * w_hi / w_lo = h_hi / h_lo (an integer).  radius_lo < 0 selects
+ * ceil(2 sigma_s / scale).  Output float32 [h_hi][w_hi] in low-resolution
+ * label units (multiply by scale for full-resolution disparity).
+ * Errors: BP_ERR_INVALID_ARGUMENT for NULL pointers, non-integer or unequal
+ * scales, channels not 1/3, sigmas <= 0; BP_ERR_UNSUPPORTED for radius_lo > 8.
+ */
+bp_status bp_upsample(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const uint8_t *guide_hi,
+                      int32_t w_hi, int32_t h_hi, int32_t channels, int64_t guide_row_stride,
+                      float sigma_s, float sigma_r, int32_t radius_lo, float *disp_hi,
+                      hipStream_t stream);
+
+/*
+ * a8. Adjoint of bp_run's single-level soft-argmin form: given the gradient
+ * of a loss with respect to every problem's soft_disparity, returns its
+ * gradient with respect to the cost volume, lambda and tau, by reverse-mode
+ * differentiation through the K half-sweeps (recomputed from the checkpoints
+ * bp_run saved) and the soft-argmin.  Ties follow the forward pass's choice.
+ *   grad_soft   device [count][H][W] float32 (problems must share W, H, L)
+ *   grad_cost   device [count][L][H][W] float32, overwritten
+ *   grad_lambda, grad_tau  device float32[1] each, overwritten
+ * Requires params->levels == 1, msg_dtype == BP_MSG_F32, checkpoint_every > 0
+ * and the same problems, params and checkpoints as the forward call.
+ */
+bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *params,
+                      const void *checkpoints, size_t ckpt_bytes, const float *grad_soft,
+                      float *grad_cost, float *grad_lambda, float *grad_tau, void *workspace,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes bp_backward needs; 0 on invalid input. */
+size_t bp_backward_workspace_size(const bp_problem *probs, int32_t count, const bp_params *params);
+
+/* Number of kernel variants bp_params.variant may select (1..count). */
+int32_t bp_variant_count(int32_t num_labels);
+
+/* Static text for a status code. */
+const char *bp_status_string(bp_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BPSTEREO_BP_H */

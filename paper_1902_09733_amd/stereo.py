@@ -1,0 +1,183 @@
+"""PyTorch-facing binding of libbpstereo.
+
+Every function marshals torch tensors (device memory) and the current HIP
+stream into the C ABI of include/bp.h; all arithmetic runs in the library's
+HIP kernels.  Nothing here computes a stereo result on the host, and there is
+no fallback: a missing library or a non-GPU tensor raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _abi
+
+MSG_DTYPES = {"f32": _abi.BP_MSG_F32, "f16": _abi.BP_MSG_F16, "bf16": _abi.BP_MSG_BF16}
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need_gpu(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libbpstereo works on GPU tensors only")
+        if t is not None and not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+
+
+def _img_dims(img):
+    if img.dim() == 2:
+        return img.shape[1], img.shape[0], 1
+    return img.shape[1], img.shape[0], img.shape[2]
+
+
+def downsample(img: torch.Tensor, factor: int, stream=None) -> torch.Tensor:
+    """s x s block mean (rounded half up) of a u8 [H][W] or [H][W][3] image."""
+    _need_gpu(img)
+    w, h, c = _img_dims(img)
+    out = torch.empty((h // factor, w // factor) + ((c,) if img.dim() == 3 else ()), dtype=torch.uint8,
+                      device=img.device)
+    st = _abi.lib().bp_downsample(_ptr(img), w, h, c, w * c, factor, _ptr(out), _stream(stream))
+    _abi.check("bp_downsample", st)
+    return out
+
+
+def cost_volume(left: torch.Tensor, right: torch.Tensor, num_labels: int, data_trunc: float = 20.0,
+                downsample: int = 1, rgb_mode: int = 0, out: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+    """Truncated absolute-difference data term, float32 [L][H/s][W/s]."""
+    _need_gpu(left, right)
+    if left.dtype != torch.uint8 or right.dtype != torch.uint8 or left.shape != right.shape:
+        raise ValueError("left/right must be u8 images of the same shape")
+    w, h, c = _img_dims(left)
+    if out is None:
+        out = torch.empty((num_labels, h // downsample, w // downsample), dtype=torch.float32, device=left.device)
+    _need_gpu(out)
+    st = _abi.lib().bp_cost_volume(_ptr(left), _ptr(right), w, h, c, w * c, downsample, num_labels,
+                                   float(data_trunc), rgb_mode, _ptr(out), _stream(stream))
+    _abi.check("bp_cost_volume", st)
+    return out
+
+
+@dataclass
+class BPParams:
+    levels: int = 1
+    iters: int = 10
+    lam: float = 10.0
+    tau: float = 2.0
+    msg_dtype: str = "f32"
+    temperature: float = 0.5
+    checkpoint_every: int = 0
+    variant: int = 0
+
+    def c(self) -> _abi.BpParams:
+        return _abi.BpParams(self.levels, self.iters, self.lam, self.tau, MSG_DTYPES[self.msg_dtype],
+                             self.temperature, self.checkpoint_every, self.variant)
+
+
+class Workspace:
+    """Reusable device scratch buffer (grows on demand; 256-byte aligned)."""
+
+    def __init__(self, device=None):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        need = nbytes + 256
+        if self.buf is None or self.buf.numel() < need or self.buf.device != device:
+            self.buf = torch.empty(need, dtype=torch.uint8, device=device)
+        off = (-self.buf.data_ptr()) % 256
+        return self.buf[off:off + nbytes] if nbytes else self.buf[:0]
+
+
+_default_ws = Workspace()
+
+
+def _problems(costs, disps, softs, msgs):
+    probs = (_abi.BpProblem * len(costs))()
+    for i, c in enumerate(costs):
+        L, h, w = c.shape
+        probs[i].width, probs[i].height, probs[i].num_labels = w, h, L
+        probs[i].cost = c.data_ptr()
+        probs[i].disparity = disps[i].data_ptr() if disps[i] is not None else None
+        probs[i].soft_disparity = softs[i].data_ptr() if softs[i] is not None else None
+        probs[i].messages_out = msgs[i].data_ptr() if msgs[i] is not None else None
+    return probs
+
+
+def workspace_bytes(costs, params: BPParams) -> int:
+    costs = list(costs)
+    probs = _problems(costs, [None] * len(costs), [None] * len(costs), [None] * len(costs))
+    p = params.c()
+    return _abi.lib().bp_workspace_size(probs, len(costs), ctypes.byref(p))
+
+
+def run(costs, params: BPParams, *, want_disp: bool = True, want_soft: bool = False, want_msgs: bool = False,
+        workspace: Workspace | None = None, checkpoints: torch.Tensor | None = None, outputs=None,
+        stream=None):
+    """Hierarchical checkerboard BP on one cost volume [L][H][W] or a list of them.
+
+    Returns a dict (or a list of dicts for a list input) with ``disp`` (int32
+    [H][W]), ``soft`` (float32 [H][W]) and ``msgs`` (float32 [4][L][H][W]).
+    ``outputs`` may pass preallocated dicts of the same form.
+    """
+    single = isinstance(costs, torch.Tensor)
+    costs = [costs] if single else list(costs)
+    for c in costs:
+        _need_gpu(c)
+        if c.dtype != torch.float32 or c.dim() != 3:
+            raise ValueError("cost volumes must be float32 [L][H][W]")
+    dev = costs[0].device
+    if outputs is None:
+        outputs = []
+        for c in costs:
+            L, h, w = c.shape
+            outputs.append({
+                "disp": torch.empty((h, w), dtype=torch.int32, device=dev) if want_disp else None,
+                "soft": torch.empty((h, w), dtype=torch.float32, device=dev) if want_soft else None,
+                "msgs": torch.empty((4, L, h, w), dtype=torch.float32, device=dev) if want_msgs else None,
+            })
+    probs = _problems(costs, [o.get("disp") for o in outputs], [o.get("soft") for o in outputs],
+                      [o.get("msgs") for o in outputs])
+    p = params.c()
+    lib = _abi.lib()
+    nbytes = lib.bp_workspace_size(probs, len(costs), ctypes.byref(p))
+    if nbytes == 0:
+        raise ValueError("bp_workspace_size rejected the problem description")
+    ws = (workspace or _default_ws).get(nbytes, dev)
+    ck_ptr, ck_bytes = (None, 0)
+    if checkpoints is not None:
+        ck_ptr, ck_bytes = _ptr(checkpoints), checkpoints.numel() * checkpoints.element_size()
+    st = lib.bp_run(probs, len(costs), ctypes.byref(p), _ptr(ws), nbytes, ck_ptr, ck_bytes, _stream(stream))
+    _abi.check("bp_run", st)
+    outs = [{k: v for k, v in o.items() if v is not None} for o in outputs]
+    return outs[0] if single else outs
+
+
+def upsample(disp_lo: torch.Tensor, guide: torch.Tensor, sigma_s: float = 8.0, sigma_r: float = 12.0,
+             radius: int = -1, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Joint bilateral upsampling (Eq. 2) -> float32 [H][W] in low-res label units."""
+    _need_gpu(disp_lo, guide)
+    if disp_lo.dtype != torch.int32 or guide.dtype != torch.uint8:
+        raise ValueError("disp_lo must be int32 and guide u8")
+    hl, wl = disp_lo.shape
+    w, h, c = _img_dims(guide)
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float32, device=guide.device)
+    st = _abi.lib().bp_upsample(_ptr(disp_lo), wl, hl, _ptr(guide), w, h, c, w * c, float(sigma_s),
+                                float(sigma_r), int(radius), _ptr(out), _stream(stream))
+    _abi.check("bp_upsample", st)
+    return out
+
+
+def variant_count(num_labels: int) -> int:
+    return _abi.lib().bp_variant_count(num_labels)

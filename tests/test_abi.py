@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+function, and rejects bad arguments before touching the GPU."""
+import ctypes
+
+import pytest
+
+from paper_1902_09733_amd import _abi
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _abi.lib()
+
+
+def test_exports_every_declared_function(lib):
+    names = _abi.header_functions()
+    assert {"bp_cost_volume", "bp_run", "bp_upsample", "bp_backward"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4):
+        assert lib.bp_status_string(code)
+    assert lib.bp_status_string(0) == b"ok"
+
+
+def _prob(w=16, h=8, L=8, cost=1):
+    p = (_abi.BpProblem * 1)()
+    p[0].width, p[0].height, p[0].num_labels = w, h, L
+    p[0].cost = cost
+    return p
+
+
+def _params(**kw):
+    d = dict(levels=1, iters_per_level=4, lambda_=10.0, tau=2.0, msg_dtype=0, temperature=0.5,
+             checkpoint_every=0, variant=0)
+    d.update(kw)
+    return _abi.BpParams(**d)
+
+
+def test_workspace_size_grows_and_rejects(lib):
+    p = _params()
+    a = lib.bp_workspace_size(_prob(16, 8, 8), 1, ctypes.byref(p))
+    b = lib.bp_workspace_size(_prob(32, 8, 8), 1, ctypes.byref(p))
+    assert 0 < a < b and a % 256 == 0
+    assert lib.bp_workspace_size(_prob(16, 8, 1), 1, ctypes.byref(p)) == 0      # L < 2
+    assert lib.bp_workspace_size(_prob(16, 8, 257), 1, ctypes.byref(p)) == 0    # L > 256
+    assert lib.bp_workspace_size(_prob(0, 8, 8), 1, ctypes.byref(p)) == 0
+    bad = _params(tau=0.0)
+    assert lib.bp_workspace_size(_prob(), 1, ctypes.byref(bad)) == 0
+    p2 = _params(levels=3, msg_dtype=1)
+    assert lib.bp_workspace_size(_prob(16, 8, 8), 1, ctypes.byref(p2)) > 0
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(lambda_=-1.0), _abi.BP_ERR_INVALID_ARGUMENT),
+    (dict(tau=0.0), _abi.BP_ERR_INVALID_ARGUMENT),
+    (dict(levels=0), _abi.BP_ERR_INVALID_ARGUMENT),
+    (dict(iters_per_level=-1), _abi.BP_ERR_INVALID_ARGUMENT),
+    (dict(msg_dtype=7), _abi.BP_ERR_INVALID_ARGUMENT),
+])
+def test_run_rejects_bad_params(lib, kw, expect):
+    p = _params(**kw)
+    st = lib.bp_run(_prob(), 1, ctypes.byref(p), ctypes.c_void_p(256), 1 << 20, None, 0, None)
+    assert st == expect
+
+
+def test_run_rejects_bad_problems(lib):
+    p = _params()
+    ws = ctypes.c_void_p(256)
+    assert lib.bp_run(_prob(cost=0), 1, ctypes.byref(p), ws, 1 << 20, None, 0, None) == _abi.BP_ERR_INVALID_ARGUMENT
+    assert lib.bp_run(_prob(L=1), 1, ctypes.byref(p), ws, 1 << 20, None, 0, None) == _abi.BP_ERR_UNSUPPORTED
+    assert lib.bp_run(_prob(L=300), 1, ctypes.byref(p), ws, 1 << 20, None, 0, None) == _abi.BP_ERR_UNSUPPORTED
+    assert lib.bp_run(_prob(), 1, ctypes.byref(p), ctypes.c_void_p(100), 1 << 20, None, 0, None) == \
+        _abi.BP_ERR_INVALID_ARGUMENT   # misaligned workspace
+    assert lib.bp_run(_prob(), 1, ctypes.byref(p), ws, 16, None, 0, None) == _abi.BP_ERR_WORKSPACE_TOO_SMALL
+    assert lib.bp_run(_prob(), 0, ctypes.byref(p), ws, 1 << 20, None, 0, None) == _abi.BP_ERR_INVALID_ARGUMENT
+    soft = _prob()
+    soft[0].soft_disparity = 256
+    p0 = _params(temperature=0.0)
+    assert lib.bp_run(soft, 1, ctypes.byref(p0), ws, 1 << 20, None, 0, None) == _abi.BP_ERR_INVALID_ARGUMENT
+
+
+def test_cost_volume_rejects(lib):
+    v = ctypes.c_void_p(256)
+    f = lib.bp_cost_volume
+    assert f(None, v, 8, 8, 1, 8, 1, 4, 20.0, 0, v, None) == _abi.BP_ERR_INVALID_ARGUMENT
+    assert f(v, v, 8, 8, 2, 16, 1, 4, 20.0, 0, v, None) == _abi.BP_ERR_INVALID_ARGUMENT   # channels
+    assert f(v, v, 8, 8, 1, 4, 1, 4, 20.0, 0, v, None) == _abi.BP_ERR_INVALID_ARGUMENT    # stride
+    assert f(v, v, 10, 8, 1, 10, 4, 4, 20.0, 0, v, None) == _abi.BP_ERR_INVALID_ARGUMENT  # s must divide
+    assert f(v, v, 8, 8, 1, 8, 1, 0, 20.0, 0, v, None) == _abi.BP_ERR_INVALID_ARGUMENT    # labels
+    assert f(v, v, 8, 8, 1, 8, 1, 4, -1.0, 0, v, None) == _abi.BP_ERR_INVALID_ARGUMENT    # trunc
+    assert f(v, v, 8, 8, 1, 8, 1, 4, 20.0, 2, v, None) == _abi.BP_ERR_INVALID_ARGUMENT    # rgb mode
+
+
+def test_upsample_rejects(lib):
+    v = ctypes.c_void_p(256)
+    f = lib.bp_upsample
+    assert f(v, 4, 4, v, 16, 12, 3, 48, 8.0, 12.0, -1, v, None) == _abi.BP_ERR_INVALID_ARGUMENT  # scales differ
+    assert f(v, 4, 4, v, 16, 16, 3, 48, 0.0, 12.0, -1, v, None) == _abi.BP_ERR_INVALID_ARGUMENT  # sigma_s
+    assert f(v, 4, 4, v, 16, 16, 3, 48, 8.0, 12.0, 9, v, None) == _abi.BP_ERR_UNSUPPORTED
+    assert f(v, 4, 4, v, 16, 16, 3, 47, 8.0, 12.0, -1, v, None) == _abi.BP_ERR_INVALID_ARGUMENT  # stride
+
+
+def test_variant_counts(lib):
+    assert lib.bp_variant_count(1) == 0
+    for L in (2, 16, 32, 48, 64, 96, 128, 256):
+        assert lib.bp_variant_count(L) >= 1
