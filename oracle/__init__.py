@@ -53,8 +53,7 @@ def lib():
         L.bpo_round_bf16.argtypes = [d]
         L.bpo_round_bf16.restype = d
         L.bpo_max_threads.restype = i
-        if hasattr(L, "bpo_backward"):
-            L.bpo_backward.argtypes = [_dp, i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, i]
+        L.bpo_backward.argtypes = [_dp, i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, i]
         _lib = L
     return _lib
 
@@ -161,3 +160,23 @@ def round_bf16(x: float) -> float:
 
 def max_threads() -> int:
     return lib().bpo_max_threads()
+
+
+def backward(cost, iters: int, lam: float, tau: float, temperature: float, grad_soft, nthreads: int = 0):
+    """Single-level BP with soft-argmin readout and its reverse-mode derivative.
+
+    Returns (soft [H][W], grad_cost [L][H][W], grad_lambda, grad_tau) for the
+    loss sum(grad_soft * soft).
+    """
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    L, H, W = cost.shape
+    g = np.ascontiguousarray(grad_soft, dtype=np.float64)
+    soft = np.empty((H, W), dtype=np.float64)
+    gc = np.empty_like(cost)
+    gl = ctypes.c_double(0.0)
+    gt = ctypes.c_double(0.0)
+    rc = lib().bpo_backward(_p(cost, _dp), W, H, L, int(iters), float(lam), float(tau), float(temperature),
+                            _p(g, _dp), _p(soft, _dp), _p(gc, _dp), ctypes.byref(gl), ctypes.byref(gt),
+                            int(nthreads))
+    _check(rc, "backward")
+    return soft, gc, gl.value, gt.value
