@@ -75,8 +75,12 @@ typedef struct {
     float temperature;         /* soft-argmin temperature T > 0 (used when soft_disparity != NULL) */
     int32_t checkpoint_every;  /* 0 = none; k > 0 saves the message state every k half-sweeps
                                   of the finest level into the checkpoint buffer (adjoint) */
-    int32_t variant;           /* 0 = library choice (tuned table); otherwise a kernel variant
-                                  id from bp_variant_count() for testing and tuning */
+    int32_t variant;           /* 0 = library choice; otherwise a label-major half-sweep kernel
+                                  variant in 1..bp_variant_count() (testing and tuning) */
+    int32_t pm_from;           /* first pyramid level stored pixel-major (labels of a pixel
+                                  contiguous, half-sweep by lane-split scans); levels before it
+                                  are label-major.  -1 = library choice, `levels` = none.
+                                  Results do not depend on it. */
 } bp_params;
 
 /*
@@ -184,13 +188,20 @@ bp_status bp_upsample(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const 
  * a8. Adjoint of bp_run's single-level soft-argmin form: given the gradient
  * of a loss with respect to every problem's soft_disparity, returns its
  * gradient with respect to the cost volume, lambda and tau, by reverse-mode
- * differentiation through the K half-sweeps (recomputed from the checkpoints
- * bp_run saved) and the soft-argmin.  Ties follow the forward pass's choice.
- *   grad_soft   device [count][H][W] float32 (problems must share W, H, L)
- *   grad_cost   device [count][L][H][W] float32, overwritten
+ * differentiation through the K half-sweeps (each state rebuilt from the
+ * checkpoints bp_run saved) and the soft-argmin.  The transform is piecewise
+ * linear; the derivative follows the branch the forward pass took (forward
+ * pass keeps h(f) on ties, backward pass keeps the current value, truncation
+ * only when strictly smaller), and lambda/tau are shared scalars whose
+ * gradients sum over the problems (reduced in a fixed order).
+ *   grad_soft   device float32, the problems' [H][W] arrays concatenated
+ *   grad_cost   device float32, the problems' [L][H][W] arrays concatenated, overwritten
  *   grad_lambda, grad_tau  device float32[1] each, overwritten
- * Requires params->levels == 1, msg_dtype == BP_MSG_F32, checkpoint_every > 0
- * and the same problems, params and checkpoints as the forward call.
+ *   workspace   bp_backward_workspace_size() bytes, 256-byte aligned
+ * Requires params->levels == 1, msg_dtype == BP_MSG_F32, checkpoint_every > 0,
+ * temperature > 0 and the same problems, params and checkpoints as the
+ * forward call.  Errors: BP_ERR_INVALID_ARGUMENT, BP_ERR_UNSUPPORTED (more
+ * levels or 16-bit messages), BP_ERR_WORKSPACE_TOO_SMALL, BP_ERR_HIP.
  */
 bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *params,
                       const void *checkpoints, size_t ckpt_bytes, const float *grad_soft,

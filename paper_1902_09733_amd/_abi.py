@@ -40,6 +40,7 @@ class BpParams(ctypes.Structure):
         ("temperature", ctypes.c_float),
         ("checkpoint_every", ctypes.c_int32),
         ("variant", ctypes.c_int32),
+        ("pm_from", ctypes.c_int32),
     ]
 
 

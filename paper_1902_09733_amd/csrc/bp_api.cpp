@@ -28,6 +28,7 @@ bool valid_params(const bp_params *p)
     if (!(p->tau > 0.0f) || !std::isfinite(p->tau)) return false;
     if (p->msg_dtype < BP_MSG_F32 || p->msg_dtype > BP_MSG_BF16) return false;
     if (p->checkpoint_every < 0) return false;
+    if (p->pm_from < -1 || p->pm_from > p->levels) return false;
     return true;
 }
 
@@ -47,12 +48,28 @@ bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
     size_t off = 0;
     for (int i = 0; i < count; ++i) {
         const bp_problem &q = probs[i];
-        if (!make_plan(q.width, q.height, q.num_labels, p->levels, p->msg_dtype, off, &plans[i])) return false;
+        // The adjoint kernels work on label-major states.
+        const int pm_from = p->checkpoint_every > 0 ? p->levels
+                            : p->pm_from >= 0      ? p->pm_from
+                                                   : default_pm_from(q.width, q.height, q.num_labels, p->levels,
+                                                                     p->msg_dtype);
+        if (!make_plan(q.width, q.height, q.num_labels, p->levels, p->msg_dtype, pm_from, off, &plans[i])) return false;
         off += plans[i].bytes;
     }
     *total = align_up(off);
     return true;
 }
+
+// Message states a forward call saves for the adjoint: after every
+// `every`-th half-sweep t < K, and the final state.
+int checkpoint_states(int K, int every) { return (K > 0 ? (K - 1) / every : 0) + 1; }
+
+size_t checkpoint_bytes_of(const Plan &pl, int K, int every)
+{
+    return (size_t)checkpoint_states(K, every) * pl.lv[0].msg_bytes;
+}
+
+bool differentiable(const bp_params &p) { return p.levels == 1 && p.msg_dtype == BP_MSG_F32; }
 
 // Optional per-launch timing of the half-sweep kernels (bp_run_profiled).
 struct Recorder {
@@ -63,12 +80,12 @@ struct Recorder {
 
 // Runs the whole hierarchical BP of one problem.
 bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8_t *ws, hipStream_t s,
-                  Recorder *prof = nullptr)
+                  Recorder *prof = nullptr, uint8_t *ckpt = nullptr)
 {
     bp_status st;
     const int n = pl.levels, K = p.iters_per_level;
-    for (int l = 0; l < n; ++l)
-        if ((st = launch_zero_border(pl, l, ws, s)) != BP_OK) return st;
+    // Out-of-grid slots of every level and the coarsest level's messages start at zero.
+    if ((st = launch_init_messages(pl, ws, s)) != BP_OK) return st;
     if ((st = launch_split_cost(q.cost, pl, ws, s)) != BP_OK) return st;
     for (int l = 1; l < n; ++l)
         if ((st = launch_pyramid_level(pl, l, ws, s)) != BP_OK) return st;
@@ -76,12 +93,13 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
     const bool fuse_ro = q.disparity && !q.soft_disparity && K >= 1;
     for (int l = n - 1; l >= 0; --l) {
         int first_src = 0;
-        if (l == n - 1) {
-            // The coarsest level starts from zero messages.
-            if ((st = launch_zero_level(pl, l, ws, s)) != BP_OK) return st;
-        } else {
-            const bool same_fmt = pl.lv[l].fmt == pl.lv[l + 1].fmt;
-            if (K >= 2 && same_fmt) first_src = 1;        // t = 0 reads the parent's slots
+        if (l < n - 1) {
+            // Half-sweep 0 reads the parent's slots directly when every slot of
+            // this level is rewritten before it is read again (K >= 2) and the
+            // storage formats agree; otherwise the copy is materialised.
+            const Level &c = pl.lv[l], &pa = pl.lv[l + 1];
+            const bool fusable = K >= 2 && c.fmt == pa.fmt && !(c.layout == PIXEL_MAJOR && pa.layout == LABEL_MAJOR);
+            if (fusable) first_src = 1;
             else if ((st = launch_parent_copy(pl, l, ws, s)) != BP_OK) return st;
         }
         for (int t = 0; t < K; ++t) {
@@ -100,7 +118,19 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
                 r.units = (double)pl.lv[l].w * pl.lv[l].h * pl.L;
                 r.ms = 0.0f;
             }
+            if (ckpt && (t + 1) % p.checkpoint_every == 0 && t + 1 < K) {
+                const size_t sb = pl.lv[0].msg_bytes;
+                if ((st = launch_copy(ws + pl.lv[0].msg_off, ckpt + (size_t)((t + 1) / p.checkpoint_every - 1) * sb, sb,
+                                      s)) != BP_OK)
+                    return st;
+            }
         }
+    }
+    if (ckpt) {
+        const size_t sb = pl.lv[0].msg_bytes;
+        if ((st = launch_copy(ws + pl.lv[0].msg_off, ckpt + (size_t)(checkpoint_states(K, p.checkpoint_every) - 1) * sb,
+                              sb, s)) != BP_OK)
+            return st;
     }
     if (q.disparity || q.soft_disparity) {
         // After the fused readout only the last receivers' labels remain.
@@ -167,7 +197,15 @@ size_t bp_workspace_size(const bp_problem *probs, int32_t count, const bp_params
 size_t bp_checkpoint_size(const bp_problem *probs, int32_t count, const bp_params *params)
 {
     if (!probs || count < 1 || !valid_params(params) || params->checkpoint_every <= 0) return 0;
-    return 0;
+    if (!differentiable(*params)) return 0;
+    for (int i = 0; i < count; ++i)
+        if (probs[i].width <= 0 || probs[i].height <= 0 || !supported_labels(probs[i].num_labels)) return 0;
+    Plan *plans = new Plan[count];
+    size_t total = 0, bytes = 0;
+    if (plan_all(probs, count, params, plans, &total))
+        for (int i = 0; i < count; ++i) bytes += checkpoint_bytes_of(plans[i], params->iters_per_level, params->checkpoint_every);
+    delete[] plans;
+    return bytes;
 }
 
 bp_status bp_run(const bp_problem *probs, int32_t count, const bp_params *params, void *workspace, size_t ws_bytes,
@@ -179,22 +217,31 @@ bp_status bp_run(const bp_problem *probs, int32_t count, const bp_params *params
         if (!valid_problem(probs[i], *params)) return BP_ERR_INVALID_ARGUMENT;
         if (!supported_labels(probs[i].num_labels)) return BP_ERR_UNSUPPORTED;
     }
-    if (params->checkpoint_every > 0) return BP_ERR_UNSUPPORTED;
-    (void)checkpoints;
-    (void)ckpt_bytes;
+    const bool ck = params->checkpoint_every > 0;
+    if (ck && !differentiable(*params)) return BP_ERR_UNSUPPORTED;
+    if (ck && (!checkpoints || ((uintptr_t)checkpoints % kAlign) != 0)) return BP_ERR_INVALID_ARGUMENT;
     Plan *plans = new Plan[count];
     size_t total = 0;
     if (!plan_all(probs, count, params, plans, &total)) {
         delete[] plans;
         return BP_ERR_UNSUPPORTED;
     }
-    if (ws_bytes < total) {
+    size_t ck_total = 0;
+    if (ck)
+        for (int i = 0; i < count; ++i)
+            ck_total += checkpoint_bytes_of(plans[i], params->iters_per_level, params->checkpoint_every);
+    if (ws_bytes < total || ckpt_bytes < ck_total) {
         delete[] plans;
         return BP_ERR_WORKSPACE_TOO_SMALL;
     }
     (void)hipGetLastError();
     bp_status st = BP_OK;
-    for (int i = 0; i < count && st == BP_OK; ++i) st = run_one(probs[i], plans[i], *params, (uint8_t *)workspace, stream);
+    size_t ck_off = 0;
+    for (int i = 0; i < count && st == BP_OK; ++i) {
+        uint8_t *cp = ck ? (uint8_t *)checkpoints + ck_off : nullptr;
+        st = run_one(probs[i], plans[i], *params, (uint8_t *)workspace, stream, nullptr, cp);
+        if (ck) ck_off += checkpoint_bytes_of(plans[i], params->iters_per_level, params->checkpoint_every);
+    }
     delete[] plans;
     return st;
 }
@@ -251,19 +298,116 @@ bp_status bp_upsample(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const 
                            R, disp_hi, stream);
 }
 
-bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *params, const void *checkpoints,
-                      size_t ckpt_bytes, const float *grad_soft, float *grad_cost, float *grad_lambda,
-                      float *grad_tau, void *workspace, size_t ws_bytes, hipStream_t stream)
+// Backward workspace: per problem its forward plan (cost + a message state
+// rebuilt from checkpoints) and the message adjoint, then the (lambda, tau)
+// partials of every reverse step of every problem.
+static bool backward_layout(const bp_problem *probs, int32_t count, const bp_params *params, Plan *plans,
+                            size_t *mbar_off, size_t *partial_off, int *n_partial, size_t *total)
 {
-    (void)probs; (void)count; (void)params; (void)checkpoints; (void)ckpt_bytes; (void)grad_soft;
-    (void)grad_cost; (void)grad_lambda; (void)grad_tau; (void)workspace; (void)ws_bytes; (void)stream;
-    return BP_ERR_UNSUPPORTED;
+    size_t off = 0;
+    int np = 0;
+    for (int i = 0; i < count; ++i) {
+        const bp_problem &q = probs[i];
+        if (!make_plan(q.width, q.height, q.num_labels, 1, BP_MSG_F32, 1, off, &plans[i])) return false;
+        off += plans[i].bytes;
+        mbar_off[i] = off;
+        off += plans[i].lv[0].msg_bytes;
+        np += params->iters_per_level * bwd_step_blocks(plans[i]);
+    }
+    *partial_off = off;
+    *n_partial = np;
+    off += align_up((size_t)(np > 0 ? np : 1) * 2 * sizeof(float));
+    *total = off;
+    return true;
+}
+
+static bool valid_backward(const bp_problem *probs, int32_t count, const bp_params *params)
+{
+    if (!probs || count < 1 || !valid_params(params)) return false;
+    if (params->checkpoint_every <= 0 || !differentiable(*params) || !(params->temperature > 0.0f)) return false;
+    for (int i = 0; i < count; ++i)
+        if (probs[i].width <= 0 || probs[i].height <= 0 || !probs[i].cost || !supported_labels(probs[i].num_labels))
+            return false;
+    return true;
 }
 
 size_t bp_backward_workspace_size(const bp_problem *probs, int32_t count, const bp_params *params)
 {
-    (void)probs; (void)count; (void)params;
-    return 0;
+    if (!valid_backward(probs, count, params)) return 0;
+    Plan *plans = new Plan[count];
+    size_t *mo = new size_t[count];
+    size_t po = 0, total = 0;
+    int np = 0;
+    bool ok = backward_layout(probs, count, params, plans, mo, &po, &np, &total);
+    delete[] plans;
+    delete[] mo;
+    return ok ? total : 0;
+}
+
+bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *params, const void *checkpoints,
+                      size_t ckpt_bytes, const float *grad_soft, float *grad_cost, float *grad_lambda,
+                      float *grad_tau, void *workspace, size_t ws_bytes, hipStream_t stream)
+{
+    if (!probs || count < 1 || !valid_params(params)) return BP_ERR_INVALID_ARGUMENT;
+    if (params->checkpoint_every <= 0 || !(params->temperature > 0.0f)) return BP_ERR_INVALID_ARGUMENT;
+    if (!differentiable(*params)) return BP_ERR_UNSUPPORTED;
+    if (!checkpoints || !grad_soft || !grad_cost || !grad_lambda || !grad_tau || !workspace) return BP_ERR_INVALID_ARGUMENT;
+    if (((uintptr_t)workspace % kAlign) != 0 || ((uintptr_t)checkpoints % kAlign) != 0) return BP_ERR_INVALID_ARGUMENT;
+    if (!valid_backward(probs, count, params)) return BP_ERR_INVALID_ARGUMENT;
+    Plan *plans = new Plan[count];
+    size_t *mo = new size_t[count];
+    size_t po = 0, total = 0;
+    int np = 0;
+    bp_status st = BP_OK;
+    const int K = params->iters_per_level, every = params->checkpoint_every;
+    if (!backward_layout(probs, count, params, plans, mo, &po, &np, &total)) st = BP_ERR_UNSUPPORTED;
+    size_t ck_total = 0;
+    for (int i = 0; st == BP_OK && i < count; ++i) ck_total += checkpoint_bytes_of(plans[i], K, every);
+    if (st == BP_OK && (ws_bytes < total || ckpt_bytes < ck_total)) st = BP_ERR_WORKSPACE_TOO_SMALL;
+    if (st != BP_OK) {
+        delete[] plans;
+        delete[] mo;
+        return st;
+    }
+    (void)hipGetLastError();
+    uint8_t *ws = (uint8_t *)workspace;
+    float *partial = (float *)(ws + po);
+    const uint8_t *ck = (const uint8_t *)checkpoints;
+    size_t soft_off = 0, cost_off = 0;
+    int part = 0;
+    for (int i = 0; i < count && st == BP_OK; ++i) {
+        const Plan &pl = plans[i];
+        const Level &v = pl.lv[0];
+        const size_t sb = v.msg_bytes;
+        uint8_t *state = ws + v.msg_off;
+        float *mbar = (float *)(ws + mo[i]);
+        float *gc = grad_cost + cost_off;
+        const int nst = checkpoint_states(K, every);
+        if ((st = launch_split_cost(probs[i].cost, pl, ws, stream)) != BP_OK) break;
+        // Readout adjoint from the final state.
+        if ((st = launch_bwd_readout(pl, ck + (size_t)(nst - 1) * sb, mbar, grad_soft + soft_off, gc,
+                                     params->temperature, ws, stream)) != BP_OK)
+            break;
+        for (int t = K - 1; t >= 0 && st == BP_OK; --t) {
+            // Rebuild M_t: restore the last saved state at or before t, replay.
+            const int t0 = (t / every) * every;
+            if (t0 == 0) st = launch_init_messages(pl, ws, stream);
+            else st = launch_copy(ck + (size_t)(t0 / every - 1) * sb, state, sb, stream);
+            for (int r = t0; r < t && st == BP_OK; ++r)
+                st = launch_iteration(pl, 0, r, 0, params->lambda, params->tau, nullptr, params->variant, ws, stream);
+            if (st == BP_OK)
+                st = launch_bwd_step(pl, t, state, mbar, gc, partial + 2 * part, params->lambda, params->tau, ws,
+                                     stream);
+            part += bwd_step_blocks(pl);
+        }
+        ck += (size_t)nst * sb;
+        soft_off += (size_t)probs[i].height * probs[i].width;
+        cost_off += (size_t)probs[i].num_labels * probs[i].height * probs[i].width;
+    }
+    if (st == BP_OK) st = launch_bwd_finish(partial, np, grad_lambda, grad_tau, stream);
+    delete[] plans;
+    delete[] mo;
+    return st;
 }
 
 int32_t bp_variant_count(int32_t num_labels)

@@ -1,14 +1,7 @@
-// Hierarchical checkerboard min-sum BP on gfx950 (Sec. 2.2, Eq. 1): cost
-// pyramid, message initialisation, the half-sweep kernel, readout and the
-// message export used by tests.
-//
-// Data layout (see Level in bp_internal.h): colour-split planes, so that the
-// pixels updated by one half-sweep, and each of their four neighbours'
-// receiving slots, are contiguous along a row.  Lane mapping of the half-sweep:
-// lanes over pixels (coalesced 256-byte accesses per label plane), G lanes per
-// pixel each owning 4/G of the outgoing messages; the label recurrence of the
-// distance transform runs sequentially in registers, so no cross-lane scan is
-// needed and every update costs a handful of VALU operations.
+// Hierarchical checkerboard min-sum BP on gfx950 (Sec. 2.2, Eq. 1): level
+// plans, cost pyramid, message initialisation, readout and message export.
+// The half-sweep kernels live in bp_iter_lm.hip (label-major levels) and
+// bp_iter_pm.hip (pixel-major levels).
 #include <hip/hip_runtime.h>
 
 #include "bp_device.h"
@@ -20,7 +13,7 @@ namespace bpk {
 // Plans
 // ------------------------------------------------------------------------
 
-bool make_plan(int w, int h, int L, int levels, int msg_fmt, size_t base, Plan *p)
+bool make_plan(int w, int h, int L, int levels, int msg_fmt, int pm_from, size_t base, Plan *p)
 {
     p->w = w;
     p->h = h;
@@ -28,6 +21,8 @@ bool make_plan(int w, int h, int L, int levels, int msg_fmt, size_t base, Plan *
     p->levels = levels;
     size_t off = base;
     int lw = w, lh = h;
+    int S, R;
+    pm_split(L, &S, &R);
     for (int l = 0; l < levels; ++l) {
         Level &v = p->lv[l];
         v.w = lw;
@@ -35,8 +30,20 @@ bool make_plan(int w, int h, int L, int levels, int msg_fmt, size_t base, Plan *
         v.wh = (lw + 1) / 2;
         v.plane = (int64_t)align_up((size_t)lh * v.wh, 64);
         v.fmt = (l == levels - 1) ? FMT_F32 : msg_fmt;
-        v.cost_bytes = align_up((size_t)2 * L * v.plane * sizeof(float));
-        v.msg_bytes = align_up((size_t)8 * L * v.plane * fmt_bytes(v.fmt));
+        v.layout = l >= pm_from ? PIXEL_MAJOR : LABEL_MAJOR;
+        if (v.layout == PIXEL_MAJOR) {
+            v.lp = S * R;
+            v.blk = v.plane * v.lp;
+            v.ls = 1;
+            v.ps = v.lp;
+        } else {
+            v.lp = L;
+            v.blk = (int64_t)L * v.plane;
+            v.ls = v.plane;
+            v.ps = 1;
+        }
+        v.cost_bytes = align_up((size_t)2 * v.blk * sizeof(float));
+        v.msg_bytes = align_up((size_t)8 * v.blk * fmt_bytes(v.fmt));
         // Buffer offsets inside one level are 32-bit.
         if ((uint64_t)v.cost_bytes >= (1ull << 32) || (uint64_t)v.msg_bytes >= (1ull << 32)) return false;
         v.cost_off = off;
@@ -50,140 +57,237 @@ bool make_plan(int w, int h, int L, int levels, int msg_fmt, size_t base, Plan *
     return true;
 }
 
+// The pixel-major lane-split kernel is the faster half-sweep at every level
+// size measured on MI355X (676x380x64: 55 vs 70 us per finest-level sweep;
+// 1352x760x128: 444 vs 680 us; small levels are latency-bound under the
+// lanes-over-pixels kernel's per-lane label chain), so every level defaults to it.
+int default_pm_from(int w, int h, int L, int levels, int msg_fmt)
+{
+    (void)w;
+    (void)h;
+    (void)L;
+    (void)levels;
+    (void)msg_fmt;
+    return 0;
+}
+
 bp_status launch_status()
 {
     return hipGetLastError() == hipSuccess ? BP_OK : BP_ERR_HIP;
 }
 
-static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+static inline unsigned cdiv(int64_t n, int64_t d) { return (unsigned)((n + d - 1) / d); }
 
-// ------------------------------------------------------------------------
-// a3: colour split of the finest cost and the sum pyramid
-// ------------------------------------------------------------------------
-
-// planar [L][h][w] -> colour-split [2][L][plane]
-__global__ void __launch_bounds__(256) k_split_cost(const float *__restrict__ planar, float *__restrict__ cs,
-                                                   int w, int h, int wh, int64_t plane, int64_t n)
+__device__ __forceinline__ int64_t cost_idx(int c, int f, int j, int64_t blk, int64_t ls, int64_t ps)
 {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    int x = (int)(i % w);
-    int64_t r = i / w;
-    int y = (int)(r % h);
-    int f = (int)(r / h);
-    int c = (x + y) & 1;
-    int64_t L = n / ((int64_t)w * h);
-    cs[((int64_t)c * L + f) * plane + (int64_t)y * wh + (x >> 1)] = planar[i];
+    return (int64_t)c * blk + (int64_t)f * ls + (int64_t)j * ps;
 }
 
-// level l from level l-1, both colour-split: each coarse pixel sums its
-// existing children in the order (0,0), (1,0), (0,1), (1,1).
-__global__ void __launch_bounds__(256) k_pyramid(const float *__restrict__ fine, float *__restrict__ coarse,
-                                                int wf, int hf, int whf, int64_t pf, int wc, int hc, int whc,
-                                                int64_t pc, int L)
+__device__ __forceinline__ int64_t msg_idx(int c, int k, int f, int j, int64_t blk, int64_t ls, int64_t ps)
 {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int64_t n = (int64_t)L * hc * wc;
-    if (i >= n) return;
-    int x = (int)(i % wc);
-    int64_t r = i / wc;
-    int y = (int)(r % hc);
-    int f = (int)(r / hc);
-    float s = 0.0f;
+    return ((int64_t)c * 4 + k) * blk + (int64_t)f * ls + (int64_t)j * ps;
+}
+
+// Level geometry passed by value to kernels.
+struct LevelDesc {
+    int w, h, wh;
+    int64_t blk, ls, ps;
+};
+
+static LevelDesc desc(const Level &v) { return LevelDesc{v.w, v.h, v.wh, v.blk, v.ls, v.ps}; }
+
+// ------------------------------------------------------------------------
+// a3: finest-level cost in the level's layout, and the sum pyramid
+// ------------------------------------------------------------------------
+
+// planar [L][h][w] -> label-major colour-split.  grid (w/256, h, L).
+__global__ void __launch_bounds__(256) k_split_lm(const float *__restrict__ planar, float *__restrict__ out,
+                                                 LevelDesc d)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, f = blockIdx.z;
+    if (x >= d.w) return;
+    const float v = planar[((int64_t)f * d.h + y) * d.w + x];
+    out[cost_idx((x + y) & 1, f, y * d.wh + (x >> 1), d.blk, d.ls, d.ps)] = v;
+}
+
+// Cost of one pixel and label at a label-major or planar source level, summed
+// over the (up to four) children when SUM (pyramid step), in the order
+// (0,0), (1,0), (0,1), (1,1).
+template <bool FROM_PLANAR, bool SUM>
+__device__ __forceinline__ float gather_cost(const float *__restrict__ src, const LevelDesc &s, int f, int x, int y)
+{
+    auto at = [&](int fx, int fy) -> float {
+        if constexpr (FROM_PLANAR) return src[((int64_t)f * s.h + fy) * s.w + fx];
+        else return src[cost_idx((fx + fy) & 1, f, fy * s.wh + (fx >> 1), s.blk, s.ls, s.ps)];
+    };
+    if constexpr (!SUM) {
+        return at(x, y);
+    } else {
+        float acc = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+        for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            int fx = 2 * x + k, fy = 2 * y + j;
-            if (fx < wf && fy < hf) {
-                int c = (fx + fy) & 1;
-                s += fine[((int64_t)c * L + f) * pf + (int64_t)fy * whf + (fx >> 1)];
+            for (int ii = 0; ii < 2; ++ii) {
+                const int fx = 2 * x + ii, fy = 2 * y + jj;
+                if (fx < s.w && fy < s.h) acc += at(fx, fy);
             }
+        return acc;
+    }
+}
+
+// Transposing tile: 64 pixels of one row x 32 labels, read along the row from a
+// planar or label-major source and written along the labels into a
+// pixel-major level.  grid (w_out/64, h_out, L/32).
+template <bool FROM_PLANAR, bool SUM>
+__global__ void __launch_bounds__(256) k_to_pm(const float *__restrict__ src, LevelDesc s, float *__restrict__ out,
+                                              LevelDesc d, int L)
+{
+    __shared__ float tile[32][65];
+    const int x0 = blockIdx.x * 64, y = blockIdx.y, f0 = blockIdx.z * 32;
+    for (int i = threadIdx.x; i < 64 * 32; i += 256) {
+        const int fl = i / 64, xl = i % 64;
+        const int x = x0 + xl, f = f0 + fl;
+        float v = 0.0f;
+        if (x < d.w && f < L) v = gather_cost<FROM_PLANAR, SUM>(src, s, f, x, y);
+        tile[fl][xl] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * 32; i += 256) {
+        const int xl = i / 32, fl = i % 32;
+        const int x = x0 + xl, f = f0 + fl;
+        if (x < d.w && f < L) out[cost_idx((x + y) & 1, f, y * d.wh + (x >> 1), d.blk, d.ls, d.ps)] = tile[fl][xl];
+    }
+}
+
+// label-major -> label-major pyramid step.  grid (wc/256, hc, L).
+__global__ void __launch_bounds__(256) k_pyr_lm(const float *__restrict__ fine, LevelDesc s, float *__restrict__ out,
+                                               LevelDesc d)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, f = blockIdx.z;
+    if (x >= d.w) return;
+    out[cost_idx((x + y) & 1, f, y * d.wh + (x >> 1), d.blk, d.ls, d.ps)] = gather_cost<false, true>(fine, s, f, x, y);
+}
+
+// pixel-major -> pixel-major pyramid step: threads along (pixel, label) with
+// the label fastest.  grid (wc * L / 256, hc).
+__global__ void __launch_bounds__(256) k_pyr_pm(const float *__restrict__ fine, LevelDesc s, float *__restrict__ out,
+                                               LevelDesc d, int L)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (i >= d.w * L) return;
+    const int x = i / L, f = i - x * L;
+    float acc = 0.0f;
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii) {
+            const int fx = 2 * x + ii, fy = 2 * y + jj;
+            if (fx < s.w && fy < s.h) acc += fine[cost_idx((fx + fy) & 1, f, fy * s.wh + (fx >> 1), s.blk, s.ls, s.ps)];
         }
-    int cc = (x + y) & 1;
-    coarse[((int64_t)cc * L + f) * pc + (int64_t)y * whc + (x >> 1)] = s;
+    out[cost_idx((x + y) & 1, f, y * d.wh + (x >> 1), d.blk, d.ls, d.ps)] = acc;
 }
 
 bp_status launch_split_cost(const float *planar, const Plan &p, uint8_t *ws, hipStream_t s)
 {
     const Level &v = p.lv[0];
-    int64_t n = (int64_t)p.L * v.h * v.w;
-    k_split_cost<<<blocks_for(n, 256), 256, 0, s>>>(planar, (float *)(ws + v.cost_off), v.w, v.h, v.wh,
-                                                   v.plane, n);
+    float *out = (float *)(ws + v.cost_off);
+    LevelDesc d = desc(v);
+    if (v.layout == PIXEL_MAJOR) {
+        LevelDesc src{v.w, v.h, 0, 0, 0, 0};
+        k_to_pm<true, false><<<dim3(cdiv(v.w, 64), v.h, cdiv(p.L, 32)), 256, 0, s>>>(planar, src, out, d, p.L);
+    } else {
+        k_split_lm<<<dim3(cdiv(v.w, 256), v.h, p.L), 256, 0, s>>>(planar, out, d);
+    }
     return launch_status();
 }
 
 bp_status launch_pyramid_level(const Plan &p, int l, uint8_t *ws, hipStream_t s)
 {
     const Level &f = p.lv[l - 1], &c = p.lv[l];
-    int64_t n = (int64_t)p.L * c.h * c.w;
-    k_pyramid<<<blocks_for(n, 256), 256, 0, s>>>((const float *)(ws + f.cost_off), (float *)(ws + c.cost_off),
-                                                f.w, f.h, f.wh, f.plane, c.w, c.h, c.wh, c.plane, p.L);
+    const float *fine = (const float *)(ws + f.cost_off);
+    float *out = (float *)(ws + c.cost_off);
+    if (c.layout == LABEL_MAJOR) {
+        k_pyr_lm<<<dim3(cdiv(c.w, 256), c.h, p.L), 256, 0, s>>>(fine, desc(f), out, desc(c));
+    } else if (f.layout == LABEL_MAJOR) {
+        k_to_pm<false, true><<<dim3(cdiv(c.w, 64), c.h, cdiv(p.L, 32)), 256, 0, s>>>(fine, desc(f), out, desc(c), p.L);
+    } else {
+        k_pyr_pm<<<dim3(cdiv((int64_t)c.w * p.L, 256), c.h), 256, 0, s>>>(fine, desc(f), out, desc(c), p.L);
+    }
     return launch_status();
 }
 
 // ------------------------------------------------------------------------
-// a4: zero out-of-grid slots, explicit parent copy
+// a4: message initialisation and explicit parent copy
 // ------------------------------------------------------------------------
 
-// Border items: for every label, the pixels of the left column (slot 0), right
-// column (slot 1), top row (slot 2) and bottom row (slot 3).
-template <typename S>
-__global__ void __launch_bounds__(256) k_zero_border(uint8_t *__restrict__ msg, uint32_t msg_bytes, int w, int h,
-                                                    int wh, int64_t plane, int L)
+struct InitArgs {
+    uint8_t *msg[kMaxLevels];
+    LevelDesc d[kMaxLevels];
+    int bytes[kMaxLevels];     // bytes per stored value
+    int L, levels;
+    int64_t coarsest_words;    // 32-bit words of the coarsest level's messages
+};
+
+// blockIdx.y < levels: zero the out-of-grid slots of level blockIdx.y (for
+// every label: slot 0 of the left column, 1 of the right column, 2 of the top
+// row, 3 of the bottom row).  blockIdx.y == levels: zero every message of the
+// coarsest level, where BP starts from zero messages.
+__global__ void __launch_bounds__(256) k_init_msgs(InitArgs a)
 {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int64_t per = 2 * (int64_t)h + 2 * (int64_t)w;
-    if (i >= per * L) return;
-    int f = (int)(i / per);
-    int e = (int)(i % per);
+    const int l = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (l == a.levels) {
+        if (i < a.coarsest_words) ((uint32_t *)a.msg[a.levels - 1])[i] = 0u;
+        return;
+    }
+    const LevelDesc &d = a.d[l];
+    const int per = 2 * d.h + 2 * d.w;
+    if (i >= (int64_t)per * a.L) return;
+    const int ii = (int)i;
+    const int f = ii / per, e = ii - f * per;
     int x, y, k;
-    if (e < h) { x = 0; y = e; k = 0; }
-    else if (e < 2 * h) { x = w - 1; y = e - h; k = 1; }
-    else if (e < 2 * h + w) { x = e - 2 * h; y = 0; k = 2; }
-    else { x = e - 2 * h - w; y = h - 1; k = 3; }
-    int c = (x + y) & 1;
-    int64_t idx = (((int64_t)c * 4 + k) * L + f) * plane + (int64_t)y * wh + (x >> 1);
-    __amdgpu_buffer_rsrc_t r = make_rsrc(msg, msg_bytes);
-    S::st(r, 0.0f, (uint32_t)(idx * S::bytes), 0);
+    if (e < d.h) { x = 0; y = e; k = 0; }
+    else if (e < 2 * d.h) { x = d.w - 1; y = e - d.h; k = 1; }
+    else if (e < 2 * d.h + d.w) { x = e - 2 * d.h; y = 0; k = 2; }
+    else { x = e - 2 * d.h - d.w; y = d.h - 1; k = 3; }
+    const int64_t idx = msg_idx((x + y) & 1, k, f, y * d.wh + (x >> 1), d.blk, d.ls, d.ps);
+    if (a.bytes[l] == 4) ((uint32_t *)a.msg[l])[idx] = 0u;
+    else ((uint16_t *)a.msg[l])[idx] = 0u;
+}
+
+bp_status launch_init_messages(const Plan &p, uint8_t *ws, hipStream_t s)
+{
+    InitArgs a;
+    int64_t most = 0;
+    for (int l = 0; l < p.levels; ++l) {
+        a.msg[l] = ws + p.lv[l].msg_off;
+        a.d[l] = desc(p.lv[l]);
+        a.bytes[l] = fmt_bytes(p.lv[l].fmt);
+        const int64_t n = (2 * (int64_t)p.lv[l].h + 2 * (int64_t)p.lv[l].w) * p.L;
+        if (n > most) most = n;
+    }
+    a.L = p.L;
+    a.levels = p.levels;
+    a.coarsest_words = (int64_t)(p.lv[p.levels - 1].msg_bytes / 4);
+    if (a.coarsest_words > most) most = a.coarsest_words;
+    k_init_msgs<<<dim3(cdiv(most, 256), p.levels + 1), 256, 0, s>>>(a);
+    return launch_status();
 }
 
 // Child slot k of pixel (x, y) takes the parent's slot k at (x/2, y/2),
-// converted to the child's storage format.
+// converted to the child's storage format.  grid (wc/256, hc, 4L).
 template <typename SP, typename SC>
-__global__ void __launch_bounds__(256) k_parent_copy(const uint8_t *__restrict__ pm, uint32_t pm_bytes,
-                                                    uint8_t *__restrict__ cm, uint32_t cm_bytes, int wc, int hc,
-                                                    int whc, int64_t pc, int whp, int64_t pp, int L)
+__global__ void __launch_bounds__(256) k_parent_copy(const uint8_t *__restrict__ pm, uint32_t pm_bytes, LevelDesc pd,
+                                                    uint8_t *__restrict__ cm, uint32_t cm_bytes, LevelDesc cd, int L)
 {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int64_t n = (int64_t)4 * L * hc * wc;
-    if (i >= n) return;
-    int x = (int)(i % wc);
-    int64_t r = i / wc;
-    int y = (int)(r % hc);
-    r /= hc;
-    int f = (int)(r % L);
-    int k = (int)(r / L);
-    int px = x >> 1, py = y >> 1;
-    int cp = (px + py) & 1, cc = (x + y) & 1;
-    int64_t src = (((int64_t)cp * 4 + k) * L + f) * pp + (int64_t)py * whp + (px >> 1);
-    int64_t dst = (((int64_t)cc * 4 + k) * L + f) * pc + (int64_t)y * whc + (x >> 1);
-    float v = SP::ld(make_rsrc(pm, pm_bytes), (uint32_t)(src * SP::bytes), 0);
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    const int k = blockIdx.z / L, f = blockIdx.z - k * L;
+    if (x >= cd.w) return;
+    const int px = x >> 1, py = y >> 1;
+    const int64_t src = msg_idx((px + py) & 1, k, f, py * pd.wh + (px >> 1), pd.blk, pd.ls, pd.ps);
+    const int64_t dst = msg_idx((x + y) & 1, k, f, y * cd.wh + (x >> 1), cd.blk, cd.ls, cd.ps);
+    const float v = SP::ld(make_rsrc(pm, pm_bytes), (uint32_t)(src * SP::bytes), 0);
     SC::st(make_rsrc(cm, cm_bytes), v, (uint32_t)(dst * SC::bytes), 0);
-}
-
-__global__ void __launch_bounds__(256) k_fill_zero(uint32_t *__restrict__ p, int64_t n)
-{
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) p[i] = 0u;
-}
-
-bp_status launch_zero_level(const Plan &p, int l, uint8_t *ws, hipStream_t s)
-{
-    const Level &v = p.lv[l];
-    const int64_t n = (int64_t)(v.msg_bytes / 4);
-    k_fill_zero<<<blocks_for(n, 256), 256, 0, s>>>((uint32_t *)(ws + v.msg_off), n);
-    return launch_status();
 }
 
 template <typename F>
@@ -196,252 +300,23 @@ static bp_status with_store(int fmt, F &&fn)
     }
 }
 
-bp_status launch_zero_border(const Plan &p, int l, uint8_t *ws, hipStream_t s)
-{
-    const Level &v = p.lv[l];
-    int64_t n = (2 * (int64_t)v.h + 2 * (int64_t)v.w) * p.L;
-    return with_store(v.fmt, [&](auto st) {
-        using S = decltype(st);
-        k_zero_border<S><<<blocks_for(n, 256), 256, 0, s>>>(ws + v.msg_off, (uint32_t)v.msg_bytes, v.w, v.h, v.wh,
-                                                           v.plane, p.L);
-        return launch_status();
-    });
-}
-
 bp_status launch_parent_copy(const Plan &p, int l, uint8_t *ws, hipStream_t s)
 {
     const Level &c = p.lv[l], &pa = p.lv[l + 1];
-    int64_t n = (int64_t)4 * p.L * c.h * c.w;
     return with_store(pa.fmt, [&](auto sp) {
         return with_store(c.fmt, [&](auto sc) {
             using SP = decltype(sp);
             using SC = decltype(sc);
-            k_parent_copy<SP, SC><<<blocks_for(n, 256), 256, 0, s>>>(ws + pa.msg_off, (uint32_t)pa.msg_bytes,
-                                                                    ws + c.msg_off, (uint32_t)c.msg_bytes, c.w, c.h,
-                                                                    c.wh, c.plane, pa.wh, pa.plane, p.L);
+            k_parent_copy<SP, SC><<<dim3(cdiv(c.w, 256), c.h, 4 * p.L), 256, 0, s>>>(
+                ws + pa.msg_off, (uint32_t)pa.msg_bytes, desc(pa), ws + c.msg_off, (uint32_t)c.msg_bytes, desc(c), p.L);
             return launch_status();
         });
     });
 }
 
 // ------------------------------------------------------------------------
-// a5: one checkerboard half-sweep
+// a5: half-sweep dispatch
 // ------------------------------------------------------------------------
-
-struct IterArgs {
-    const float *cost;     // this level's colour-split cost
-    uint32_t cost_bytes;
-    uint8_t *msg;          // this level's messages
-    uint32_t msg_bytes;
-    const uint8_t *src;    // where incoming messages are read (own level or parent)
-    uint32_t src_bytes;
-    int32_t *disp;         // finest-level argmin output of the senders, or NULL
-    int w, h, wh;
-    uint32_t plane;        // elements per plane, this level
-    uint32_t src_plane;    // elements per plane of `src`
-    int src_w, src_h, src_wh;
-    int src_mode;          // 0 own slots, 1 parent slots, 2 zero
-    int colour;            // sender colour
-    int L;                 // label count (runtime, <= LP)
-    int ncomp;             // h * wh
-    float lambda, lt;      // lambda and lambda * tau
-};
-
-// One half-sweep.  Thread group of G lanes = one sender pixel of colour
-// `colour`; lane `sub` owns the outgoing messages k = sub*(4/G) .. +4/G-1, the
-// message to the neighbour on side k (0 left, 1 right, 2 up, 3 down), which
-// excludes what that neighbour sent (incoming slot k):
-//   S(f)   = cost(f) + sum_k m_k(f)             (group sum over the G lanes)
-//   h_k(f) = S(f) - m_k(f)
-//   a(f)   = min(h_k(f), a(f-1) + lambda)       forward pass, kept in registers
-//   b(f)   = min(a(f), b(f+1) + lambda, min h_k + lambda*tau)   backward pass
-//   out(f) = b(f) - min h_k                     (= b minus its own minimum)
-// The truncation folded into the backward pass and the normaliser min h_k are
-// exact rewrites of the two-pass transform followed by min(., min h + lambda tau)
-// and subtraction of the result's minimum (the result's minimum is min h_k).
-// The message lands in the neighbour's slot k^1 (it sees this pixel on the
-// opposite side).  Out-of-grid slots hold zero (zeroed per level), so loads
-// need no predicate; stores to missing neighbours are masked.
-template <int LP, int G, typename S, bool EXACT, bool RO>
-__global__ void __launch_bounds__(256) k_iter(const IterArgs a)
-{
-    constexpr int ND = 4 / G;
-    // Labels whose loads are in flight while one label is combined: bounds the
-    // registers held by prefetched values (the forward pass itself keeps ND*LP).
-    constexpr int PD = LP < 8 ? LP : 8;
-    const int nl = EXACT ? LP : a.L;
-    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
-    const int j = (int)(gid / G);
-    const int sub = (int)(gid % G);
-    if (j >= a.ncomp) return;
-    const int y = j / a.wh;
-    const int x = 2 * (j - y * a.wh) + ((y + a.colour) & 1);
-    if (x >= a.w) return;
-
-    const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost, a.cost_bytes);
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, a.src_bytes);
-    const __amdgpu_buffer_rsrc_t rm = make_rsrc(a.msg, a.msg_bytes);
-
-    // Per-lane byte offsets of label 0; label f adds f * plane * bytes (uniform).
-    const uint32_t lp_c = (uint32_t)nl * a.plane;          // elements per (colour) block of the cost
-    const uint32_t cost_off = ((uint32_t)a.colour * lp_c + (uint32_t)j) * 4u;
-    uint32_t src_off[ND];
-    uint32_t dst_off[ND];
-    bool has[ND];
-    {
-        int sj = j, sc = a.colour, sx = x, sy = y;
-        if (a.src_mode == 1) {
-            sx = x >> 1;
-            sy = y >> 1;
-            sc = (sx + sy) & 1;
-            sj = sy * a.src_wh + (sx >> 1);
-        }
-        const uint32_t lps = (uint32_t)nl * a.src_plane;
-#pragma unroll
-        for (int i = 0; i < ND; ++i) {
-            const int k = sub * ND + i;
-            src_off[i] = (((uint32_t)sc * 4u + (uint32_t)k) * lps + (uint32_t)sj) * S::bytes;
-            int nx = x, ny = y;
-            bool ok;
-            if (k == 0) { nx = x - 1; ok = x > 0; }
-            else if (k == 1) { nx = x + 1; ok = x < a.w - 1; }
-            else if (k == 2) { ny = y - 1; ok = y > 0; }
-            else { ny = y + 1; ok = y < a.h - 1; }
-            has[i] = ok;
-            const uint32_t dj = ok ? (uint32_t)(ny * a.wh + (nx >> 1)) : 0u;
-            dst_off[i] = ((((uint32_t)(a.colour ^ 1)) * 4u + (uint32_t)(k ^ 1)) * (uint32_t)nl * a.plane + dj) * S::bytes;
-        }
-    }
-    const float lam = a.lambda;
-    const float inf = __builtin_huge_valf();
-
-    // Prefetch ring: cost and owned incoming messages of labels f .. f+PD-1.
-    float pc[PD], pm[PD][ND];
-    auto issue = [&](int f, int slot) {
-        if (EXACT || f < nl) {
-            pc[slot] = ld_f32(rc, cost_off, (uint32_t)f * a.plane * 4u);
-#pragma unroll
-            for (int i = 0; i < ND; ++i) pm[slot][i] = S::ld(rs, src_off[i], (uint32_t)f * a.src_plane * S::bytes);
-        }
-    };
-#pragma unroll
-    for (int f = 0; f < PD; ++f) issue(f, f);
-
-    float acc[ND][LP];
-    float mn[ND];
-    float best = inf;
-    int bidx = 0;
-#pragma unroll
-    for (int f = 0; f < LP; ++f) {
-        const int slot = f % PD;
-        const bool on = EXACT || f < nl;
-        const float c = pc[slot];
-        float m[ND];
-#pragma unroll
-        for (int i = 0; i < ND; ++i) m[i] = pm[slot][i];
-        float part = (G == 1 || sub == 0) ? c : 0.0f;
-#pragma unroll
-        for (int i = 0; i < ND; ++i) part += m[i];
-        float tot = group_sum<G>(part);
-        if (!on) tot = inf;
-        if constexpr (RO) {
-            if (tot < best) {
-                best = tot;
-                bidx = f;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < ND; ++i) {
-            const float hv = on ? tot - m[i] : inf;
-            if (f == 0) {
-                acc[i][0] = hv;
-                mn[i] = hv;
-            } else {
-                acc[i][f] = fminf(hv, acc[i][f - 1] + lam);
-                mn[i] = fminf(mn[i], hv);
-            }
-            // Keep the recurrence at this step: otherwise the compiler sinks it
-            // past the loop and holds every label's loaded values at once.
-            asm volatile("" : "+v"(acc[i][f]), "+v"(mn[i]));
-        }
-        if (f + PD < LP) issue(f + PD, slot);
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    if constexpr (RO) {
-        if (sub == 0) a.disp[(int64_t)y * a.w + x] = bidx;
-    }
-    // Backward pass, one outgoing message at a time (border pixels skip the
-    // messages that have no receiver without per-label branches).
-#pragma unroll
-    for (int i = 0; i < ND; ++i) {
-        if (!has[i]) continue;
-        const float cap = mn[i] + a.lt;
-        float b = inf;
-#pragma unroll
-        for (int f = LP - 1; f >= 0; --f) {
-            const float v = fminf(fminf(acc[i][f], b + lam), cap);
-            b = v;
-            if (EXACT || f < nl) S::st(rm, v - mn[i], dst_off[i], (uint32_t)f * a.plane * S::bytes);
-        }
-    }
-}
-
-// Variant table: lanes per pixel G for a label count.
-struct IterVariant {
-    int G;
-};
-
-int iteration_variants(int L)
-{
-    if (L <= 32) return 3;   // G = 1, 2, 4
-    if (L <= 64) return 2;   // G = 2, 4
-    return 1;                // G = 4
-}
-
-int iteration_lanes(int L, int variant)
-{
-    static const int small[3] = {1, 2, 4};
-    static const int mid[2] = {2, 4};
-    int nv = iteration_variants(L);
-    int v = (variant <= 0 || variant > nv) ? 0 : variant - 1;
-    if (L <= 32) return small[v];
-    if (L <= 64) return mid[v];
-    return 4;
-}
-
-template <int LP, int G, typename S, bool EXACT>
-static void launch_iter_ro(const IterArgs &a, bool ro, unsigned grid, hipStream_t s)
-{
-    if (ro) k_iter<LP, G, S, EXACT, true><<<grid, 256, 0, s>>>(a);
-    else k_iter<LP, G, S, EXACT, false><<<grid, 256, 0, s>>>(a);
-}
-
-template <typename S>
-static bp_status dispatch_iter(const IterArgs &a, int G, bool ro, hipStream_t s)
-{
-    const unsigned grid = blocks_for((int64_t)a.ncomp * G, 256);
-    const int L = a.L;
-#define BP_ITER_CASE(LV, GV, EX)                                  \
-    if (G == GV) {                                                \
-        launch_iter_ro<LV, GV, S, EX>(a, ro, grid, s);            \
-        return launch_status();                                   \
-    }
-    switch (L) {
-    case 16: BP_ITER_CASE(16, 1, true) BP_ITER_CASE(16, 2, true) BP_ITER_CASE(16, 4, true) break;
-    case 32: BP_ITER_CASE(32, 1, true) BP_ITER_CASE(32, 2, true) BP_ITER_CASE(32, 4, true) break;
-    case 64: BP_ITER_CASE(64, 2, true) BP_ITER_CASE(64, 4, true) break;
-    case 96: BP_ITER_CASE(96, 4, true) break;
-    case 128: BP_ITER_CASE(128, 4, true) break;
-    default: break;
-    }
-    if (L <= 16) { BP_ITER_CASE(16, 1, false) BP_ITER_CASE(16, 2, false) BP_ITER_CASE(16, 4, false) }
-    else if (L <= 32) { BP_ITER_CASE(32, 1, false) BP_ITER_CASE(32, 2, false) BP_ITER_CASE(32, 4, false) }
-    else if (L <= 64) { BP_ITER_CASE(64, 2, false) BP_ITER_CASE(64, 4, false) }
-    else if (L <= 128) { BP_ITER_CASE(128, 4, false) }
-    else { BP_ITER_CASE(256, 4, false) }
-#undef BP_ITER_CASE
-    return BP_ERR_UNSUPPORTED;
-}
 
 bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lambda, float tau, int32_t *disp,
                            int variant, uint8_t *ws, hipStream_t s)
@@ -456,69 +331,69 @@ bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lamb
     a.w = v.w;
     a.h = v.h;
     a.wh = v.wh;
-    a.plane = (uint32_t)v.plane;
-    a.src_mode = src_mode;
-    if (src_mode == 1) {
-        const Level &pa = p.lv[l + 1];
-        a.src = ws + pa.msg_off;
-        a.src_bytes = (uint32_t)pa.msg_bytes;
-        a.src_plane = (uint32_t)pa.plane;
-        a.src_w = pa.w;
-        a.src_h = pa.h;
-        a.src_wh = pa.wh;
-    } else {
-        a.src = a.msg;
-        a.src_bytes = a.msg_bytes;
-        a.src_plane = a.plane;
-        a.src_w = v.w;
-        a.src_h = v.h;
-        a.src_wh = v.wh;
-    }
+    a.blk = (uint32_t)v.blk;
+    a.ls = (uint32_t)v.ls;
+    a.ps = (uint32_t)v.ps;
+    a.lp = (uint32_t)v.lp;
+    const Level &src = src_mode == 1 ? p.lv[l + 1] : v;
+    a.src = ws + src.msg_off;
+    a.src_bytes = (uint32_t)src.msg_bytes;
+    a.sblk = (uint32_t)src.blk;
+    a.sls = (uint32_t)src.ls;
+    a.sps = (uint32_t)src.ps;
+    a.src_wh = src.wh;
+    a.src_w = src.w;
+    a.src_h = src.h;
+    a.src_parent = src_mode == 1;
     a.colour = t & 1;
     a.L = p.L;
     a.ncomp = v.h * v.wh;
     a.lambda = lambda;
     a.lt = lambda * tau;
-    const int G = iteration_lanes(p.L, variant);
-    return with_store(v.fmt, [&](auto st) { return dispatch_iter<decltype(st)>(a, G, disp != nullptr, s); });
+    if (v.layout == PIXEL_MAJOR) {
+        int S, R;
+        pm_split(p.L, &S, &R);
+        return dispatch_iter_pm(a, v.fmt, S, R, disp != nullptr, s);
+    }
+    return dispatch_iter_lm(a, v.fmt, iteration_lanes(p.L, variant), disp != nullptr, s);
 }
 
 // ------------------------------------------------------------------------
 // a6: readout, message export
 // ------------------------------------------------------------------------
 
-// Belief b(f) = cost(f) + m_0 + m_1 + m_2 + m_3 at every pixel of the colours
-// in `mask`; lowest-index argmin, and soft-argmin sum f w / sum w with
-// w = exp(-(b - min b) / T) accumulated with a running minimum.
+// Label-major readout: belief b(f) = cost(f) + m_0 + m_1 + m_2 + m_3 at every
+// pixel of colour blockIdx.y (if in `mask`); lowest-index argmin, and
+// soft-argmin sum f w / sum w with w = exp(-(b - min b) / T) accumulated with a
+// running minimum.  grid (ncomp/256, 2).
 template <typename S>
-__global__ void __launch_bounds__(256) k_readout(const float *__restrict__ cost, uint32_t cost_bytes,
-                                                const uint8_t *__restrict__ msg, uint32_t msg_bytes, int w, int h,
-                                                int wh, uint32_t plane, int L, int mask, int32_t *__restrict__ disp,
-                                                float *__restrict__ soft, float inv_t)
+__global__ void __launch_bounds__(256) k_readout_lm(const float *__restrict__ cost, uint32_t cost_bytes,
+                                                   const uint8_t *__restrict__ msg, uint32_t msg_bytes, LevelDesc d,
+                                                   int L, int mask, int32_t *__restrict__ disp,
+                                                   float *__restrict__ soft, float inv_t)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t ncomp = (int64_t)h * wh;
-    if (i >= 2 * ncomp) return;
-    const int c = (int)(i / ncomp);
+    const int c = blockIdx.y;
     if (!((mask >> c) & 1)) return;
-    const int j = (int)(i - c * ncomp);
-    const int y = j / wh;
-    const int x = 2 * (j - y * wh) + ((y + c) & 1);
-    if (x >= w) return;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= d.h * d.wh) return;
+    const int y = j / d.wh;
+    const int x = 2 * (j - y * d.wh) + ((y + c) & 1);
+    if (x >= d.w) return;
     const __amdgpu_buffer_rsrc_t rc = make_rsrc(cost, cost_bytes);
     const __amdgpu_buffer_rsrc_t rm = make_rsrc(msg, msg_bytes);
-    const uint32_t lp = (uint32_t)L * plane;
-    const uint32_t co = ((uint32_t)c * lp + (uint32_t)j) * 4u;
+    const uint32_t co = (uint32_t)(c * d.blk + j) * 4u;
     uint32_t mo[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) mo[k] = (((uint32_t)c * 4u + (uint32_t)k) * lp + (uint32_t)j) * S::bytes;
+    for (int k = 0; k < 4; ++k) mo[k] = (uint32_t)((c * 4 + k) * d.blk + j) * S::bytes;
+    const uint32_t cls = (uint32_t)d.ls * 4u, mls = (uint32_t)d.ls * S::bytes;
     float best = __builtin_huge_valf();
     int bidx = 0;
     float num = 0.0f, den = 0.0f;
+#pragma unroll 8
     for (int f = 0; f < L; ++f) {
-        float b = ld_f32(rc, co, (uint32_t)f * plane * 4u);
+        float b = ld_f32(rc, co, (uint32_t)f * cls);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) b += S::ld(rm, mo[k], (uint32_t)f * plane * S::bytes);
+        for (int k = 0; k < 4; ++k) b += S::ld(rm, mo[k], (uint32_t)f * mls);
         if (b < best) {
             if (soft) {
                 const float sc = expf((b - best) * inv_t);
@@ -534,59 +409,130 @@ __global__ void __launch_bounds__(256) k_readout(const float *__restrict__ cost,
             den += wgt;
         }
     }
-    const int64_t o = (int64_t)y * w + x;
+    const int64_t o = (int64_t)y * d.w + x;
     if (disp) disp[o] = bidx;
     if (soft) soft[o] = num / den;
+}
+
+// Pixel-major readout: SEG lanes per pixel, R labels per lane.  grid (ncomp*SEG/256, 2).
+template <int SEG, int R, typename S>
+__global__ void __launch_bounds__(256) k_readout_pm(const float *__restrict__ cost, uint32_t cost_bytes,
+                                                   const uint8_t *__restrict__ msg, uint32_t msg_bytes, LevelDesc d,
+                                                   int lp, int L, int mask, int32_t *__restrict__ disp,
+                                                   float *__restrict__ soft, float inv_t)
+{
+    const int c = blockIdx.y;
+    if (!((mask >> c) & 1)) return;
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    const int j = gid / SEG, s = gid % SEG;
+    if (j >= d.h * d.wh) return;
+    const int y = j / d.wh;
+    const int x = 2 * (j - y * d.wh) + ((y + c) & 1);
+    if (x >= d.w) return;
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(cost, cost_bytes);
+    const __amdgpu_buffer_rsrc_t rm = make_rsrc(msg, msg_bytes);
+    const int f0 = s * R;
+    float b[R], m[R];
+    ld_row<StoreF32, R>(rc, ((uint32_t)(c * d.blk) + (uint32_t)j * lp + f0) * 4u, b);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ld_row<S, R>(rm, ((uint32_t)((c * 4 + k) * d.blk) + (uint32_t)j * lp + f0) * S::bytes, m);
+#pragma unroll
+        for (int r = 0; r < R; ++r) b[r] += m[r];
+    }
+    const float inf = __builtin_huge_valf();
+    float bv = inf;
+    int bi = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (f0 + r >= L) b[r] = inf;
+        if (b[r] < bv) {
+            bv = b[r];
+            bi = f0 + r;
+        }
+    }
+    seg_argmin<SEG>(bv, bi);
+    const int64_t o = (int64_t)y * d.w + x;
+    if (soft) {
+        float num = 0.0f, den = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (f0 + r < L) {
+                const float wgt = expf(-(b[r] - bv) * inv_t);
+                num += (float)(f0 + r) * wgt;
+                den += wgt;
+            }
+        }
+        auto add = [](float p, float q) { return p + q; };
+        num = seg_allreduce<SEG>(num, add);
+        den = seg_allreduce<SEG>(den, add);
+        if (s == 0) soft[o] = num / den;
+    }
+    if (disp && s == 0) disp[o] = bi;
 }
 
 bp_status launch_readout(const Plan &p, int colour_mask, int32_t *disp, float *soft, float temperature, uint8_t *ws,
                          hipStream_t s)
 {
     const Level &v = p.lv[0];
-    const int64_t n = 2 * (int64_t)v.h * v.wh;
+    const int64_t ncomp = (int64_t)v.h * v.wh;
     const float inv_t = soft ? 1.0f / temperature : 0.0f;
     return with_store(v.fmt, [&](auto st) {
         using S = decltype(st);
-        k_readout<S><<<blocks_for(n, 256), 256, 0, s>>>((const float *)(ws + v.cost_off), (uint32_t)v.cost_bytes,
-                                                       ws + v.msg_off, (uint32_t)v.msg_bytes, v.w, v.h, v.wh,
-                                                       (uint32_t)v.plane, p.L, colour_mask, disp, soft, inv_t);
-        return launch_status();
+        const float *cost = (const float *)(ws + v.cost_off);
+        const uint8_t *msg = ws + v.msg_off;
+        if (v.layout == LABEL_MAJOR) {
+            k_readout_lm<S><<<dim3(cdiv(ncomp, 256), 2), 256, 0, s>>>(cost, (uint32_t)v.cost_bytes, msg,
+                                                                     (uint32_t)v.msg_bytes, desc(v), p.L, colour_mask,
+                                                                     disp, soft, inv_t);
+            return launch_status();
+        }
+        int SEGV, R;
+        pm_split(p.L, &SEGV, &R);
+#define BP_RO_CASE(SV, RV)                                                                                         \
+    if (SEGV == SV && R == RV) {                                                                                   \
+        k_readout_pm<SV, RV, S><<<dim3(cdiv(ncomp * SV, 256), 2), 256, 0, s>>>(                                    \
+            cost, (uint32_t)v.cost_bytes, msg, (uint32_t)v.msg_bytes, desc(v), v.lp, p.L, colour_mask, disp, soft, \
+            inv_t);                                                                                                \
+        return launch_status();                                                                                    \
+    }
+        BP_RO_CASE(4, 4)
+        BP_RO_CASE(8, 4)
+        BP_RO_CASE(16, 4)
+        BP_RO_CASE(16, 6)
+        BP_RO_CASE(16, 8)
+        BP_RO_CASE(16, 12)
+        BP_RO_CASE(16, 16)
+#undef BP_RO_CASE
+        return BP_ERR_UNSUPPORTED;
     });
 }
 
-// Colour-split messages -> planar float32 [4][L][h][w]; slots without a
-// neighbour read as zero.
+// Messages of level 0 -> planar float32 [4][L][h][w]; slots without a
+// neighbour read as zero.  grid (w/256, h, 4L).
 template <typename S>
-__global__ void __launch_bounds__(256) k_export(const uint8_t *__restrict__ msg, uint32_t msg_bytes, int w, int h,
-                                               int wh, uint32_t plane, int L, float *__restrict__ out)
+__global__ void __launch_bounds__(256) k_export(const uint8_t *__restrict__ msg, uint32_t msg_bytes, LevelDesc d, int L,
+                                               float *__restrict__ out)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t n = (int64_t)4 * L * h * w;
-    if (i >= n) return;
-    const int x = (int)(i % w);
-    int64_t r = i / w;
-    const int y = (int)(r % h);
-    r /= h;
-    const int f = (int)(r % L);
-    const int k = (int)(r / L);
-    bool ok = (k == 0) ? x > 0 : (k == 1) ? x < w - 1 : (k == 2) ? y > 0 : y < h - 1;
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    const int k = blockIdx.z / L, f = blockIdx.z - k * L;
+    if (x >= d.w) return;
+    const bool ok = (k == 0) ? x > 0 : (k == 1) ? x < d.w - 1 : (k == 2) ? y > 0 : y < d.h - 1;
     float v = 0.0f;
     if (ok) {
-        const int c = (x + y) & 1;
-        const int64_t idx = (((int64_t)c * 4 + k) * L + f) * plane + (int64_t)y * wh + (x >> 1);
+        const int64_t idx = msg_idx((x + y) & 1, k, f, y * d.wh + (x >> 1), d.blk, d.ls, d.ps);
         v = S::ld(make_rsrc(msg, msg_bytes), (uint32_t)(idx * S::bytes), 0);
     }
-    out[i] = v;
+    out[(((int64_t)k * L + f) * d.h + y) * d.w + x] = v;
 }
 
 bp_status launch_export(const Plan &p, float *out, uint8_t *ws, hipStream_t s)
 {
     const Level &v = p.lv[0];
-    const int64_t n = (int64_t)4 * p.L * v.h * v.w;
     return with_store(v.fmt, [&](auto st) {
         using S = decltype(st);
-        k_export<S><<<blocks_for(n, 256), 256, 0, s>>>(ws + v.msg_off, (uint32_t)v.msg_bytes, v.w, v.h, v.wh,
-                                                      (uint32_t)v.plane, p.L, out);
+        k_export<S><<<dim3(cdiv(v.w, 256), v.h, 4 * p.L), 256, 0, s>>>(ws + v.msg_off, (uint32_t)v.msg_bytes, desc(v),
+                                                                        p.L, out);
         return launch_status();
     });
 }

@@ -27,6 +27,7 @@ __device__ __forceinline__ void st_f32(__amdgpu_buffer_rsrc_t r, float v, uint32
 // rounded to nearest-even in the storage format.
 struct StoreF32 {
     static constexpr int bytes = 4;
+    static constexpr int fmt = 0;
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
     {
         return ld_f32(r, voff, soff);
@@ -39,6 +40,9 @@ struct StoreF32 {
 
 struct StoreF16 {
     static constexpr int bytes = 2;
+    static constexpr int fmt = 1;
+    static __device__ __forceinline__ float decode(uint16_t u) { return (float)__builtin_bit_cast(_Float16, u); }
+    static __device__ __forceinline__ uint16_t encode(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
     {
         uint16_t u = __builtin_bit_cast(uint16_t, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
@@ -53,6 +57,8 @@ struct StoreF16 {
 
 struct StoreBF16 {
     static constexpr int bytes = 2;
+    static constexpr int fmt = 2;
+    static __device__ __forceinline__ float decode(uint16_t u) { return __builtin_bit_cast(float, (uint32_t)u << 16); }
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
     {
         uint16_t u = __builtin_bit_cast(uint16_t, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
@@ -70,6 +76,164 @@ struct StoreBF16 {
         __builtin_amdgcn_raw_buffer_store_b16(encode(v), r, voff, soff, 0);
     }
 };
+
+// ---- R consecutive values at a byte offset (pixel-major rows) ----
+
+typedef unsigned int u32x2 __attribute__((vector_size(8)));
+typedef unsigned int u32x4 __attribute__((vector_size(16)));
+
+// Rows are loaded as consecutive 32-bit buffer loads held in scalar
+// temporaries; the backend merges them into 8- and 16-byte loads.  (This
+// toolchain's b128 load builtin lowers to a single 32-bit load, and 32-bit
+// loads written into vector components are folded into one load.)
+template <int N>
+__device__ __forceinline__ void ld_words(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t (&w)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff + 4u * i, 0, 0);
+}
+
+// Stores: 16-byte stores for groups of four words, then 8- and 4-byte ones.
+template <int N>
+__device__ __forceinline__ void st_words(__amdgpu_buffer_rsrc_t r, uint32_t voff, const uint32_t (&w)[N])
+{
+    constexpr int Q = N / 4, rem = N - 4 * Q;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        u32x4 t;
+        t[0] = w[4 * q]; t[1] = w[4 * q + 1]; t[2] = w[4 * q + 2]; t[3] = w[4 * q + 3];
+        __builtin_amdgcn_raw_buffer_store_b128(t, r, voff + 16u * q, 0, 0);
+    }
+    if constexpr (rem >= 2) {
+        u32x2 t;
+        t[0] = w[4 * Q]; t[1] = w[4 * Q + 1];
+        __builtin_amdgcn_raw_buffer_store_b64(t, r, voff + 16u * Q, 0, 0);
+    }
+    if constexpr (rem % 2 == 1) __builtin_amdgcn_raw_buffer_store_b32(w[N - 1], r, voff + 4u * (N - 1), 0, 0);
+}
+
+template <typename S, int R>
+__device__ __forceinline__ void ld_row(__amdgpu_buffer_rsrc_t r, uint32_t voff, float (&v)[R])
+{
+    static_assert(R % 2 == 0, "pixel-major rows hold an even number of labels per lane");
+    if constexpr (S::bytes == 4) {
+        uint32_t w[R];
+        ld_words<R>(r, voff, w);
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = __builtin_bit_cast(float, w[i]);
+    } else {
+        uint32_t w[R / 2];
+        ld_words<R / 2>(r, voff, w);
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            v[2 * i] = S::decode((uint16_t)(w[i] & 0xffffu));
+            v[2 * i + 1] = S::decode((uint16_t)(w[i] >> 16));
+        }
+    }
+}
+
+template <typename S, int R>
+__device__ __forceinline__ void st_row(__amdgpu_buffer_rsrc_t r, uint32_t voff, const float (&v)[R])
+{
+    if constexpr (S::bytes == 4) {
+        uint32_t w[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) w[i] = __builtin_bit_cast(uint32_t, v[i]);
+        st_words<R>(r, voff, w);
+    } else {
+        uint32_t w[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) w[i] = (uint32_t)S::encode(v[2 * i]) | ((uint32_t)S::encode(v[2 * i + 1]) << 16);
+        st_words<R / 2>(r, voff, w);
+    }
+}
+
+// ---- DPP exchanges inside segments of SEG lanes (SEG = 4, 8 or 16) ----
+// dpp controls: row_shl:n = 0x100 + n, row_shr:n = 0x110 + n,
+// quad_perm(1,0,3,2) = 0xB1, quad_perm(2,3,0,1) = 0x4E, row_half_mirror = 0x141,
+// row_mirror = 0x140.
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float old, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v),
+                                                                 CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int old, int v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xF, 0xF, false);
+}
+
+// Value of lane (s - N) of the same segment, or `ident` when s < N.
+template <int SEG, int N>
+__device__ __forceinline__ float seg_from_lower(float v, float ident, int s)
+{
+    float r = dpp_f<0x110 + N>(ident, v);
+    if constexpr (SEG < 16) r = s < N ? ident : r;
+    return r;
+}
+
+// Value of lane (s + N) of the same segment, or `ident` when s + N >= SEG.
+template <int SEG, int N>
+__device__ __forceinline__ float seg_from_upper(float v, float ident, int s)
+{
+    float r = dpp_f<0x100 + N>(ident, v);
+    if constexpr (SEG < 16) r = s + N >= SEG ? ident : r;
+    return r;
+}
+
+// Inclusive prefix minimum over lanes 0..s of the segment.
+template <int SEG>
+__device__ __forceinline__ float seg_prefix_min(float v, int s)
+{
+    const float inf = __builtin_huge_valf();
+    v = fminf(v, seg_from_lower<SEG, 1>(v, inf, s));
+    v = fminf(v, seg_from_lower<SEG, 2>(v, inf, s));
+    if constexpr (SEG > 4) v = fminf(v, seg_from_lower<SEG, 4>(v, inf, s));
+    if constexpr (SEG > 8) v = fminf(v, seg_from_lower<SEG, 8>(v, inf, s));
+    return v;
+}
+
+// Inclusive suffix minimum over lanes s..SEG-1 of the segment.
+template <int SEG>
+__device__ __forceinline__ float seg_suffix_min(float v, int s)
+{
+    const float inf = __builtin_huge_valf();
+    v = fminf(v, seg_from_upper<SEG, 1>(v, inf, s));
+    v = fminf(v, seg_from_upper<SEG, 2>(v, inf, s));
+    if constexpr (SEG > 4) v = fminf(v, seg_from_upper<SEG, 4>(v, inf, s));
+    if constexpr (SEG > 8) v = fminf(v, seg_from_upper<SEG, 8>(v, inf, s));
+    return v;
+}
+
+// Butterfly combine over the segment: every lane ends with op over all lanes.
+template <int SEG, typename Op>
+__device__ __forceinline__ float seg_allreduce(float v, Op op)
+{
+    v = op(v, dpp_f<0xB1>(v, v));
+    v = op(v, dpp_f<0x4E>(v, v));
+    if constexpr (SEG > 4) v = op(v, dpp_f<0x141>(v, v));
+    if constexpr (SEG > 8) v = op(v, dpp_f<0x140>(v, v));
+    return v;
+}
+
+// Lowest index attaining the minimum value over the segment (ties: lower index).
+template <int SEG>
+__device__ __forceinline__ void seg_argmin(float &v, int &i)
+{
+    auto step = [&](float ov, int oi) {
+        if (ov < v || (ov == v && oi < i)) {
+            v = ov;
+            i = oi;
+        }
+    };
+    step(dpp_f<0xB1>(v, v), dpp_i<0xB1>(i, i));
+    step(dpp_f<0x4E>(v, v), dpp_i<0x4E>(i, i));
+    if constexpr (SEG > 4) step(dpp_f<0x141>(v, v), dpp_i<0x141>(i, i));
+    if constexpr (SEG > 8) step(dpp_f<0x140>(v, v), dpp_i<0x140>(i, i));
+}
 
 // Sum of `v` over aligned groups of G lanes (G = 1, 2, 4) with DPP quad
 // permutations; IEEE addition is commutative, so every lane of a group gets

@@ -20,16 +20,25 @@ inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a
 enum MsgFmt : int { FMT_F32 = 0, FMT_F16 = 1, FMT_BF16 = 2 };
 inline int fmt_bytes(int fmt) { return fmt == FMT_F32 ? 4 : 2; }
 
-// One pyramid level of one problem.  Both the cost and the messages are stored
-// colour-split: pixel (x, y) has colour (x + y) & 1 and compact index
-// j = y * wh + (x >> 1) inside its colour's planes, wh = ceil(w / 2).  A plane
-// holds `plane` >= h * wh elements (padded to 64); planes are ordered
-//   cost: [colour][label][plane]          (float32)
-//   msg:  [colour][slot][label][plane]    (slot k = received from side k:
-//                                          0 left, 1 right, 2 up, 3 down)
+// Layouts of a level's cost and messages.  Both are colour-split: pixel (x, y)
+// has colour c = (x + y) & 1 and compact index j = y * wh + (x >> 1) among its
+// colour's `plane` slots (wh = ceil(w / 2), plane >= h * wh).
+//  LABEL_MAJOR: [colour][slot][label][plane] -- lanes over pixels read one
+//               label plane at a time (coalesced along rows).
+//  PIXEL_MAJOR: [colour][slot][plane][lp]    -- a pixel's labels are contiguous
+//               (lp = label count padded to the lane split), so the lanes that
+//               share one pixel read 16-byte vectors of consecutive labels.
+// The cost has the same layout without the slot index.  Element offsets:
+//   cost(c, f, j)   = c * blk + f * ls + j * ps
+//   msg(c, k, f, j) = (c * 4 + k) * blk + f * ls + j * ps
+enum Layout : int { LABEL_MAJOR = 0, PIXEL_MAJOR = 1 };
+
 struct Level {
     int w, h, wh;
-    int64_t plane;        // elements per (colour, slot, label) plane
+    int64_t plane;        // compact pixel slots per colour (padded to 64)
+    int layout;
+    int lp;               // labels stored per pixel (L, or padded for PIXEL_MAJOR)
+    int64_t blk, ls, ps;  // element strides: per (colour[, slot]) block, per label, per pixel
     int fmt;              // message storage format at this level
     size_t cost_off;      // byte offset of this level's cost in the workspace
     size_t msg_off;       // byte offset of this level's messages
@@ -43,11 +52,18 @@ struct Plan {
     size_t bytes;         // total workspace bytes of this problem (aligned)
 };
 
-// Fills `plan` for one problem with its workspace starting at byte `base`.
-// Returns false when the sizes do not fit the kernels' 32-bit offsets.
-bool make_plan(int w, int h, int L, int levels, int msg_fmt, size_t base, Plan *plan);
+// Pixel-major lane split for L labels: S lanes per message direction (4, 8 or
+// 16, a DPP row or part of one), R consecutive labels per lane, lp = S * R.
+void pm_split(int L, int *S, int *R);
 
-// Status helpers.
+// Fills `plan` for one problem with its workspace starting at byte `base`.
+// Levels >= pm_from are pixel-major.  Returns false when a level does not fit
+// the kernels' 32-bit byte offsets.
+bool make_plan(int w, int h, int L, int levels, int msg_fmt, int pm_from, size_t base, Plan *plan);
+
+// First pixel-major level the library picks when the caller does not.
+int default_pm_from(int w, int h, int L, int levels, int msg_fmt);
+
 bp_status launch_status();
 
 // ---- kernel launchers (each enqueues on `s`, returns BP_OK or BP_ERR_HIP) ----
@@ -59,17 +75,17 @@ bp_status launch_cost_volume(const uint8_t *left, const uint8_t *right, int w, i
 bp_status launch_downsample(const uint8_t *in, int w, int h, int ch, int64_t stride, int ds,
                             uint8_t *out, hipStream_t s);
 
-// a3: colour-split copy of the finest cost, and the sum pyramid.
+// a3: level-0 cost in the level's layout, and the sum pyramid.
 bp_status launch_split_cost(const float *planar, const Plan &p, uint8_t *ws, hipStream_t s);
 bp_status launch_pyramid_level(const Plan &p, int l, uint8_t *ws, hipStream_t s);
 
-// a4: out-of-grid message slots of a level set to zero; explicit parent copy.
-bp_status launch_zero_border(const Plan &p, int l, uint8_t *ws, hipStream_t s);
+// a4: zero every level's out-of-grid slots and the coarsest level's
+// messages; explicit parent copy.
+bp_status launch_init_messages(const Plan &p, uint8_t *ws, hipStream_t s);
 bp_status launch_parent_copy(const Plan &p, int l, uint8_t *ws, hipStream_t s);
-bp_status launch_zero_level(const Plan &p, int l, uint8_t *ws, hipStream_t s);
 
 // a5: one checkerboard half-sweep at level l.  src_mode: 0 read own slots,
-// 1 read the parent level's slots (fused parent copy), 2 start from zero.
+// 1 read the parent level's slots (fused parent copy).
 // If disp != NULL the senders' argmin labels are written (finest level).
 bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lambda, float tau,
                            int32_t *disp, int variant, uint8_t *ws, hipStream_t s);
@@ -84,9 +100,41 @@ bp_status launch_upsample(const int32_t *disp_lo, int wl, int hl, const uint8_t 
                           int ch, int64_t stride, float sigma_s, float sigma_r, int radius, float *out,
                           hipStream_t s);
 
-// Number of iteration-kernel variants for a label count and the variant's
+// Label-major half-sweep variants: count for a label count and the variant's
 // lanes per pixel (1, 2 or 4); variant 0 = default.
 int iteration_variants(int L);
 int iteration_lanes(int L, int variant);
+
+// Label-major half-sweep (bp_iter_lm.hip) and pixel-major half-sweep (bp_iter_pm.hip).
+struct IterArgs {
+    const float *cost;     // this level's cost
+    uint32_t cost_bytes;
+    uint8_t *msg;          // this level's messages
+    uint32_t msg_bytes;
+    const uint8_t *src;    // where incoming messages are read (own level or parent)
+    uint32_t src_bytes;
+    int32_t *disp;         // finest-level argmin output of the senders, or NULL
+    int w, h, wh;
+    uint32_t blk, ls, ps, lp;              // this level's element strides (see Level)
+    uint32_t sblk, sls, sps;               // element strides of `src`
+    int src_wh, src_w, src_h;
+    int src_parent;        // 1 when `src` is the parent level
+    int colour;            // sender colour
+    int L;                 // label count
+    int ncomp;             // h * wh
+    float lambda, lt;      // lambda and lambda * tau
+};
+bp_status dispatch_iter_lm(const IterArgs &a, int fmt, int G, bool ro, hipStream_t s);
+
+// a8: adjoint kernels (bp_adjoint.hip).  `msg` is a finest-level message
+// state (label-major float32), `mbar` its adjoint, `grad_cost` planar.
+bp_status launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+int bwd_step_blocks(const Plan &p);
+bp_status launch_bwd_readout(const Plan &p, const uint8_t *msg, float *mbar, const float *grad_soft,
+                             float *grad_cost, float temperature, uint8_t *ws, hipStream_t s);
+bp_status launch_bwd_step(const Plan &p, int t, const uint8_t *msg, float *mbar, float *grad_cost, float *partial,
+                          float lambda, float tau, uint8_t *ws, hipStream_t s);
+bp_status launch_bwd_finish(const float *partial, int n, float *grad_lambda, float *grad_tau, hipStream_t s);
+bp_status dispatch_iter_pm(const IterArgs &a, int fmt, int S, int R, bool ro, hipStream_t s);
 
 }  // namespace bpk

@@ -1,0 +1,193 @@
+// a5, pixel-major levels: one checkerboard half-sweep with the labels of a
+// pixel spread over lanes and the distance transform done as wave-level
+// min-plus scans.
+//
+// A sender pixel owns 4*SEG lanes: SEG lanes per outgoing message k (0 left,
+// 1 right, 2 up, 3 down), lane s holding labels [s*R, s*R + R).  Each lane
+// reads its labels of the cost and of the four incoming slots as 16-byte
+// vectors (a pixel's labels are contiguous in this layout), and forms
+//   h(f) = cost(f) + sum of the incoming messages except slot k   (order 0..3)
+// The two passes of the transform are split into a lane-local pass over R
+// labels and a scan across the SEG lanes of the message:
+//   forward   A(f) = min_{g<=f} h(g) + lambda (f - g):
+//             local a(f) within the lane, then the value entering lane s is
+//             A(sR - 1) = lambda R (s - 1) + min_{s'<s} (e_s' - lambda R s'),
+//             e_s' = lane s' local value at its last label (exclusive DPP
+//             prefix-min over the segment);
+//   backward  B(f) = min_{g>=f} A(g) + lambda (g - f): local pass over A,
+//             then B((s+1)R) = min_{s'>s} (b_s' + lambda R s') - lambda R (s+1)
+//             (exclusive DPP suffix-min), b_s' = lane s' local value at its
+//             first label;
+//   out(f)    = min(B(f), min h + lambda tau) - min h   (DPP min-reduction).
+// With integer-valued data every step is exact, so the result equals the
+// sequential two-pass transform bit for bit.  Labels past L are +inf in h and
+// never influence real labels.
+#include <hip/hip_runtime.h>
+
+#include "bp_device.h"
+#include "bp_internal.h"
+
+namespace bpk {
+
+template <int SEG, int R, typename S, bool EXACT, bool RO>
+__global__ void __launch_bounds__(256) k_iter_pm(const IterArgs a)
+{
+    constexpr int GP = 4 * SEG;           // lanes per pixel
+    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+    const int j = (int)(gid / GP);
+    const int lane = (int)(gid % GP);
+    const int k = lane / SEG;             // outgoing message / excluded incoming slot
+    const int s = lane % SEG;             // label segment
+    if (j >= a.ncomp) return;
+    const int y = j / a.wh;
+    const int x = 2 * (j - y * a.wh) + ((y + a.colour) & 1);
+    if (x >= a.w) return;
+
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost, a.cost_bytes);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, a.src_bytes);
+    const __amdgpu_buffer_rsrc_t rm = make_rsrc(a.msg, a.msg_bytes);
+    const int f0 = s * R;
+
+    // Cost and the four incoming rows of labels f0 .. f0+R-1.
+    float c[R], m[4][R];
+    ld_row<StoreF32, R>(rc, ((uint32_t)a.colour * a.blk + (uint32_t)j * a.lp + (uint32_t)f0) * 4u, c);
+    {
+        int sj = j, sc = a.colour;
+        if (a.src_parent) {
+            const int sx = x >> 1, sy = y >> 1;
+            sc = (sx + sy) & 1;
+            sj = sy * a.src_wh + (sx >> 1);
+        }
+        const uint32_t base = (uint32_t)sj * a.sps + (uint32_t)f0;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            ld_row<S, R>(rs, (((uint32_t)sc * 4u + (uint32_t)kk) * a.sblk + base) * S::bytes, m[kk]);
+    }
+    const float inf = __builtin_huge_valf();
+    const float lam = a.lambda;
+    const float lamR = lam * (float)R;
+
+    if constexpr (RO) {
+        // Belief b(f) = cost + m_0 + m_1 + m_2 + m_3 and its lowest-index argmin.
+        float bv = inf;
+        int bi = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float b = (((c[r] + m[0][r]) + m[1][r]) + m[2][r]) + m[3][r];
+            if (!EXACT && f0 + r >= a.L) b = inf;
+            if (b < bv) {
+                bv = b;
+                bi = f0 + r;
+            }
+        }
+        seg_argmin<SEG>(bv, bi);
+        if (k == 0 && s == 0) a.disp[(int64_t)y * a.w + x] = bi;
+    }
+
+    // h excluding slot k, summed in slot order (adding zero for the excluded one).
+    float h[R];
+    float hmin = inf;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float v = c[r];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) v += (kk == k) ? 0.0f : m[kk][r];
+        if (!EXACT && f0 + r >= a.L) v = inf;
+        h[r] = v;
+        hmin = fminf(hmin, v);
+    }
+    hmin = seg_allreduce<SEG>(hmin, [](float p, float q) { return fminf(p, q); });
+
+    // Forward pass.
+    float A[R];
+    A[0] = h[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r) A[r] = fminf(h[r], A[r - 1] + lam);
+    {
+        const float u = A[R - 1] - lamR * (float)s;
+        const float P = seg_prefix_min<SEG>(seg_from_lower<SEG, 1>(u, inf, s), s);
+        const float carry = P + lamR * (float)(s - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) A[r] = fminf(A[r], carry + lam * (float)(r + 1));
+    }
+    // Backward pass.
+    float B[R];
+    B[R - 1] = A[R - 1];
+#pragma unroll
+    for (int r = R - 2; r >= 0; --r) B[r] = fminf(A[r], B[r + 1] + lam);
+    {
+        const float v = B[0] + lamR * (float)s;
+        const float Q = seg_suffix_min<SEG>(seg_from_upper<SEG, 1>(v, inf, s), s);
+        const float carry = Q - lamR * (float)(s + 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) B[r] = fminf(B[r], carry + lam * (float)(R - r));
+    }
+    const float cap = hmin + a.lt;
+    float out[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r] = fminf(B[r], cap) - hmin;
+
+    // Receiver of message k and its slot k^1.
+    int nx = x, ny = y;
+    bool ok;
+    if (k == 0) { nx = x - 1; ok = x > 0; }
+    else if (k == 1) { nx = x + 1; ok = x < a.w - 1; }
+    else if (k == 2) { ny = y - 1; ok = y > 0; }
+    else { ny = y + 1; ok = y < a.h - 1; }
+    if (ok) {
+        const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
+        st_row<S, R>(rm, (((uint32_t)(a.colour ^ 1) * 4u + (uint32_t)(k ^ 1)) * a.blk + dj * a.lp + (uint32_t)f0) *
+                             S::bytes,
+                     out);
+    }
+}
+
+void pm_split(int L, int *S, int *R)
+{
+    if (L <= 16) { *S = 4; *R = 4; }
+    else if (L <= 32) { *S = 8; *R = 4; }
+    else if (L <= 64) { *S = 16; *R = 4; }
+    else if (L <= 96) { *S = 16; *R = 6; }
+    else if (L <= 128) { *S = 16; *R = 8; }
+    else if (L <= 192) { *S = 16; *R = 12; }
+    else { *S = 16; *R = 16; }
+}
+
+template <int SEG, int R, typename S>
+static bp_status launch_pm(const IterArgs &a, bool ro, hipStream_t st)
+{
+    const unsigned grid = (unsigned)(((int64_t)a.ncomp * 4 * SEG + 255) / 256);
+    const bool exact = a.L == SEG * R;
+    if (exact) {
+        if (ro) k_iter_pm<SEG, R, S, true, true><<<grid, 256, 0, st>>>(a);
+        else k_iter_pm<SEG, R, S, true, false><<<grid, 256, 0, st>>>(a);
+    } else {
+        if (ro) k_iter_pm<SEG, R, S, false, true><<<grid, 256, 0, st>>>(a);
+        else k_iter_pm<SEG, R, S, false, false><<<grid, 256, 0, st>>>(a);
+    }
+    return launch_status();
+}
+
+template <typename S>
+static bp_status dispatch_pm(const IterArgs &a, int SEGV, int R, bool ro, hipStream_t st)
+{
+    if (SEGV == 4 && R == 4) return launch_pm<4, 4, S>(a, ro, st);
+    if (SEGV == 8 && R == 4) return launch_pm<8, 4, S>(a, ro, st);
+    if (SEGV == 16 && R == 4) return launch_pm<16, 4, S>(a, ro, st);
+    if (SEGV == 16 && R == 6) return launch_pm<16, 6, S>(a, ro, st);
+    if (SEGV == 16 && R == 8) return launch_pm<16, 8, S>(a, ro, st);
+    if (SEGV == 16 && R == 12) return launch_pm<16, 12, S>(a, ro, st);
+    if (SEGV == 16 && R == 16) return launch_pm<16, 16, S>(a, ro, st);
+    return BP_ERR_UNSUPPORTED;
+}
+
+bp_status dispatch_iter_pm(const IterArgs &a, int fmt, int SEGV, int R, bool ro, hipStream_t st)
+{
+    switch (fmt) {
+    case FMT_F16: return dispatch_pm<StoreF16>(a, SEGV, R, ro, st);
+    case FMT_BF16: return dispatch_pm<StoreBF16>(a, SEGV, R, ro, st);
+    default: return dispatch_pm<StoreF32>(a, SEGV, R, ro, st);
+    }
+}
+
+}  // namespace bpk

@@ -78,10 +78,11 @@ class BPParams:
     temperature: float = 0.5
     checkpoint_every: int = 0
     variant: int = 0
+    pm_from: int = -1
 
     def c(self) -> _abi.BpParams:
         return _abi.BpParams(self.levels, self.iters, self.lam, self.tau, MSG_DTYPES[self.msg_dtype],
-                             self.temperature, self.checkpoint_every, self.variant)
+                             self.temperature, self.checkpoint_every, self.variant, self.pm_from)
 
 
 class Workspace:
@@ -161,6 +162,49 @@ def run(costs, params: BPParams, *, want_disp: bool = True, want_soft: bool = Fa
     _abi.check("bp_run", st)
     outs = [{k: v for k, v in o.items() if v is not None} for o in outputs]
     return outs[0] if single else outs
+
+
+def checkpoint_bytes(costs, params: BPParams) -> int:
+    """Bytes of the checkpoint buffer a forward call with checkpoint_every > 0 fills."""
+    costs = [costs] if isinstance(costs, torch.Tensor) else list(costs)
+    probs = _problems(costs, [None] * len(costs), [None] * len(costs), [None] * len(costs))
+    p = params.c()
+    return _abi.lib().bp_checkpoint_size(probs, len(costs), ctypes.byref(p))
+
+
+def backward(costs, params: BPParams, checkpoints: torch.Tensor, grad_soft, workspace: Workspace | None = None,
+             stream=None):
+    """Gradient of sum(grad_soft * soft_disparity) with respect to the cost
+    volumes, lambda and tau, from the checkpoints of a forward ``run`` with the
+    same costs and params.  ``grad_soft`` is a tensor [H][W] (or a list).
+    Returns (grad_costs (tensor or list), grad_lambda [1], grad_tau [1])."""
+    single = isinstance(costs, torch.Tensor)
+    costs = [costs] if single else list(costs)
+    grads_soft = [grad_soft] if single else list(grad_soft)
+    dev = costs[0].device
+    for c, g in zip(costs, grads_soft):
+        _need_gpu(c, g)
+    gs = torch.cat([g.reshape(-1).float() for g in grads_soft]).contiguous()
+    total = sum(c.numel() for c in costs)
+    gc = torch.empty(total, dtype=torch.float32, device=dev)
+    gl = torch.empty(1, dtype=torch.float32, device=dev)
+    gt = torch.empty(1, dtype=torch.float32, device=dev)
+    probs = _problems(costs, [None] * len(costs), [None] * len(costs), [None] * len(costs))
+    p = params.c()
+    lib = _abi.lib()
+    nbytes = lib.bp_backward_workspace_size(probs, len(costs), ctypes.byref(p))
+    if nbytes == 0:
+        raise ValueError("bp_backward_workspace_size rejected the problem description")
+    ws = (workspace or Workspace()).get(nbytes, dev)
+    st = lib.bp_backward(probs, len(costs), ctypes.byref(p), _ptr(checkpoints),
+                         checkpoints.numel() * checkpoints.element_size(), _ptr(gs), _ptr(gc), _ptr(gl), _ptr(gt),
+                         _ptr(ws), nbytes, _stream(stream))
+    _abi.check("bp_backward", st)
+    outs, off = [], 0
+    for c in costs:
+        outs.append(gc[off:off + c.numel()].view(c.shape))
+        off += c.numel()
+    return (outs[0] if single else outs), gl, gt
 
 
 def upsample(disp_lo: torch.Tensor, guide: torch.Tensor, sigma_s: float = 8.0, sigma_r: float = 12.0,

@@ -34,7 +34,7 @@ def _prob(w=16, h=8, L=8, cost=1):
 
 def _params(**kw):
     d = dict(levels=1, iters_per_level=4, lambda_=10.0, tau=2.0, msg_dtype=0, temperature=0.5,
-             checkpoint_every=0, variant=0)
+             checkpoint_every=0, variant=0, pm_from=-1)
     d.update(kw)
     return _abi.BpParams(**d)
 
@@ -59,6 +59,8 @@ def test_workspace_size_grows_and_rejects(lib):
     (dict(levels=0), _abi.BP_ERR_INVALID_ARGUMENT),
     (dict(iters_per_level=-1), _abi.BP_ERR_INVALID_ARGUMENT),
     (dict(msg_dtype=7), _abi.BP_ERR_INVALID_ARGUMENT),
+    (dict(pm_from=5), _abi.BP_ERR_INVALID_ARGUMENT),
+    (dict(pm_from=-2), _abi.BP_ERR_INVALID_ARGUMENT),
 ])
 def test_run_rejects_bad_params(lib, kw, expect):
     p = _params(**kw)

@@ -91,13 +91,13 @@ def test_downsample_exact(dev, shape):
 
 # ---------------------------------------------------------------- a3-a6, integer exactness
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
-def test_planes160_exact(dev, variant):
+@pytest.mark.parametrize("variant,pm_from", [(0, -1), (1, 1), (2, 1), (3, 1), (0, 0)])
+def test_planes160_exact(dev, variant, pm_from):
     w = workload("planes160x120_L32")
     cost = oracle.cost_volume(w["left"], w["right"], 32, 20.0)
     o = oracle_run(cost, 1, 10, 10.0, 2.0)
-    g = gpu_run(cost, dev, levels=1, iters=10, lam=10.0, tau=2.0, variant=variant)
-    assert_exact(g, o, f"variant {variant}")
+    g = gpu_run(cost, dev, levels=1, iters=10, lam=10.0, tau=2.0, variant=variant, pm_from=pm_from)
+    assert_exact(g, o, f"variant {variant} pm_from {pm_from}")
 
 
 @pytest.mark.parametrize("w,h,L,levels", [
@@ -108,9 +108,14 @@ def test_planes160_exact(dev, variant):
 def test_multilevel_exact(dev, w, h, L, levels):
     cost = int_cost(w, h, L, w * 7 + L)
     o = oracle_run(cost, levels, 6, 10.0, 2.0)
+    # Every label-major kernel variant, and every split between label-major
+    # and pixel-major levels.
     for variant in range(bp_mod().variant_count(L) + 1):
-        g = gpu_run(cost, dev, levels=levels, iters=6, lam=10.0, tau=2.0, variant=variant)
-        assert_exact(g, o, f"{w}x{h} L{L} n{levels} v{variant}")
+        g = gpu_run(cost, dev, levels=levels, iters=6, lam=10.0, tau=2.0, variant=variant, pm_from=levels)
+        assert_exact(g, o, f"{w}x{h} L{L} n{levels} v{variant} label-major")
+    for pm_from in range(levels):
+        g = gpu_run(cost, dev, levels=levels, iters=6, lam=10.0, tau=2.0, pm_from=pm_from)
+        assert_exact(g, o, f"{w}x{h} L{L} n{levels} pixel-major from {pm_from}")
 
 
 @pytest.mark.parametrize("K", [0, 1, 2, 3, 7])
@@ -118,8 +123,9 @@ def test_multilevel_exact(dev, w, h, L, levels):
 def test_iteration_counts_exact(dev, K, levels):
     cost = int_cost(41, 27, 32, 5)
     o = oracle_run(cost, levels, K, 10.0, 2.0)
-    g = gpu_run(cost, dev, levels=levels, iters=K, lam=10.0, tau=2.0)
-    assert_exact(g, o, f"K{K} n{levels}")
+    for pm_from in sorted({0, levels - 1, levels}):
+        g = gpu_run(cost, dev, levels=levels, iters=K, lam=10.0, tau=2.0, pm_from=pm_from)
+        assert_exact(g, o, f"K{K} n{levels} pm_from {pm_from}")
 
 
 @pytest.mark.parametrize("w,h", [(1, 1), (1, 9), (9, 1), (2, 2), (3, 5), (2, 7), (130, 1), (1, 70)])
@@ -128,16 +134,18 @@ def test_degenerate_grids_exact(dev, w, h):
     cost = rng.integers(0, 21, size=(16, h, w)).astype(np.float64)
     levels = 3 if min(w, h) > 1 else 2
     o = oracle_run(cost, levels, 5, 10.0, 2.0)
-    g = gpu_run(cost, dev, levels=levels, iters=5, lam=10.0, tau=2.0)
-    assert_exact(g, o, f"{w}x{h}")
+    for pm_from in (0, levels):
+        g = gpu_run(cost, dev, levels=levels, iters=5, lam=10.0, tau=2.0, pm_from=pm_from)
+        assert_exact(g, o, f"{w}x{h} pm_from {pm_from}")
 
 
 @pytest.mark.parametrize("lam,tau", [(0.0, 2.0), (10.0, 0.5), (3.0, 40.0), (1.0, 3.0)])
 def test_parameter_edges_exact(dev, lam, tau):
     cost = int_cost(50, 34, 32, 3)
     o = oracle_run(cost, 3, 6, lam, tau)
-    g = gpu_run(cost, dev, levels=3, iters=6, lam=lam, tau=tau)
-    assert_exact(g, o, f"lam {lam} tau {tau}")
+    for pm_from in (0, 3):
+        g = gpu_run(cost, dev, levels=3, iters=6, lam=lam, tau=tau, pm_from=pm_from)
+        assert_exact(g, o, f"lam {lam} tau {tau} pm_from {pm_from}")
 
 
 # ---------------------------------------------------------------- real-valued inputs
@@ -150,23 +158,24 @@ def real_case(w=96, h=64, L=64, seed=3):
     return cost
 
 
-@pytest.mark.parametrize("levels", [1, 3])
-def test_real_valued_tolerance(dev, levels):
+@pytest.mark.parametrize("levels,pm_from", [(1, 1), (3, 3), (1, 0), (3, 1)])
+def test_real_valued_tolerance(dev, levels, pm_from):
     lam, tau = 7.3, 2.6
     cost = real_case()
     o = oracle_run(cost, levels, 8, lam, tau)
-    g = gpu_run(cost, dev, levels=levels, iters=8, lam=lam, tau=tau)
+    g = gpu_run(cost, dev, levels=levels, iters=8, lam=lam, tau=tau, pm_from=pm_from)
     err = np.abs(g["msgs"].astype(np.float64) - o["msgs"]).max()
     assert err <= MSG_TOL_REL * lam * tau, err
     bad = (np.abs(g["disp"] - o["disp"]) > 1).mean()
     assert bad <= BAD_PIXEL_MAX, bad
 
 
-def test_soft_argmin(dev):
+@pytest.mark.parametrize("pm_from", [0, 1])
+def test_soft_argmin(dev, pm_from):
     lam, tau, T = 7.3, 2.6, 0.5
     cost = real_case(64, 48, 32, 9)
     o = oracle_run(cost, 1, 6, lam, tau, want_soft=True, temperature=T)
-    g = gpu_run(cost, dev, levels=1, iters=6, lam=lam, tau=tau, temperature=T, want_soft=True)
+    g = gpu_run(cost, dev, levels=1, iters=6, lam=lam, tau=tau, temperature=T, want_soft=True, pm_from=pm_from)
     # Soft-argmin of beliefs within 1e-4*lambda*tau of the oracle's; the
     # readout's label-space error is then bounded by L * that / T (loose).
     err = np.abs(g["soft"].astype(np.float64) - o["soft"]).max()
@@ -176,12 +185,13 @@ def test_soft_argmin(dev):
 
 # ---------------------------------------------------------------- precision form
 
+@pytest.mark.parametrize("pm_from", [0, 2, 4])
 @pytest.mark.parametrize("fmt,mode", [("f16", oracle.STORE_F16), ("bf16", oracle.STORE_BF16)])
-def test_16bit_messages_integer_exact(dev, fmt, mode):
+def test_16bit_messages_integer_exact(dev, fmt, mode, pm_from):
     cost = int_cost(88, 50, 64, 21)
     o = oracle_run(cost, 4, 6, 10.0, 2.0, store_mode=mode)
-    g = gpu_run(cost, dev, levels=4, iters=6, lam=10.0, tau=2.0, msg_dtype=fmt)
-    assert_exact(g, o, fmt)
+    g = gpu_run(cost, dev, levels=4, iters=6, lam=10.0, tau=2.0, msg_dtype=fmt, pm_from=pm_from)
+    assert_exact(g, o, f"{fmt} pm_from {pm_from}")
 
 
 @pytest.mark.parametrize("fmt,mode", [("f16", oracle.STORE_F16), ("bf16", oracle.STORE_BF16)])
@@ -190,12 +200,13 @@ def test_16bit_messages_real(dev, fmt, mode):
     cost = real_case(96, 64, 64, 5)
     o16 = oracle_run(cost, 3, 8, lam, tau, store_mode=mode)
     o64 = oracle_run(cost, 3, 8, lam, tau)
-    g = gpu_run(cost, dev, levels=3, iters=8, lam=lam, tau=tau, msg_dtype=fmt)
     ulp = 2.0 ** -10 if fmt == "f16" else 2.0 ** -7
-    err = np.abs(g["msgs"].astype(np.float64) - o16["msgs"]).max()
-    # Within a few storage ulps of the emulated-storage oracle.
-    assert err <= 8 * ulp * lam * tau, err
-    assert (np.abs(g["disp"] - o64["disp"]) > 1).mean() <= BAD_PIXEL_MAX
+    for pm_from in (0, 3):
+        g = gpu_run(cost, dev, levels=3, iters=8, lam=lam, tau=tau, msg_dtype=fmt, pm_from=pm_from)
+        err = np.abs(g["msgs"].astype(np.float64) - o16["msgs"]).max()
+        # Within a few storage ulps of the emulated-storage oracle.
+        assert err <= 8 * ulp * lam * tau, (pm_from, err)
+        assert (np.abs(g["disp"] - o64["disp"]) > 1).mean() <= BAD_PIXEL_MAX
 
 
 # ---------------------------------------------------------------- a7
@@ -232,6 +243,12 @@ def test_aerial_full_pipeline_exact(dev, aerial_full):
     right = torch.from_numpy(w["right"]).to(dev)
     c = bp.cost_volume(left, right, 64, 20.0, downsample=4)
     np.testing.assert_array_equal(c.cpu().numpy().astype(np.float64), cost)
+    for pm_from in (0, 5):
+        out = bp.run(c, bp.BPParams(levels=5, iters=10, lam=10.0, tau=2.0, pm_from=pm_from), want_msgs=True)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        assert_exact(g, o, f"aerial full pm_from {pm_from}")
+        del out, g
     out = bp.run(c, bp.BPParams(levels=5, iters=10, lam=10.0, tau=2.0), want_msgs=True)
     up = bp.upsample(out["disp"], left, 8.0, 12.0, -1)
     torch.cuda.synchronize()
