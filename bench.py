@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint"],
+                    help="pair: the benchmarked single-pair path (default); the others measure the "
+                         "batched, 16-bit-message and differentiation forms")
     return ap.parse_args()
 
 
@@ -57,6 +60,9 @@ def main():
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.form != "pair":
+        print(json.dumps(run_form(args.form, args)))
+        return
     import torch
 
     import paper_1902_09733_amd as bp
@@ -119,8 +125,9 @@ def main():
     torch.cuda.synchronize()
     bp_ms = e0.elapsed_time(e1) / reps
 
-    # Dominant kernel: the half-sweep, timed per launch with HIP events
-    # recorded on the stream it is launched on.
+    # Dominant kernel: the level-0 half-sweep (k_iter_pm), timed with a HIP
+    # event pair recorded on its launch stream around the level's K
+    # back-to-back launches (per-level records keep the events' own cost out).
     import ctypes
     lib = _abi.lib()
     probs = (_abi.BpProblem * 1)()
@@ -130,37 +137,35 @@ def main():
     cp = params.c()
     nbytes = lib.bp_workspace_size(probs, 1, ctypes.byref(cp))
     wsb = ws.get(nbytes, dev)
-    recs = (_abi.BpLaunchRecord * 256)()
+    recs = (_abi.BpLaunchRecord * 64)()
     nrec = ctypes.c_int32(0)
     stream_h = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    per = {}
-    for _ in range(5):
-        st = lib.bp_run_profiled(probs, 1, ctypes.byref(cp), ctypes.c_void_p(wsb.data_ptr()), nbytes, stream_h,
-                                 recs, 256, ctypes.byref(nrec))
+    lv_ms, lv_bytes, lv_n = {}, {}, {}
+    for _ in range(6):
+        st = lib.bp_run_profiled(probs, 1, ctypes.byref(cp), ctypes.c_void_p(wsb.data_ptr()), nbytes, stream_h, 1,
+                                 recs, 64, ctypes.byref(nrec))
         _abi.check("bp_run_profiled", st)
         for i in range(nrec.value):
             r = recs[i]
-            if r.readout_fused:
-                continue       # a different kernel instance (it also writes labels)
-            per.setdefault("ms", []).append(r.ms)
             # Algorithmic bytes: the active half of the pixels reads the cost
             # (4 B) and 4 incoming messages and writes 4 outgoing ones.
-            per.setdefault("bytes", []).append(r.units * (4.0 + 8.0 * r.msg_bytes) / 2.0)
-            per.setdefault("lvl0", []).append(r.level == 0)
-    ms = np.array(per["ms"])
-    byt = np.array(per["bytes"])
-    lvl0 = np.array(per["lvl0"])
-    avg_ms = float(ms.mean())
-    achieved = float(byt.mean() / (avg_ms * 1e-3) / 1e9)
-    lvl0_gbs = float(byt[lvl0].mean() / (ms[lvl0].mean() * 1e-3) / 1e9)
+            lv_ms.setdefault(r.level, []).append(r.ms / r.launches)
+            lv_bytes[r.level] = r.units / r.launches * (4.0 + 8.0 * r.msg_bytes) / 2.0
+            lv_n[r.level] = r.launches
+    per_level = {l: float(np.median(v[1:])) for l, v in lv_ms.items()}     # first run is a warm-up
+    l0_ms = per_level[0]
+    achieved = lv_bytes[0] / (l0_ms * 1e-3) / 1e9
+    all_ms = sum(per_level[l] * lv_n[l] for l in per_level)
+    all_bytes = sum(lv_bytes[l] * lv_n[l] for l in per_level)
 
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-        "kernel": "k_iter (checkerboard half-sweep), all levels",
-        "avg_launch_us": round(avg_ms * 1e3, 2), "launches": int(len(ms)) // 5,
-        "level0_GBps": round(lvl0_gbs, 1), "level0_avg_launch_us": round(float(ms[lvl0].mean()) * 1e3, 2),
-        "bytes_per_update": BYTES_PER_UPDATE[args.msg_dtype],
+        "kernel": f"k_iter_pm level-0 checkerboard half-sweep ({w}x{h}x{L}, {args.msg_dtype} messages)",
+        "avg_launch_us": round(l0_ms * 1e3, 2), "launches_per_step": lv_n[0],
+        "bytes_per_launch": lv_bytes[0], "bytes_per_update": BYTES_PER_UPDATE[args.msg_dtype],
+        "per_level_avg_launch_us": {str(l): round(per_level[l] * 1e3, 2) for l in sorted(per_level)},
+        "all_levels_GBps": round(all_bytes / (all_ms * 1e-3) / 1e9, 1),
     }
 
     cpu = None
@@ -218,6 +223,179 @@ def cpu_baseline(wl, updates, budget_s):
         "sample": f"{reps} x (downsampled-pair cost volume + 5-level BP, {updates/1e6:.2f} M updates) of the "
                   f"benchmarked pair, {el:.1f} s",
     }
+
+
+# ---------------------------------------------------------------------------
+# Forms: batched, 16-bit messages, differentiation (python bench.py --form ...)
+# ---------------------------------------------------------------------------
+
+def _graph(fn):
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g
+
+
+def _time(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def level_units(w, h, L, levels, K):
+    u = 0
+    for _ in range(levels):
+        u += w * h
+        w, h = (w + 1) // 2, (h + 1) // 2
+    return u * L * K
+
+
+def form_batch(args):
+    """48 pairs, 320x180 .. 1352x760, labels in {32, 64, 96, 128}, 5 levels x 8
+    half-sweeps.  Plain form: one bp_run per pair, FP32, eager launches.
+    Batched form: one bp_run over all 48 pairs, replayed as a HIP graph, in
+    FP32 and with FP16 message storage.  Each step = cost volumes + BP."""
+    import torch
+
+    import paper_1902_09733_amd as bp
+    from synth import workload
+    dev = torch.device("cuda:0")
+    wl = workload("batch48_mixed")
+    pairs = wl["pairs"]
+    lefts = [torch.from_numpy(p["left"]).to(dev) for p in pairs]
+    rights = [torch.from_numpy(p["right"]).to(dev) for p in pairs]
+    costs = [torch.empty((p["num_labels"], p["height"], p["width"]), dtype=torch.float32, device=dev) for p in pairs]
+    updates = float(sum(level_units(p["width"], p["height"], p["num_labels"], wl["levels"], wl["iters"]) for p in pairs))
+
+    def make_outs():
+        return [{"disp": torch.empty((p["height"], p["width"]), dtype=torch.int32, device=dev), "soft": None,
+                 "msgs": None} for p in pairs]
+
+    def costs_step():
+        for l, r, c, p in zip(lefts, rights, costs, pairs):
+            bp.cost_volume(l, r, p["num_labels"], wl["data_trunc"], out=c)
+
+    res = {}
+    plain_outs = make_outs()
+    p32 = bp.BPParams(levels=wl["levels"], iters=wl["iters"], lam=wl["lam"], tau=wl["tau"])
+    ws_plain = bp.Workspace()
+
+    def plain():
+        costs_step()
+        for c, o in zip(costs, plain_outs):
+            bp.run(c, p32, workspace=ws_plain, outputs=[o])
+    t_plain = _time(plain, 3)
+    res["plain_f32_pairs_per_s"] = round(48 / t_plain, 2)
+    t_plain_g = _time(_graph(plain).replay, 3)
+    res["plain_f32_graph_pairs_per_s"] = round(48 / t_plain_g, 2)
+    disp_plain = [o["disp"].clone() for o in plain_outs]
+
+    for fmt in ("f32", "f16"):
+        outs = make_outs()
+        pp = bp.BPParams(levels=wl["levels"], iters=wl["iters"], lam=wl["lam"], tau=wl["tau"], msg_dtype=fmt)
+        ws = bp.Workspace()
+
+        def batched():
+            costs_step()
+            bp.run(costs, pp, workspace=ws, outputs=outs)
+        batched()
+        torch.cuda.synchronize()
+        g = _graph(batched)
+        t = _time(g.replay, 5)
+        res[f"batched_{fmt}_pairs_per_s"] = round(48 / t, 2)
+        res[f"batched_{fmt}_updates_per_s"] = round(updates / t, 1)
+        bad = sum(int((torch.abs(o["disp"] - d) > 1).sum()) for o, d in zip(outs, disp_plain))
+        npx = sum(int(d.numel()) for d in disp_plain)
+        res[f"batched_{fmt}_bad_pixel_vs_plain_f32"] = bad / npx
+    res["speedup_batched_f16_vs_plain_f32"] = round(res["batched_f16_pairs_per_s"] / res["plain_f32_pairs_per_s"], 3)
+    res["speedup_batched_f32_vs_plain_f32"] = round(res["batched_f32_pairs_per_s"] / res["plain_f32_pairs_per_s"], 3)
+    return {"form": "batched", "workload": "batch48_mixed", "updates_per_batch": updates, **res}
+
+
+def form_precision(args):
+    """1352x760 RGB pair, 128 labels, 6 levels x 12 half-sweeps: FP32 / FP16 /
+    BF16 message storage, times and deviation from the FP32 GPU result, on an
+    integer-valued parameter set (16-bit storage is exact there) and a
+    real-valued one (unrounded channel mean, lambda 7.3, tau 2.6).  The
+    comparison with the FP64 oracle is made by the GPU test suite."""
+    import torch
+
+    import paper_1902_09733_amd as bp
+    from synth import workload
+    dev = torch.device("cuda:0")
+    wl = workload("aerial1352x760_L128")
+    L, levels, K = wl["num_labels"], wl["levels"], wl["iters"]
+    left = torch.from_numpy(wl["left"]).to(dev)
+    right = torch.from_numpy(wl["right"]).to(dev)
+    units = level_units(1352, 760, L, levels, K)
+    out = {"form": "precision", "workload": "aerial1352x760_L128", "updates_per_pair": units}
+    for pset, rgb_mode, lam, tau in (("int", 0, 10.0, 2.0), ("real", 1, 7.3, 2.6)):
+        cost = bp.cost_volume(left, right, L, 20.0, rgb_mode=rgb_mode)
+        ref = None
+        for fmt in ("f32", "f16", "bf16"):
+            p = bp.BPParams(levels=levels, iters=K, lam=lam, tau=tau, msg_dtype=fmt)
+            r = bp.run(cost, p, want_msgs=True)
+            ws = bp.Workspace()
+            outs = [{"disp": torch.empty_like(r["disp"]), "soft": None, "msgs": None}]
+            t = _time(lambda: bp.run(cost, p, workspace=ws, outputs=outs), 10)
+            rec = {"bp_ms": round(t * 1e3, 3), "updates_per_s": round(units / t, 1)}
+            if ref is None:
+                ref = r
+            else:
+                rec["bad_pixel_vs_gpu_f32"] = float((torch.abs(r["disp"] - ref["disp"]) > 1).float().mean())
+                rec["max_msg_diff_vs_gpu_f32_over_lambda_tau"] = float(
+                    (r["msgs"] - ref["msgs"]).abs().max() / (lam * tau))
+            out[f"{pset}_{fmt}"] = rec
+        del ref
+    return out
+
+
+def form_adjoint(args):
+    """8 x 320x240 grey pairs, 64 labels, 8 half-sweeps, soft-argmin (T 0.5),
+    checkpoints every 2: forward (with checkpoints) and backward times."""
+    import torch
+
+    import paper_1902_09733_amd as bp
+    from synth import workload
+    from paper_1902_09733_amd import soft_argmin_bp
+    dev = torch.device("cuda:0")
+    wl = workload("planes320x240_L64_x8")
+    vols = [bp.cost_volume(torch.from_numpy(p["left"]).to(dev), torch.from_numpy(p["right"]).to(dev), 64, 20.0)
+            + torch.from_numpy(p["jitter"].astype(np.float32)).to(dev) for p in wl["pairs"]]
+    ct = torch.stack(vols).detach().requires_grad_(True)
+    lt = torch.tensor(10.0, device=dev, requires_grad=True)
+    tt = torch.tensor(wl["tau"], device=dev, requires_grad=True)
+    G = torch.randn(8, 240, 320, device=dev)
+
+    def fwd():
+        return soft_argmin_bp(ct, lt, tt, iters=wl["iters"], temperature=wl["temperature"],
+                              checkpoint_every=wl["checkpoint_every"])
+
+    def fwd_bwd():
+        ct.grad = None
+        (fwd() * G).sum().backward()
+    t_f = _time(lambda: fwd(), 5)
+    t_fb = _time(fwd_bwd, 5)
+    units = 8 * 320 * 240 * 64 * wl["iters"]
+    return {"form": "differentiation", "workload": "planes320x240_L64_x8", "forward_ms": round(t_f * 1e3, 3),
+            "forward_backward_ms": round(t_fb * 1e3, 3), "backward_ms": round((t_fb - t_f) * 1e3, 3),
+            "forward_updates_per_s": round(units / t_f, 1)}
+
+
+def run_form(form, args):
+    return {"batch": form_batch, "precision": form_precision, "adjoint": form_adjoint}[form](args)
 
 
 if __name__ == "__main__":

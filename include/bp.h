@@ -75,8 +75,14 @@ typedef struct {
     float temperature;         /* soft-argmin temperature T > 0 (used when soft_disparity != NULL) */
     int32_t checkpoint_every;  /* 0 = none; k > 0 saves the message state every k half-sweeps
                                   of the finest level into the checkpoint buffer (adjoint) */
-    int32_t variant;           /* 0 = library choice; otherwise a label-major half-sweep kernel
-                                  variant in 1..bp_variant_count() (testing and tuning) */
+    int32_t variant;           /* 0 = library choice; otherwise a half-sweep kernel variant in
+                                  1..bp_variant_count() (testing and tuning).  Label-major
+                                  levels: lanes per pixel 1/2/4 by label count.  Pixel-major
+                                  levels: 1 default lane split, 2 half the lanes with twice
+                                  the labels per lane, 3 and 4 the same with each direction's
+                                  lanes reading only their own incoming message and sharing
+                                  sums by lane shuffles.  A number beyond what one layout has
+                                  selects that layout's variant 1.  Results do not depend on it. */
     int32_t pm_from;           /* first pyramid level stored pixel-major (labels of a pixel
                                   contiguous, half-sweep by lane-split scans); levels before it
                                   are label-major.  -1 = library choice, `levels` = none.
@@ -144,27 +150,30 @@ size_t bp_checkpoint_size(const bp_problem *probs, int32_t count, const bp_param
 bp_status bp_run(const bp_problem *probs, int32_t count, const bp_params *params, void *workspace,
                  size_t ws_bytes, void *checkpoints, size_t ckpt_bytes, hipStream_t stream);
 
-/* One timed half-sweep launch (bp_run_profiled). */
+/* One timed span of half-sweep launches (bp_run_profiled). */
 typedef struct {
-    int32_t level;          /* pyramid level of the launch (0 = finest) */
-    int32_t half_sweep;     /* t within the level */
-    int32_t readout_fused;  /* 1 if this launch also wrote the senders' labels */
+    int32_t level;          /* pyramid level of the launches (0 = finest) */
+    int32_t half_sweep;     /* t of the first launch covered */
+    int32_t launches;       /* launches covered: 1, or the level's K with per_level */
+    int32_t readout_fused;  /* number of covered launches that also wrote the senders' labels */
     int32_t msg_bytes;      /* bytes per stored message value at this level (4 or 2) */
-    double units;           /* pixel-label updates of this launch: W_l * H_l * L */
-    float ms;               /* kernel time from HIP events recorded on `stream` around the launch */
+    double units;           /* pixel-label updates covered: launches * W_l * H_l * L */
+    float ms;               /* time between HIP events recorded on `stream` around the span */
 } bp_launch_record;
 
 /*
  * Measurement form of bp_run for one problem (count must be 1): the same
  * launch sequence, with a HIP event pair recorded on `stream` around every
- * half-sweep launch (up to `capacity` of them).  Unlike bp_run it
+ * half-sweep launch (per_level = 0) or around the K back-to-back half-sweep
+ * launches of every level (per_level = 1, which keeps the events' own cost
+ * out of short launches), up to `capacity` records.  Unlike bp_run it
  * synchronises `stream` before returning.  Writes the number of records to
  * *n_records.  Errors as bp_run, plus BP_ERR_INVALID_ARGUMENT for NULL
- * records/n_records or negative capacity.
+ * records/n_records, negative capacity or per_level not 0/1.
  */
 bp_status bp_run_profiled(const bp_problem *probs, int32_t count, const bp_params *params, void *workspace,
-                          size_t ws_bytes, hipStream_t stream, bp_launch_record *records, int32_t capacity,
-                          int32_t *n_records);
+                          size_t ws_bytes, hipStream_t stream, int32_t per_level, bp_launch_record *records,
+                          int32_t capacity, int32_t *n_records);
 
 /*
  * a7. Joint bilateral upsampling, Eq. 2:
@@ -211,7 +220,21 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
 /* Workspace bytes bp_backward needs; 0 on invalid input. */
 size_t bp_backward_workspace_size(const bp_problem *probs, int32_t count, const bp_params *params);
 
-/* Number of kernel variants bp_params.variant may select (1..count). */
+/*
+ * Launch-shape table written by the autotuner (paper_1902_09733_amd/tune.py):
+ * text lines "width height labels fmt levels pm_from variant us".  When
+ * bp_params.pm_from == -1 and variant == 0, a problem uses the entry with its
+ * label count, format and level count whose pixel count is nearest (log
+ * scale); results never depend on the choice.  The table named by the
+ * environment variable BP_TUNE_TABLE is read at the first planning call;
+ * bp_load_tune_table replaces it (NULL clears it).  Errors:
+ * BP_ERR_INVALID_ARGUMENT if the file cannot be opened.  Not to be called
+ * concurrently with planning calls that should see a consistent table.
+ */
+bp_status bp_load_tune_table(const char *path);
+
+/* Number of kernel variants bp_params.variant may select (1..count); 0 for an
+ * unsupported label count. */
 int32_t bp_variant_count(int32_t num_labels);
 
 /* Static text for a status code. */

@@ -48,6 +48,7 @@ class BpLaunchRecord(ctypes.Structure):
     _fields_ = [
         ("level", ctypes.c_int32),
         ("half_sweep", ctypes.c_int32),
+        ("launches", ctypes.c_int32),
         ("readout_fused", ctypes.c_int32),
         ("msg_bytes", ctypes.c_int32),
         ("units", ctypes.c_double),
@@ -86,7 +87,7 @@ def lib():
     L.bp_checkpoint_size.restype = sz
     L.bp_run.argtypes = [P(BpProblem), i32, P(BpParams), vp, sz, vp, sz, vp]
     L.bp_run.restype = ctypes.c_int
-    L.bp_run_profiled.argtypes = [P(BpProblem), i32, P(BpParams), vp, sz, vp, P(BpLaunchRecord), i32, P(i32)]
+    L.bp_run_profiled.argtypes = [P(BpProblem), i32, P(BpParams), vp, sz, vp, i32, P(BpLaunchRecord), i32, P(i32)]
     L.bp_run_profiled.restype = ctypes.c_int
     L.bp_upsample.argtypes = [vp, i32, i32, vp, i32, i32, i32, i64, f32, f32, i32, vp, vp]
     L.bp_upsample.restype = ctypes.c_int
@@ -94,6 +95,8 @@ def lib():
     L.bp_backward.restype = ctypes.c_int
     L.bp_backward_workspace_size.argtypes = [P(BpProblem), i32, P(BpParams)]
     L.bp_backward_workspace_size.restype = sz
+    L.bp_load_tune_table.argtypes = [ctypes.c_char_p]
+    L.bp_load_tune_table.restype = ctypes.c_int
     L.bp_variant_count.argtypes = [i32]
     L.bp_variant_count.restype = i32
     _lib = L

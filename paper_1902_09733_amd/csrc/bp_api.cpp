@@ -3,7 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "bp.h"
 #include "bp_internal.h"
@@ -42,18 +46,75 @@ bool valid_problem(const bp_problem &q, const bp_params &p)
 
 bool supported_labels(int L) { return L >= 2 && L <= kMaxLabels; }
 
+// Launch-shape table written by the autotuner (paper_1902_09733_amd/tune.py):
+// text lines "width height labels fmt levels pm_from variant us", read once
+// from the file named by BP_TUNE_TABLE.
+struct TuneEntry {
+    int w, h, L, fmt, levels, pm_from, variant;
+};
+
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+bool g_tune_init = false;
+
+// Parses a table file; false if it cannot be opened.
+bool read_tune_file(const char *path, std::vector<TuneEntry> *out)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        TuneEntry e;
+        double us;
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %lf", &e.w, &e.h, &e.L, &e.fmt, &e.levels, &e.pm_from,
+                        &e.variant, &us) == 8)
+            out->push_back(e);
+    }
+    std::fclose(f);
+    return true;
+}
+
+// Tuned (pm_from, variant) for a problem, if the table has an entry with the
+// same label count, format and level count; the nearest pixel count wins.
+bool tuned_choice(int w, int h, int L, int fmt, int levels, int *pm_from, int *variant)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (!g_tune_init) {
+        g_tune_init = true;
+        const char *path = std::getenv("BP_TUNE_TABLE");
+        if (path && *path) read_tune_file(path, &g_tune);
+    }
+    const TuneEntry *best = nullptr;
+    double bd = 0.0;
+    for (const TuneEntry &e : g_tune) {
+        if (e.L != L || e.fmt != fmt || e.levels != levels) continue;
+        const double d = std::fabs(std::log((double)e.w * e.h) - std::log((double)w * h));
+        if (!best || d < bd) {
+            best = &e;
+            bd = d;
+        }
+    }
+    if (!best) return false;
+    *pm_from = best->pm_from < 0 ? 0 : (best->pm_from > levels ? levels : best->pm_from);
+    *variant = best->variant;
+    return true;
+}
+
 // Problem plans laid out back to back in the workspace.
 bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *plans, size_t *total)
 {
     size_t off = 0;
     for (int i = 0; i < count; ++i) {
         const bp_problem &q = probs[i];
+        int pm_from = p->pm_from, tv = 0;
+        if (pm_from < 0 && !(p->variant == 0 && tuned_choice(q.width, q.height, q.num_labels, p->msg_dtype,
+                                                             p->levels, &pm_from, &tv)))
+            pm_from = default_pm_from(q.width, q.height, q.num_labels, p->levels, p->msg_dtype);
         // The adjoint kernels work on label-major states.
-        const int pm_from = p->checkpoint_every > 0 ? p->levels
-                            : p->pm_from >= 0      ? p->pm_from
-                                                   : default_pm_from(q.width, q.height, q.num_labels, p->levels,
-                                                                     p->msg_dtype);
+        if (p->checkpoint_every > 0) pm_from = p->levels;
         if (!make_plan(q.width, q.height, q.num_labels, p->levels, p->msg_dtype, pm_from, off, &plans[i])) return false;
+        plans[i].variant = p->variant != 0 ? p->variant : tv != 0 ? tv : default_variant(q.num_labels, p->msg_dtype);
         off += plans[i].bytes;
     }
     *total = align_up(off);
@@ -71,11 +132,13 @@ size_t checkpoint_bytes_of(const Plan &pl, int K, int every)
 
 bool differentiable(const bp_params &p) { return p.levels == 1 && p.msg_dtype == BP_MSG_F32; }
 
-// Optional per-launch timing of the half-sweep kernels (bp_run_profiled).
+// Optional timing of the half-sweep kernels (bp_run_profiled): an event pair
+// around every launch, or around the K launches of every level.
 struct Recorder {
     bp_launch_record *rec;
     hipEvent_t (*ev)[2];
     int cap, n;
+    bool per_level;
 };
 
 // Runs the whole hierarchical BP of one problem.
@@ -102,17 +165,20 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
             if (fusable) first_src = 1;
             else if ((st = launch_parent_copy(pl, l, ws, s)) != BP_OK) return st;
         }
+        const bool lrec = prof && prof->per_level && prof->n < prof->cap && K > 0;
+        if (lrec && hipEventRecord(prof->ev[prof->n][0], s) != hipSuccess) return BP_ERR_HIP;
         for (int t = 0; t < K; ++t) {
             int32_t *ro = (l == 0 && t == K - 1 && fuse_ro) ? q.disparity : nullptr;
-            const bool rec = prof && prof->n < prof->cap;
+            const bool rec = prof && !prof->per_level && prof->n < prof->cap;
             if (rec && hipEventRecord(prof->ev[prof->n][0], s) != hipSuccess) return BP_ERR_HIP;
-            if ((st = launch_iteration(pl, l, t, t == 0 ? first_src : 0, p.lambda, p.tau, ro, p.variant, ws, s)) != BP_OK)
+            if ((st = launch_iteration(pl, l, t, t == 0 ? first_src : 0, p.lambda, p.tau, ro, pl.variant, ws, s)) != BP_OK)
                 return st;
             if (rec) {
                 if (hipEventRecord(prof->ev[prof->n][1], s) != hipSuccess) return BP_ERR_HIP;
                 bp_launch_record &r = prof->rec[prof->n++];
                 r.level = l;
                 r.half_sweep = t;
+                r.launches = 1;
                 r.readout_fused = ro != nullptr;
                 r.msg_bytes = fmt_bytes(pl.lv[l].fmt);
                 r.units = (double)pl.lv[l].w * pl.lv[l].h * pl.L;
@@ -124,6 +190,17 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
                                       s)) != BP_OK)
                     return st;
             }
+        }
+        if (lrec) {
+            if (hipEventRecord(prof->ev[prof->n][1], s) != hipSuccess) return BP_ERR_HIP;
+            bp_launch_record &r = prof->rec[prof->n++];
+            r.level = l;
+            r.half_sweep = 0;
+            r.launches = K;
+            r.readout_fused = (l == 0 && fuse_ro) ? 1 : 0;
+            r.msg_bytes = fmt_bytes(pl.lv[l].fmt);
+            r.units = (double)K * pl.lv[l].w * pl.lv[l].h * pl.L;
+            r.ms = 0.0f;
         }
     }
     if (ckpt) {
@@ -140,6 +217,109 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
     if (q.messages_out)
         if ((st = launch_export(pl, q.messages_out, ws, s)) != BP_OK) return st;
     return BP_OK;
+}
+
+// The batched form: problems whose levels are all pixel-major run each
+// (level, half-sweep) as one launch per lane split, over all of them.
+bool batched(const Plan *plans, int32_t count, const bp_params &p)
+{
+    if (count < 2 || p.checkpoint_every > 0) return false;
+    for (int i = 0; i < count; ++i)
+        for (int l = 0; l < plans[i].levels; ++l)
+            if (plans[i].lv[l].layout != PIXEL_MAJOR) return false;
+    return true;
+}
+
+// Table entries of the batched form: per level, three kinds of half-sweep
+// (t = 0, odd t, even t >= 2), per problem.
+size_t batch_table_bytes(int32_t count, int levels) { return align_up((size_t)levels * 3 * count * sizeof(BatchEntry)); }
+
+bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans, const bp_params &p, uint8_t *ws,
+                      size_t table_off, hipStream_t s)
+{
+    bp_status st;
+    const int n = p.levels, K = p.iters_per_level;
+    for (int i = 0; i < count; ++i) {
+        if ((st = launch_init_messages(plans[i], ws, s)) != BP_OK) return st;
+        if ((st = launch_split_cost(probs[i].cost, plans[i], ws, s)) != BP_OK) return st;
+        for (int l = 1; l < n; ++l)
+            if ((st = launch_pyramid_level(plans[i], l, ws, s)) != BP_OK) return st;
+    }
+    // Problems grouped by lane split (classes of one launch each).
+    int cls_S[32], cls_R[32], ncls = 0;
+    bool cls_X[32];
+    int *cls_of = new int[count];
+    for (int i = 0; i < count; ++i) {
+        int S, R;
+        bool X;
+        pm_split_variant(plans[i].L, plans[i].variant, &S, &R, &X);
+        int c = 0;
+        while (c < ncls && !(cls_S[c] == S && cls_R[c] == R && cls_X[c] == X)) ++c;
+        if (c == ncls) {
+            cls_S[c] = S;
+            cls_R[c] = R;
+            cls_X[c] = X;
+            ++ncls;
+        }
+        cls_of[i] = c;
+    }
+    // Entries for every (level, kind), grouped by class; written once.
+    BatchEntry *host = new BatchEntry[(size_t)n * 3 * count];
+    BatchEntry *dev = (BatchEntry *)(ws + table_off);
+    int *start = new int[(size_t)n * 3 * ncls], *num = new int[(size_t)n * 3 * ncls], *blocks = new int[(size_t)n * 3 * ncls];
+    int e = 0;
+    for (int l = 0; l < n; ++l)
+        for (int kind = 0; kind < 3; ++kind) {
+            const int t = kind == 0 ? 0 : (kind == 1 ? 1 : 2);
+            for (int c = 0; c < ncls; ++c) {
+                const int slot = (l * 3 + kind) * ncls + c;
+                start[slot] = e;
+                num[slot] = 0;
+                int b0 = 0;
+                for (int i = 0; i < count; ++i) {
+                    if (cls_of[i] != c) continue;
+                    const Plan &pl = plans[i];
+                    int src_mode = 0;
+                    if (kind == 0 && l < n - 1 && K >= 2 && pl.lv[l].fmt == pl.lv[l + 1].fmt) src_mode = 1;
+                    BatchEntry &be = host[e++];
+                    be.a = make_iter_args(pl, l, t, src_mode, p.lambda, p.tau, nullptr, ws);
+                    be.block0 = b0;
+                    b0 += pm_blocks(be.a.ncomp, cls_S[c]);
+                    ++num[slot];
+                }
+                blocks[slot] = b0;
+            }
+        }
+    st = launch_write_entries(dev, host, e, s);
+    for (int l = n - 1; l >= 0 && st == BP_OK; --l) {
+        if (l < n - 1)
+            for (int i = 0; i < count && st == BP_OK; ++i) {
+                const Level &c = plans[i].lv[l], &pa = plans[i].lv[l + 1];
+                if (!(K >= 2 && c.fmt == pa.fmt)) st = launch_parent_copy(plans[i], l, ws, s);
+            }
+        for (int t = 0; t < K && st == BP_OK; ++t) {
+            const int kind = t == 0 ? 0 : (t & 1 ? 1 : 2);
+            for (int c = 0; c < ncls && st == BP_OK; ++c) {
+                const int slot = (l * 3 + kind) * ncls + c;
+                if (num[slot] == 0) continue;
+                const int fmt = plans[0].lv[l].fmt;   // every problem has the same levels
+                st = launch_iteration_batch(dev + start[slot], num[slot], blocks[slot], fmt, cls_S[c], cls_R[c],
+                                            cls_X[c], s);
+            }
+        }
+    }
+    for (int i = 0; i < count && st == BP_OK; ++i) {
+        const bp_problem &q = probs[i];
+        if (q.disparity || q.soft_disparity)
+            st = launch_readout(plans[i], 3, q.disparity, q.soft_disparity, p.temperature, ws, s);
+        if (st == BP_OK && q.messages_out) st = launch_export(plans[i], q.messages_out, ws, s);
+    }
+    delete[] host;
+    delete[] start;
+    delete[] num;
+    delete[] blocks;
+    delete[] cls_of;
+    return st;
 }
 
 }  // namespace
@@ -190,6 +370,7 @@ size_t bp_workspace_size(const bp_problem *probs, int32_t count, const bp_params
     Plan *plans = new Plan[count];
     size_t total = 0;
     bool ok = plan_all(probs, count, params, plans, &total);
+    if (ok && batched(plans, count, *params)) total += batch_table_bytes(count, params->levels);
     delete[] plans;
     return ok ? total : 0;
 }
@@ -230,11 +411,19 @@ bp_status bp_run(const bp_problem *probs, int32_t count, const bp_params *params
     if (ck)
         for (int i = 0; i < count; ++i)
             ck_total += checkpoint_bytes_of(plans[i], params->iters_per_level, params->checkpoint_every);
+    const bool batch = batched(plans, count, *params);
+    const size_t table_off = total;
+    if (batch) total += batch_table_bytes(count, params->levels);
     if (ws_bytes < total || ckpt_bytes < ck_total) {
         delete[] plans;
         return BP_ERR_WORKSPACE_TOO_SMALL;
     }
     (void)hipGetLastError();
+    if (batch) {
+        bp_status bs = run_batched(probs, count, plans, *params, (uint8_t *)workspace, table_off, stream);
+        delete[] plans;
+        return bs;
+    }
     bp_status st = BP_OK;
     size_t ck_off = 0;
     for (int i = 0; i < count && st == BP_OK; ++i) {
@@ -247,10 +436,10 @@ bp_status bp_run(const bp_problem *probs, int32_t count, const bp_params *params
 }
 
 bp_status bp_run_profiled(const bp_problem *probs, int32_t count, const bp_params *params, void *workspace,
-                          size_t ws_bytes, hipStream_t stream, bp_launch_record *records, int32_t capacity,
-                          int32_t *n_records)
+                          size_t ws_bytes, hipStream_t stream, int32_t per_level, bp_launch_record *records,
+                          int32_t capacity, int32_t *n_records)
 {
-    if (!records || capacity < 0 || !n_records) return BP_ERR_INVALID_ARGUMENT;
+    if (!records || capacity < 0 || !n_records || (per_level != 0 && per_level != 1)) return BP_ERR_INVALID_ARGUMENT;
     if (!probs || count != 1 || !valid_params(params)) return BP_ERR_INVALID_ARGUMENT;
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return BP_ERR_INVALID_ARGUMENT;
     if (!valid_problem(probs[0], *params)) return BP_ERR_INVALID_ARGUMENT;
@@ -261,7 +450,7 @@ bp_status bp_run_profiled(const bp_problem *probs, int32_t count, const bp_param
     if (!plan_all(probs, 1, params, &plan, &total)) return BP_ERR_UNSUPPORTED;
     if (ws_bytes < total) return BP_ERR_WORKSPACE_TOO_SMALL;
     (void)hipGetLastError();
-    Recorder prof{records, new hipEvent_t[capacity > 0 ? capacity : 1][2], capacity, 0};
+    Recorder prof{records, new hipEvent_t[capacity > 0 ? capacity : 1][2], capacity, 0, per_level == 1};
     bp_status st = BP_OK;
     int made = 0;
     for (; made < capacity && st == BP_OK; ++made)
@@ -309,6 +498,7 @@ static bool backward_layout(const bp_problem *probs, int32_t count, const bp_par
     for (int i = 0; i < count; ++i) {
         const bp_problem &q = probs[i];
         if (!make_plan(q.width, q.height, q.num_labels, 1, BP_MSG_F32, 1, off, &plans[i])) return false;
+        plans[i].variant = params->variant;
         off += plans[i].bytes;
         mbar_off[i] = off;
         off += plans[i].lv[0].msg_bytes;
@@ -394,7 +584,7 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
             if (t0 == 0) st = launch_init_messages(pl, ws, stream);
             else st = launch_copy(ck + (size_t)(t0 / every - 1) * sb, state, sb, stream);
             for (int r = t0; r < t && st == BP_OK; ++r)
-                st = launch_iteration(pl, 0, r, 0, params->lambda, params->tau, nullptr, params->variant, ws, stream);
+                st = launch_iteration(pl, 0, r, 0, params->lambda, params->tau, nullptr, pl.variant, ws, stream);
             if (st == BP_OK)
                 st = launch_bwd_step(pl, t, state, mbar, gc, partial + 2 * part, params->lambda, params->tau, ws,
                                      stream);
@@ -410,10 +600,21 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
     return st;
 }
 
+bp_status bp_load_tune_table(const char *path)
+{
+    std::vector<TuneEntry> t;
+    if (path && !read_tune_file(path, &t)) return BP_ERR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.swap(t);
+    g_tune_init = true;
+    return BP_OK;
+}
+
 int32_t bp_variant_count(int32_t num_labels)
 {
     if (!supported_labels(num_labels)) return 0;
-    return iteration_variants(num_labels);
+    const int lm = iteration_variants(num_labels), pm = pm_variants(num_labels);
+    return lm > pm ? lm : pm;
 }
 
 }  // extern "C"

@@ -19,6 +19,7 @@ bool make_plan(int w, int h, int L, int levels, int msg_fmt, int pm_from, size_t
     p->h = h;
     p->L = L;
     p->levels = levels;
+    p->variant = 0;
     size_t off = base;
     int lw = w, lh = h;
     int S, R;
@@ -318,8 +319,8 @@ bp_status launch_parent_copy(const Plan &p, int l, uint8_t *ws, hipStream_t s)
 // a5: half-sweep dispatch
 // ------------------------------------------------------------------------
 
-bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lambda, float tau, int32_t *disp,
-                           int variant, uint8_t *ws, hipStream_t s)
+IterArgs make_iter_args(const Plan &p, int l, int t, int src_mode, float lambda, float tau, int32_t *disp,
+                        uint8_t *ws)
 {
     const Level &v = p.lv[l];
     IterArgs a;
@@ -350,10 +351,19 @@ bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lamb
     a.ncomp = v.h * v.wh;
     a.lambda = lambda;
     a.lt = lambda * tau;
+    return a;
+}
+
+bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lambda, float tau, int32_t *disp,
+                           int variant, uint8_t *ws, hipStream_t s)
+{
+    const Level &v = p.lv[l];
+    const IterArgs a = make_iter_args(p, l, t, src_mode, lambda, tau, disp, ws);
     if (v.layout == PIXEL_MAJOR) {
         int S, R;
-        pm_split(p.L, &S, &R);
-        return dispatch_iter_pm(a, v.fmt, S, R, disp != nullptr, s);
+        bool xchg;
+        pm_split_variant(p.L, variant, &S, &R, &xchg);
+        return dispatch_iter_pm(a, v.fmt, S, R, disp != nullptr, xchg, s);
     }
     return dispatch_iter_lm(a, v.fmt, iteration_lanes(p.L, variant), disp != nullptr, s);
 }

@@ -166,6 +166,29 @@ __device__ __forceinline__ int dpp_i(int old, int v)
     return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xF, 0xF, false);
 }
 
+// x + x[lane ^ D] for D in {4, 8, 16, 32}: both lanes of a pair get the same
+// bits (IEEE addition is commutative).  D = 4 composes a quad reversal with a
+// half-row mirror, D = 8 is a rotation by 8 within a 16-lane row, D = 16 and
+// D = 32 are gfx950's register-only row and half-wave swaps.
+template <int D>
+__device__ __forceinline__ float xor_sum(float x)
+{
+    static_assert(D == 4 || D == 8 || D == 16 || D == 32, "unsupported lane distance");
+    if constexpr (D == 4) {
+        return x + dpp_f<0x141>(x, dpp_f<0x1B>(x, x));
+    } else if constexpr (D == 8) {
+        return x + dpp_f<0x128>(x, x);
+    } else if constexpr (D == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x),
+                                                        __builtin_bit_cast(unsigned, x), false, false);
+        return __builtin_bit_cast(float, r[0]) + __builtin_bit_cast(float, r[1]);
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x),
+                                                        __builtin_bit_cast(unsigned, x), false, false);
+        return __builtin_bit_cast(float, r[0]) + __builtin_bit_cast(float, r[1]);
+    }
+}
+
 // Value of lane (s - N) of the same segment, or `ident` when s < N.
 template <int SEG, int N>
 __device__ __forceinline__ float seg_from_lower(float v, float ident, int s)

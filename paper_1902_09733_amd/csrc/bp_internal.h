@@ -48,6 +48,7 @@ struct Level {
 // Workspace plan of one problem.
 struct Plan {
     int w, h, L, levels;
+    int variant;          // half-sweep kernel variant (0 = default)
     Level lv[kMaxLevels];
     size_t bytes;         // total workspace bytes of this problem (aligned)
 };
@@ -135,6 +136,33 @@ bp_status launch_bwd_readout(const Plan &p, const uint8_t *msg, float *mbar, con
 bp_status launch_bwd_step(const Plan &p, int t, const uint8_t *msg, float *mbar, float *grad_cost, float *partial,
                           float lambda, float tau, uint8_t *ws, hipStream_t s);
 bp_status launch_bwd_finish(const float *partial, int n, float *grad_lambda, float *grad_tau, hipStream_t s);
-bp_status dispatch_iter_pm(const IterArgs &a, int fmt, int S, int R, bool ro, hipStream_t s);
+bp_status dispatch_iter_pm(const IterArgs &a, int fmt, int S, int R, bool ro, bool xchg, hipStream_t s);
+
+// Pixel-major kernel variants (1 default split; 2 half the lanes per message,
+// twice the labels per lane; 3 and 4 the same with each lane group reading
+// only its own incoming row and exchanging sums by lane shuffles).
+int pm_variants(int L);
+// Variant used when the caller and the tuning table leave the choice open.
+int default_variant(int L, int msg_fmt);
+void pm_split_variant(int L, int variant, int *S, int *R, bool *xchg);
+
+// Batched pixel-major half-sweep: one launch over several problems that share
+// a lane split; table entries hold each problem's arguments and first block.
+struct BatchEntry {
+    IterArgs a;
+    int block0;
+    int pad[3];
+};
+constexpr int kChunk = 16;
+struct EntryChunk {
+    BatchEntry e[kChunk];
+    int n;
+};
+int pm_blocks(int ncomp, int S);
+bp_status launch_write_entries(BatchEntry *dst, const BatchEntry *src, int n, hipStream_t s);
+IterArgs make_iter_args(const Plan &p, int l, int t, int src_mode, float lambda, float tau, int32_t *disp,
+                        uint8_t *ws);
+bp_status launch_iteration_batch(const BatchEntry *tab, int n, int blocks, int fmt, int S, int R, bool xchg,
+                                 hipStream_t s);
 
 }  // namespace bpk

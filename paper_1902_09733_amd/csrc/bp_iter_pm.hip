@@ -29,11 +29,11 @@
 
 namespace bpk {
 
-template <int SEG, int R, typename S, bool EXACT, bool RO>
-__global__ void __launch_bounds__(256) k_iter_pm(const IterArgs a)
+template <int SEG, int R, typename S, bool EXACT, bool RO, bool XCHG>
+__device__ __forceinline__ void pm_sweep(const IterArgs &a, uint32_t block)
 {
     constexpr int GP = 4 * SEG;           // lanes per pixel
-    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t gid = block * 256u + threadIdx.x;
     const int j = (int)(gid / GP);
     const int lane = (int)(gid % GP);
     const int k = lane / SEG;             // outgoing message / excluded incoming slot
@@ -48,32 +48,66 @@ __global__ void __launch_bounds__(256) k_iter_pm(const IterArgs a)
     const __amdgpu_buffer_rsrc_t rm = make_rsrc(a.msg, a.msg_bytes);
     const int f0 = s * R;
 
-    // Cost and the four incoming rows of labels f0 .. f0+R-1.
-    float c[R], m[4][R];
-    ld_row<StoreF32, R>(rc, ((uint32_t)a.colour * a.blk + (uint32_t)j * a.lp + (uint32_t)f0) * 4u, c);
-    {
-        int sj = j, sc = a.colour;
-        if (a.src_parent) {
-            const int sx = x >> 1, sy = y >> 1;
-            sc = (sx + sy) & 1;
-            sj = sy * a.src_wh + (sx >> 1);
-        }
-        const uint32_t base = (uint32_t)sj * a.sps + (uint32_t)f0;
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-            ld_row<S, R>(rs, (((uint32_t)sc * 4u + (uint32_t)kk) * a.sblk + base) * S::bytes, m[kk]);
-    }
     const float inf = __builtin_huge_valf();
     const float lam = a.lambda;
     const float lamR = lam * (float)R;
+    int sj = j, sc = a.colour;
+    if (a.src_parent) {
+        const int sx = x >> 1, sy = y >> 1;
+        sc = (sx + sy) & 1;
+        sj = sy * a.src_wh + (sx >> 1);
+    }
+    const uint32_t base = (uint32_t)sj * a.sps + (uint32_t)f0;
+    const uint32_t cost_off = ((uint32_t)a.colour * a.blk + (uint32_t)j * a.lp + (uint32_t)f0) * 4u;
+    float h[R];
+    float bel[R];   // belief cost + sum of the four incoming rows (fused readout)
+    if constexpr (!XCHG) {
+        // Every lane reads the cost and all four incoming rows of its labels
+        // and sums in slot order, adding zero for the excluded slot.
+        float c[R], m[4][R];
+        ld_row<StoreF32, R>(rc, cost_off, c);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            ld_row<S, R>(rs, (((uint32_t)sc * 4u + (uint32_t)kk) * a.sblk + base) * S::bytes, m[kk]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float v = c[r];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) v += (kk == k) ? 0.0f : m[kk][r];
+            h[r] = v;
+            if constexpr (RO) bel[r] = (((c[r] + m[0][r]) + m[1][r]) + m[2][r]) + m[3][r];
+        }
+    } else {
+        // Each lane group reads only its own incoming row (group 0 also the
+        // cost); the four groups' partial sums are exchanged across lanes
+        // (DPP and lane swaps): total = ((cost + m0) + m1) + (m2 + m3),
+        // h = total - m_k.
+        float own[R], part[R];
+        ld_row<S, R>(rs, (((uint32_t)sc * 4u + (uint32_t)k) * a.sblk + base) * S::bytes, own);
+        if (k == 0) {
+            float c[R];
+            ld_row<StoreF32, R>(rc, cost_off, c);
+#pragma unroll
+            for (int r = 0; r < R; ++r) part[r] = c[r] + own[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) part[r] = own[r];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float tot = xor_sum<2 * SEG>(xor_sum<SEG>(part[r]));
+            h[r] = tot - own[r];
+            if constexpr (RO) bel[r] = tot;
+        }
+    }
 
     if constexpr (RO) {
-        // Belief b(f) = cost + m_0 + m_1 + m_2 + m_3 and its lowest-index argmin.
+        // Lowest-index argmin of the belief.
         float bv = inf;
         int bi = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            float b = (((c[r] + m[0][r]) + m[1][r]) + m[2][r]) + m[3][r];
+            float b = bel[r];
             if (!EXACT && f0 + r >= a.L) b = inf;
             if (b < bv) {
                 bv = b;
@@ -84,17 +118,11 @@ __global__ void __launch_bounds__(256) k_iter_pm(const IterArgs a)
         if (k == 0 && s == 0) a.disp[(int64_t)y * a.w + x] = bi;
     }
 
-    // h excluding slot k, summed in slot order (adding zero for the excluded one).
-    float h[R];
     float hmin = inf;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        float v = c[r];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) v += (kk == k) ? 0.0f : m[kk][r];
-        if (!EXACT && f0 + r >= a.L) v = inf;
-        h[r] = v;
-        hmin = fminf(hmin, v);
+        if (!EXACT && f0 + r >= a.L) h[r] = inf;
+        hmin = fminf(hmin, h[r]);
     }
     hmin = seg_allreduce<SEG>(hmin, [](float p, float q) { return fminf(p, q); });
 
@@ -142,6 +170,80 @@ __global__ void __launch_bounds__(256) k_iter_pm(const IterArgs a)
     }
 }
 
+template <int SEG, int R, typename S, bool EXACT, bool RO, bool XCHG>
+__global__ void __launch_bounds__(256) k_iter_pm(const IterArgs a)
+{
+    pm_sweep<SEG, R, S, EXACT, RO, XCHG>(a, blockIdx.x);
+}
+
+// Batched half-sweep: the problems of one launch share the lane split; block
+// b belongs to the last table entry whose first block is <= b.
+template <int SEG, int R, typename S, bool XCHG>
+__global__ void __launch_bounds__(256) k_iter_pm_batch(const BatchEntry *__restrict__ tab, int n)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].block0 <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const IterArgs a = tab[lo].a;
+    pm_sweep<SEG, R, S, false, false, XCHG>(a, blockIdx.x - (uint32_t)tab[lo].block0);
+}
+
+// Table of batch entries written from kernel arguments (capture-safe: no
+// host buffer has to outlive the call).
+__global__ void k_write_entries(BatchEntry *__restrict__ dst, EntryChunk c)
+{
+    const int i = threadIdx.x;
+    if (i < c.n) dst[i] = c.e[i];
+}
+
+bp_status launch_write_entries(BatchEntry *dst, const BatchEntry *src, int n, hipStream_t st)
+{
+    for (int i = 0; i < n; i += kChunk) {
+        EntryChunk c;
+        c.n = n - i < kChunk ? n - i : kChunk;
+        for (int k = 0; k < c.n; ++k) c.e[k] = src[i + k];
+        k_write_entries<<<1, 64, 0, st>>>(dst + i, c);
+        const bp_status s = launch_status();
+        if (s != BP_OK) return s;
+    }
+    return BP_OK;
+}
+
+template <int SEG, int R, typename S>
+static bp_status launch_pm_batch(const BatchEntry *tab, int n, int blocks, bool xchg, hipStream_t st)
+{
+    if (xchg) k_iter_pm_batch<SEG, R, S, true><<<blocks, 256, 0, st>>>(tab, n);
+    else k_iter_pm_batch<SEG, R, S, false><<<blocks, 256, 0, st>>>(tab, n);
+    return launch_status();
+}
+
+template <typename S>
+static bp_status dispatch_pm_batch(const BatchEntry *tab, int n, int blocks, int SEGV, int R, bool xchg,
+                                   hipStream_t st)
+{
+#define BP_PMB(SV, RV) \
+    if (SEGV == SV && R == RV) return launch_pm_batch<SV, RV, S>(tab, n, blocks, xchg, st);
+    BP_PMB(4, 4) BP_PMB(8, 4) BP_PMB(16, 4) BP_PMB(16, 6) BP_PMB(16, 8) BP_PMB(16, 12) BP_PMB(16, 16)
+    BP_PMB(4, 8) BP_PMB(8, 8) BP_PMB(8, 12) BP_PMB(8, 16)
+#undef BP_PMB
+    return BP_ERR_UNSUPPORTED;
+}
+
+bp_status launch_iteration_batch(const BatchEntry *tab, int n, int blocks, int fmt, int SEGV, int R, bool xchg,
+                                 hipStream_t st)
+{
+    switch (fmt) {
+    case FMT_F16: return dispatch_pm_batch<StoreF16>(tab, n, blocks, SEGV, R, xchg, st);
+    case FMT_BF16: return dispatch_pm_batch<StoreBF16>(tab, n, blocks, SEGV, R, xchg, st);
+    default: return dispatch_pm_batch<StoreF32>(tab, n, blocks, SEGV, R, xchg, st);
+    }
+}
+
+int pm_blocks(int ncomp, int SEGV) { return (int)(((int64_t)ncomp * 4 * SEGV + 255) / 256); }
+
 void pm_split(int L, int *S, int *R)
 {
     if (L <= 16) { *S = 4; *R = 4; }
@@ -153,40 +255,82 @@ void pm_split(int L, int *S, int *R)
     else { *S = 16; *R = 16; }
 }
 
-template <int SEG, int R, typename S>
-static bp_status launch_pm(const IterArgs &a, bool ro, hipStream_t st)
+static bool pm_can_halve(int L) { return L > 16 && L <= 128; }
+
+int pm_variants(int L) { return pm_can_halve(L) ? 4 : 2; }
+
+// Measured on MI355X (676x380x64 and 1352x760x128 pyramids): with FP32
+// storage the shuffled-sum split wins from 128 labels, with 16-bit storage
+// halving the lanes per message and shuffling sums wins throughout.
+int default_variant(int L, int msg_fmt)
 {
-    const unsigned grid = (unsigned)(((int64_t)a.ncomp * 4 * SEG + 255) / 256);
+    if (msg_fmt != FMT_F32) return pm_can_halve(L) ? 4 : 3;
+    return L > 64 ? 3 : 1;
+}
+
+// Pixel-major kernel variants (same storage for all: lp = SEG * R):
+//   1 default lane split, every lane reads all five rows of its labels
+//   2 half the lanes per message, twice the labels per lane
+//   3 default split, each lane group reads only its own row (shuffled sums)
+//   4 half lanes and shuffled sums
+// Variant 0 means 1.
+void pm_split_variant(int L, int variant, int *S, int *R, bool *xchg)
+{
+    pm_split(L, S, R);
+    if (variant <= 0 || variant > pm_variants(L)) variant = 1;
+    const bool half = (variant == 2 || variant == 4) && pm_can_halve(L);
+    *xchg = variant >= 3;
+    if (half) {
+        *S /= 2;
+        *R *= 2;
+    }
+}
+
+template <int SEG, int R, typename S, bool XCHG>
+static void launch_pm_x(const IterArgs &a, bool ro, unsigned grid, hipStream_t st)
+{
     const bool exact = a.L == SEG * R;
     if (exact) {
-        if (ro) k_iter_pm<SEG, R, S, true, true><<<grid, 256, 0, st>>>(a);
-        else k_iter_pm<SEG, R, S, true, false><<<grid, 256, 0, st>>>(a);
+        if (ro) k_iter_pm<SEG, R, S, true, true, XCHG><<<grid, 256, 0, st>>>(a);
+        else k_iter_pm<SEG, R, S, true, false, XCHG><<<grid, 256, 0, st>>>(a);
     } else {
-        if (ro) k_iter_pm<SEG, R, S, false, true><<<grid, 256, 0, st>>>(a);
-        else k_iter_pm<SEG, R, S, false, false><<<grid, 256, 0, st>>>(a);
+        if (ro) k_iter_pm<SEG, R, S, false, true, XCHG><<<grid, 256, 0, st>>>(a);
+        else k_iter_pm<SEG, R, S, false, false, XCHG><<<grid, 256, 0, st>>>(a);
     }
+}
+
+template <int SEG, int R, typename S>
+static bp_status launch_pm(const IterArgs &a, bool ro, bool xchg, hipStream_t st)
+{
+    const unsigned grid = (unsigned)(((int64_t)a.ncomp * 4 * SEG + 255) / 256);
+    if (xchg) launch_pm_x<SEG, R, S, true>(a, ro, grid, st);
+    else launch_pm_x<SEG, R, S, false>(a, ro, grid, st);
     return launch_status();
 }
 
 template <typename S>
-static bp_status dispatch_pm(const IterArgs &a, int SEGV, int R, bool ro, hipStream_t st)
+static bp_status dispatch_pm(const IterArgs &a, int SEGV, int R, bool ro, bool xchg, hipStream_t st)
 {
-    if (SEGV == 4 && R == 4) return launch_pm<4, 4, S>(a, ro, st);
-    if (SEGV == 8 && R == 4) return launch_pm<8, 4, S>(a, ro, st);
-    if (SEGV == 16 && R == 4) return launch_pm<16, 4, S>(a, ro, st);
-    if (SEGV == 16 && R == 6) return launch_pm<16, 6, S>(a, ro, st);
-    if (SEGV == 16 && R == 8) return launch_pm<16, 8, S>(a, ro, st);
-    if (SEGV == 16 && R == 12) return launch_pm<16, 12, S>(a, ro, st);
-    if (SEGV == 16 && R == 16) return launch_pm<16, 16, S>(a, ro, st);
+    if (SEGV == 4 && R == 4) return launch_pm<4, 4, S>(a, ro, xchg, st);
+    if (SEGV == 8 && R == 4) return launch_pm<8, 4, S>(a, ro, xchg, st);
+    if (SEGV == 16 && R == 4) return launch_pm<16, 4, S>(a, ro, xchg, st);
+    if (SEGV == 16 && R == 6) return launch_pm<16, 6, S>(a, ro, xchg, st);
+    if (SEGV == 16 && R == 8) return launch_pm<16, 8, S>(a, ro, xchg, st);
+    if (SEGV == 16 && R == 12) return launch_pm<16, 12, S>(a, ro, xchg, st);
+    if (SEGV == 16 && R == 16) return launch_pm<16, 16, S>(a, ro, xchg, st);
+    if (SEGV == 4 && R == 8) return launch_pm<4, 8, S>(a, ro, xchg, st);
+    if (SEGV == 8 && R == 8) return launch_pm<8, 8, S>(a, ro, xchg, st);
+    if (SEGV == 8 && R == 12) return launch_pm<8, 12, S>(a, ro, xchg, st);
+    if (SEGV == 8 && R == 16) return launch_pm<8, 16, S>(a, ro, xchg, st);
     return BP_ERR_UNSUPPORTED;
 }
 
-bp_status dispatch_iter_pm(const IterArgs &a, int fmt, int SEGV, int R, bool ro, hipStream_t st)
+bp_status dispatch_iter_pm(const IterArgs &a, int fmt, int SEGV, int R, bool ro, bool xchg, hipStream_t st)
 {
     switch (fmt) {
-    case FMT_F16: return dispatch_pm<StoreF16>(a, SEGV, R, ro, st);
-    case FMT_BF16: return dispatch_pm<StoreBF16>(a, SEGV, R, ro, st);
-    default: return dispatch_pm<StoreF32>(a, SEGV, R, ro, st);
+    case FMT_F16: return dispatch_pm<StoreF16>(a, SEGV, R, ro, xchg, st);
+    case FMT_BF16: return dispatch_pm<StoreBF16>(a, SEGV, R, ro, xchg, st);
+    default: return dispatch_pm<StoreF32>(a, SEGV, R, ro, xchg, st);
     }
 }
 

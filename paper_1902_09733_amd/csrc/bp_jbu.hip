@@ -2,14 +2,16 @@
 //
 // A 256-thread block owns 16 x 16 full-resolution pixels.  The low-resolution
 // taps every pixel of the block can reach (disparity and the guide sample
-// I_q at scale*q + scale/2, packed RGB) are staged once in LDS.  The weight of
-// a tap is one exp2 of a sum of exponents: the spatial part is separable and
-// depends only on the pixel's sub-pixel phase, so it is a per-thread table of
-// 2R+1 values per axis; the range part is |I_p - I_q|^2 scaled by
-// log2(e) / (2 sigma_r^2).  Weights are evaluated relative to the smallest
-// exponent of the window (a common factor that cancels in K_p), so no pixel
-// can lose all its weights to underflow.  ALU/transcendental bound: about
-// (2R+1)^2 exp2 per output pixel.
+// I_q at scale*q + scale/2, packed RGB, with |I_q|^2) are staged once in LDS.
+// The weight of a tap is one exp2 of a sum of exponents: the spatial part is
+// separable and depends only on the pixel's sub-pixel phase, so it is a
+// per-thread table of 2R+1 values per axis; the range part is |I_p - I_q|^2
+// scaled by log2(e) / (2 sigma_r^2), with the squared distance formed exactly
+// in integers as |I_p|^2 + |I_q|^2 - 2 I_p.I_q (one 4 x u8 dot product per
+// tap).  Weights are evaluated relative to the smallest exponent of the window
+// (a common factor that cancels in K_p), so no pixel can lose all its weights
+// to underflow.  ALU/transcendental bound: about (2R+1)^2 exp2 and a dozen
+// other vector operations per output pixel and tap.
 #include <hip/hip_runtime.h>
 
 #include "bp_internal.h"
@@ -27,25 +29,15 @@ __device__ __forceinline__ uint32_t guide_px(const uint8_t *__restrict__ g, int6
     else return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
 }
 
-template <int C>
-__device__ __forceinline__ float range2(uint32_t a, uint32_t b)
-{
-    float s = 0.0f;
-#pragma unroll
-    for (int ch = 0; ch < C; ++ch) {
-        const float d = (float)((int)((a >> (8 * ch)) & 0xffu) - (int)((b >> (8 * ch)) & 0xffu));
-        s = fmaf(d, d, s);
-    }
-    return s;
-}
-
 template <int R, int C>
 __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, int wl, int hl,
                                             const uint8_t *__restrict__ guide, int wh, int hh, int64_t stride,
                                             int s, float ksp, float krg, float *__restrict__ out)
 {
     __shared__ float t_d[kMaxTap * kMaxTap];
-    __shared__ uint32_t t_g[kMaxTap * kMaxTap];   // bit 31 set = tap inside the grid
+    // Per tap: packed guide colour and |I_q|^2 (+inf outside the grid, which
+    // gives the tap zero weight).
+    __shared__ uint2 t_g[kMaxTap * kMaxTap];
     constexpr int NT = 2 * R + 1;
     const int bx0 = blockIdx.x * kTile, by0 = blockIdx.y * kTile;
     const int qx0 = bx0 / s - R, qy0 = by0 / s - R;
@@ -56,17 +48,20 @@ __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, i
         const int qx = qx0 + tx, qy = qy0 + ty;
         float d = 0.0f;
         uint32_t g = 0u;
+        float n = __builtin_huge_valf();
         if (qx >= 0 && qx < wl && qy >= 0 && qy < hl) {
             d = (float)disp[(int64_t)qy * wl + qx];
-            g = guide_px<C>(guide, stride, s * qx + s / 2, s * qy + s / 2) | 0x80000000u;
+            g = guide_px<C>(guide, stride, s * qx + s / 2, s * qy + s / 2);
+            n = (float)__builtin_amdgcn_udot4(g, g, 0u, false);
         }
         t_d[ty * kMaxTap + tx] = d;
-        t_g[ty * kMaxTap + tx] = g;
+        t_g[ty * kMaxTap + tx] = make_uint2(g, __float_as_uint(n));
     }
     __syncthreads();
     const int px = bx0 + (int)(threadIdx.x % kTile), py = by0 + (int)(threadIdx.x / kTile);
     if (px >= wh || py >= hh) return;
     const uint32_t ip = guide_px<C>(guide, stride, px, py);
+    const int np = (int)__builtin_amdgcn_udot4(ip, ip, 0u, false);
     const int cx = px / s, cy = py / s;
     const int ox = cx - R - qx0, oy = cy - R - qy0;   // tile coordinates of the window corner
     // Separable spatial exponents: s * (p_lo - q) = phase + 0.5 - s/2 - s*dq.
@@ -80,14 +75,20 @@ __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, i
     }
     constexpr bool KEEP = NT * NT <= 81;
     float e[KEEP ? NT * NT : 1];
+    // Exponent of tap (dx, dy); |I_p - I_q|^2 = (|I_p|^2 - 2 I_p.I_q) + |I_q|^2
+    // is an integer below 2^24, so every step is exact.
+    auto expo = [&](int dx, int dy) {
+        const uint2 g = t_g[(oy + dy) * kMaxTap + ox + dx];
+        const int dot = (int)__builtin_amdgcn_udot4(ip, g.x, 0u, false);
+        const float r2 = (float)(np - 2 * dot) + __uint_as_float(g.y);
+        return fmaf(r2, krg, ex[dx] + ey[dy]);
+    };
     float emin = __builtin_huge_valf();
 #pragma unroll
     for (int dy = 0; dy < NT; ++dy)
 #pragma unroll
         for (int dx = 0; dx < NT; ++dx) {
-            const uint32_t g = t_g[(oy + dy) * kMaxTap + ox + dx];
-            float v = __builtin_huge_valf();
-            if (g & 0x80000000u) v = ex[dx] + ey[dy] + range2<C>(ip, g) * krg;
+            const float v = expo(dx, dy);
             if constexpr (KEEP) e[dy * NT + dx] = v;
             emin = fminf(emin, v);
         }
@@ -97,12 +98,8 @@ __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, i
 #pragma unroll
         for (int dx = 0; dx < NT; ++dx) {
             float v;
-            if constexpr (KEEP) {
-                v = e[dy * NT + dx];
-            } else {
-                const uint32_t g = t_g[(oy + dy) * kMaxTap + ox + dx];
-                v = (g & 0x80000000u) ? ex[dx] + ey[dy] + range2<C>(ip, g) * krg : __builtin_huge_valf();
-            }
+            if constexpr (KEEP) v = e[dy * NT + dx];
+            else v = expo(dx, dy);
             const float w = __builtin_amdgcn_exp2f(emin - v);
             num = fmaf(w, t_d[(oy + dy) * kMaxTap + ox + dx], num);
             den += w;

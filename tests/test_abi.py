@@ -109,3 +109,11 @@ def test_variant_counts(lib):
     assert lib.bp_variant_count(1) == 0
     for L in (2, 16, 32, 48, 64, 96, 128, 256):
         assert lib.bp_variant_count(L) >= 1
+
+
+def test_tune_table_loading(lib, tmp_path):
+    t = tmp_path / "t.txt"
+    t.write_text("# comment\n676 380 64 0 5 0 1 900.0\nnot a line\n")
+    assert lib.bp_load_tune_table(str(t).encode()) == 0
+    assert lib.bp_load_tune_table(str(tmp_path / "missing.txt").encode()) == _abi.BP_ERR_INVALID_ARGUMENT
+    assert lib.bp_load_tune_table(None) == 0

@@ -70,8 +70,17 @@ def test_adjoint_matches_oracle_adjoint(dev, shape, K, every):
 
 
 def test_autograd_batch_matches_finite_differences(dev):
-    """The 8 x 320x240 x 64 batch: directional derivatives of a random
-    projection of the loss against FP64 central differences (eps = 1e-4)."""
+    """The 8 x 320x240 x 64 batch through the autograd.Function, against the
+    FP64 oracle adjoint, which is in turn checked against FP64 central
+    differences of the oracle's forward pass.
+
+    The loss is piecewise smooth, with kinks wherever a min-plus comparison
+    ties.  Over 20 M cost entries per pair a step of 1e-4 along a random
+    direction crosses many of them (the quotient moves by up to 30 %), and
+    even 1e-6 can straddle one (pair 6 of this workload, direction seed 100:
+    8 %).  The check therefore uses eps = 1e-7 per pair, where every quotient
+    of this workload agrees with the FP64 adjoint to 3e-7 relative; the 1e-4
+    quotient of the whole batch is printed for reference."""
     from paper_1902_09733_amd import soft_argmin_bp
     w = workload("planes320x240_L64_x8")
     K, lam, tau, T = w["iters"], 10.0, w["tau"], w["temperature"]
@@ -89,19 +98,44 @@ def test_autograd_batch_matches_finite_differences(dev):
     loss = (soft * torch.from_numpy(G.astype(np.float32)).to(dev)).sum()
     loss.backward()
     gC = ct.grad.double().cpu().numpy()
+    gl, gt = lt.grad.item(), tt.grad.item()
 
-    def ell(Cx, l=lam, t=tau):
-        return sum(float((G[i] * oracle.run(Cx[i], 1, K, l, t, want_soft=True, temperature=T)["soft"]).sum())
-                   for i in range(8))
-    eps = 1e-4
-    for d in range(3):
+    # FP64 oracle adjoint, pair by pair.
+    ogC = np.empty_like(C)
+    ogl = ogt = 0.0
+    for i in range(8):
+        _, ogC[i], a, b = oracle.backward(C[i], K, lam, tau, T, G[i])
+        ogl += a
+        ogt += b
+
+    # GPU against the FP64 adjoint.
+    scale = np.abs(ogC).max()
+    close = np.abs(gC - ogC) <= 1e-3 * scale + 1e-5
+    assert close.mean() >= 0.999, close.mean()
+    for d in range(2):
         V = np.random.default_rng(100 + d).normal(size=C.shape)
-        fd = (ell(C + eps * V) - ell(C - eps * V)) / (2 * eps)
-        an = float((gC * V).sum())
-        print(f"direction {d}: fd {fd:.6f} adjoint {an:.6f}", flush=True)
-        assert abs(fd - an) <= DIR_TOL * abs(fd), (fd, an)
-    fdl = (ell(C, lam + eps) - ell(C, lam - eps)) / (2 * eps)
-    fdt = (ell(C, lam, tau + eps) - ell(C, lam, tau - eps)) / (2 * eps)
-    print(f"lambda: fd {fdl:.6f} adjoint {lt.grad.item():.6f}; tau: fd {fdt:.6f} adjoint {tt.grad.item():.6f}")
-    assert abs(fdl - lt.grad.item()) <= DIR_TOL * abs(fdl)
-    assert abs(fdt - tt.grad.item()) <= DIR_TOL * abs(fdt)
+        an, oa = float((gC * V).sum()), float((ogC * V).sum())
+        print(f"direction {d}: gpu adjoint {an:.6f}  fp64 adjoint {oa:.6f}", flush=True)
+        assert abs(an - oa) <= DIR_TOL * abs(oa), (an, oa)
+    print(f"lambda: gpu {gl:.6f} fp64 {ogl:.6f}; tau: gpu {gt:.6f} fp64 {ogt:.6f}", flush=True)
+    assert abs(gl - ogl) <= DIR_TOL * abs(ogl), (gl, ogl)
+    assert abs(gt - ogt) <= DIR_TOL * abs(ogt), (gt, ogt)
+
+    # FP64 adjoint against central differences of the oracle forward.
+    def ell(i, Cx, l=lam, t=tau):
+        return float((G[i] * oracle.run(Cx, 1, K, l, t, want_soft=True, temperature=T)["soft"]).sum())
+    eps = 1e-7
+    for i in range(8):
+        V = np.random.default_rng(200 + i).normal(size=C.shape[1:])
+        fd = (ell(i, C[i] + eps * V) - ell(i, C[i] - eps * V)) / (2 * eps)
+        oa = float((ogC[i] * V).sum())
+        print(f"pair {i}: fd(1e-7) {fd:.6f} fp64 adjoint {oa:.6f}", flush=True)
+        assert abs(fd - oa) <= 1e-5 * abs(fd), (i, fd, oa)
+    fdl = sum(ell(i, C[i], lam + eps) - ell(i, C[i], lam - eps) for i in range(8)) / (2 * eps)
+    fdt = sum(ell(i, C[i], lam, tau + eps) - ell(i, C[i], lam, tau - eps) for i in range(8)) / (2 * eps)
+    print(f"lambda fd {fdl:.6f}; tau fd {fdt:.6f}", flush=True)
+    assert abs(fdl - ogl) <= 1e-5 * abs(fdl), (fdl, ogl)
+    assert abs(fdt - ogt) <= 1e-5 * abs(fdt), (fdt, ogt)
+    V = np.random.default_rng(100).normal(size=C.shape)
+    fd4 = sum(ell(i, C[i] + 1e-4 * V[i]) - ell(i, C[i] - 1e-4 * V[i]) for i in range(8)) / 2e-4
+    print(f"batch fd(1e-4) {fd4:.6f} (kink-polluted reference)", flush=True)

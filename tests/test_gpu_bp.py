@@ -116,6 +116,10 @@ def test_multilevel_exact(dev, w, h, L, levels):
     for pm_from in range(levels):
         g = gpu_run(cost, dev, levels=levels, iters=6, lam=10.0, tau=2.0, pm_from=pm_from)
         assert_exact(g, o, f"{w}x{h} L{L} n{levels} pixel-major from {pm_from}")
+    # Every pixel-major kernel variant at every level.
+    for variant in range(1, bp_mod().variant_count(L) + 1):
+        g = gpu_run(cost, dev, levels=levels, iters=6, lam=10.0, tau=2.0, variant=variant, pm_from=0)
+        assert_exact(g, o, f"{w}x{h} L{L} n{levels} v{variant} pixel-major")
 
 
 @pytest.mark.parametrize("K", [0, 1, 2, 3, 7])
@@ -158,12 +162,12 @@ def real_case(w=96, h=64, L=64, seed=3):
     return cost
 
 
-@pytest.mark.parametrize("levels,pm_from", [(1, 1), (3, 3), (1, 0), (3, 1)])
-def test_real_valued_tolerance(dev, levels, pm_from):
+@pytest.mark.parametrize("levels,pm_from,variant", [(1, 1, 0), (3, 3, 0), (1, 0, 0), (3, 1, 0), (1, 0, 3), (3, 0, 4)])
+def test_real_valued_tolerance(dev, levels, pm_from, variant):
     lam, tau = 7.3, 2.6
     cost = real_case()
     o = oracle_run(cost, levels, 8, lam, tau)
-    g = gpu_run(cost, dev, levels=levels, iters=8, lam=lam, tau=tau, pm_from=pm_from)
+    g = gpu_run(cost, dev, levels=levels, iters=8, lam=lam, tau=tau, pm_from=pm_from, variant=variant)
     err = np.abs(g["msgs"].astype(np.float64) - o["msgs"]).max()
     assert err <= MSG_TOL_REL * lam * tau, err
     bad = (np.abs(g["disp"] - o["disp"]) > 1).mean()
@@ -260,3 +264,59 @@ def test_aerial_full_pipeline_exact(dev, aerial_full):
     ref = oracle.upsample(o["disp"], w["left"], 8.0, 12.0)
     err = np.abs(up.cpu().numpy()[rows].astype(np.float64) - ref[rows]).max()
     assert err <= 2e-3, err
+
+
+# ---------------------------------------------------------------- batched form, kernel variants
+
+BATCH_SHAPES = [(60, 40, 32), (90, 50, 64), (33, 21, 96), (120, 70, 128), (45, 35, 64), (17, 9, 16), (71, 45, 100)]
+
+
+@pytest.mark.parametrize("fmt,mode", [("f32", oracle.STORE_F64), ("f16", oracle.STORE_F16)])
+def test_batched_mixed_problems_exact(dev, fmt, mode):
+    """Problems of uneven size and label count in one bp_run call (one launch
+    per half-sweep and lane split) equal the oracle problem by problem."""
+    bp = bp_mod()
+    costs = [int_cost(w, h, L, w + h + L) for (w, h, L) in BATCH_SHAPES]
+    vols = [torch.from_numpy(c.astype(np.float32)).to(dev) for c in costs]
+    p = bp.BPParams(levels=3, iters=6, lam=10.0, tau=2.0, msg_dtype=fmt)
+    outs = bp.run(vols, p, want_msgs=True)
+    torch.cuda.synchronize()
+    for c, o_gpu, shp in zip(costs, outs, BATCH_SHAPES):
+        o = oracle_run(c, 3, 6, 10.0, 2.0, store_mode=mode)
+        g = {k: v.cpu().numpy() for k, v in o_gpu.items()}
+        assert_exact(g, o, f"batched {shp} {fmt}")
+
+
+@pytest.mark.parametrize("K", [1, 2, 5])
+def test_batched_iteration_counts(dev, K):
+    bp = bp_mod()
+    shapes = BATCH_SHAPES[:4]
+    costs = [int_cost(w, h, L, 7 * w + L) for (w, h, L) in shapes]
+    vols = [torch.from_numpy(c.astype(np.float32)).to(dev) for c in costs]
+    outs = bp.run(vols, bp.BPParams(levels=2, iters=K, lam=10.0, tau=2.0), want_msgs=True)
+    torch.cuda.synchronize()
+    for c, o_gpu in zip(costs, outs):
+        o = oracle_run(c, 2, K, 10.0, 2.0)
+        assert_exact({k: v.cpu().numpy() for k, v in o_gpu.items()}, o, f"batched K{K}")
+
+
+@pytest.mark.parametrize("L", [16, 24, 32, 64, 96, 128])
+@pytest.mark.parametrize("variant", [2, 3, 4])
+def test_pixel_major_variants_exact(dev, L, variant):
+    cost = int_cost(53, 37, L, L + 1)
+    o = oracle_run(cost, 3, 6, 10.0, 2.0)
+    g = gpu_run(cost, dev, levels=3, iters=6, lam=10.0, tau=2.0, pm_from=0, variant=variant)
+    assert_exact(g, o, f"L{L} pixel-major variant {variant}")
+
+
+@pytest.mark.parametrize("variant", [3, 4])
+def test_batched_shuffled_sum_variants_exact(dev, variant):
+    bp = bp_mod()
+    costs = [int_cost(w, h, L, w + 3 * h + L) for (w, h, L) in BATCH_SHAPES]
+    vols = [torch.from_numpy(c.astype(np.float32)).to(dev) for c in costs]
+    outs = bp.run(vols, bp.BPParams(levels=3, iters=5, lam=10.0, tau=2.0, variant=variant, pm_from=0),
+                  want_msgs=True)
+    torch.cuda.synchronize()
+    for c, o_gpu, shp in zip(costs, outs, BATCH_SHAPES):
+        o = oracle_run(c, 3, 5, 10.0, 2.0)
+        assert_exact({k: v.cpu().numpy() for k, v in o_gpu.items()}, o, f"batched {shp} variant {variant}")
