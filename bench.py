@@ -2,8 +2,10 @@
 """Benchmark of the stereo hot path on one MI355X.
 
 One step = the whole path for one synthetic aerial pair at 2.7K:
-  2704x1520 RGB u8 pair (resident in HBM) -> 4x block-mean downsampling fused
-  with the truncated absolute-difference cost volume [64][380][676] ->
+  2704x1520 RGB u8 pair (resident in HBM) -> 4x block-mean downsampling ->
+  truncated absolute-difference data term for 64 labels at 676x380, written
+  by bp_run straight into the finest level's colour-split layout (with
+  --volume: bp_cost_volume's planar [64][380][676] volume, then bp_run) ->
   5-level pyramid, 10 checkerboard half-sweeps per level, argmin readout ->
   joint bilateral upsampling to 2704x1520 (sigma_s 8 px, sigma_r 12).
 The timed steps replay one HIP graph of that launch sequence.
@@ -39,6 +41,8 @@ def parse():
     ap.add_argument("--msg-dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--volume", action="store_true",
+                    help="materialise the planar cost volume with bp_cost_volume inside the step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint"],
                     help="pair: the benchmarked single-pair path (default); the others measure the "
@@ -86,9 +90,16 @@ def main():
     ws = bp.Workspace()
     outs = [{"disp": disp, "soft": None, "msgs": None}]
 
+    pair = bp.Pair(left, right, L, wl["data_trunc"], downsample=S)
+    # The planar volume for the BP-only and per-level timings below.
+    bp.cost_volume(left, right, L, wl["data_trunc"], downsample=S, out=cost)
+
     def step():
-        bp.cost_volume(left, right, L, wl["data_trunc"], downsample=S, out=cost)
-        bp.run(cost, params, workspace=ws, outputs=outs)
+        if args.volume:
+            bp.cost_volume(left, right, L, wl["data_trunc"], downsample=S, out=cost)
+            bp.run(cost, params, workspace=ws, outputs=outs)
+        else:
+            bp.run(pair, params, workspace=ws, outputs=outs)
         bp.upsample(disp, left, wl["sigma_s"], wl["sigma_r"], -1, out=up)
 
     step()
@@ -191,6 +202,7 @@ def main():
             "labels": L, "levels": levels, "iters_per_level": K, "lambda": wl["lam"], "tau": wl["tau"],
             "data_trunc": wl["data_trunc"], "jbu_sigma_s": wl["sigma_s"], "jbu_sigma_r": wl["sigma_r"],
             "graph": not args.no_graph,
+            "cost_source": "planar volume (bp_cost_volume)" if args.volume else "pair, fused into bp_run",
         },
         "pairs_per_s": round(1e3 / ms_step, 2),
         "updates_per_step": updates,

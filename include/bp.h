@@ -53,6 +53,20 @@ typedef enum {
  * coarsest pyramid level always stores FP32. */
 typedef enum { BP_MSG_F32 = 0, BP_MSG_F16 = 1, BP_MSG_BF16 = 2 } bp_msg_dtype;
 
+/* A rectified pair from which bp_run computes the finest level's data term
+ * itself, straight into its internal layout (the planar volume is never
+ * stored).  The values are those bp_cost_volume writes for the same
+ * arguments; the pair's size is (width * downsample) x (height * downsample)
+ * with the bp_problem's width and height. */
+typedef struct {
+    const uint8_t *left, *right;   /* device images [height*downsample][row_stride_bytes] */
+    int32_t channels;              /* 1 = grey, 3 = RGB */
+    int32_t downsample;            /* s >= 1 */
+    int64_t row_stride_bytes;      /* >= width * downsample * channels */
+    float data_trunc;              /* >= 0 */
+    int32_t rgb_mode;              /* 0 rounded channel mean, 1 exact (bp_cost_volume) */
+} bp_pair;
+
 /* One rectified pair's BP problem at the matching (low) resolution. */
 typedef struct {
     int32_t width, height;     /* finest BP grid, >= 1 each */
@@ -63,6 +77,8 @@ typedef struct {
     float *messages_out;       /* [4][L][height][width] final finest-level messages, or NULL.
                                   Slot k = message received from the neighbour on side k
                                   (0 left, 1 right, 2 up, 3 down); 0 where there is none. */
+    const bp_pair *pair;       /* host pointer, read when cost == NULL (bp_run, bp_run_profiled,
+                                  bp_workspace_size); NULL otherwise */
 } bp_problem;
 
 /* Parameters of the method, shared by every problem of a call. */
@@ -117,7 +133,8 @@ bp_status bp_cost_volume(const uint8_t *left, const uint8_t *right, int32_t widt
 bp_status bp_downsample(const uint8_t *in, int32_t width, int32_t height, int32_t channels,
                         int64_t row_stride_bytes, int32_t downsample, uint8_t *out, hipStream_t stream);
 
-/* Workspace bytes bp_run needs for `count` problems with `params`; 0 on invalid input. */
+/* Workspace bytes bp_run needs for `count` problems with `params` (a problem
+ * without a cost volume must carry its valid pair); 0 on invalid input. */
 size_t bp_workspace_size(const bp_problem *probs, int32_t count, const bp_params *params);
 
 /* Checkpoint bytes bp_run writes when params->checkpoint_every > 0 (else 0). */
@@ -142,7 +159,7 @@ size_t bp_checkpoint_size(const bp_problem *probs, int32_t count, const bp_param
  * workspace device scratch of at least bp_workspace_size() bytes, 256-byte aligned
  * checkpoints device buffer of bp_checkpoint_size() bytes, or NULL when
  *           checkpoint_every == 0 (used by bp_backward)
- * Errors: BP_ERR_INVALID_ARGUMENT (bad sizes, NULL cost, lambda < 0,
+ * Errors: BP_ERR_INVALID_ARGUMENT (bad sizes, neither cost nor a valid pair, lambda < 0,
  * tau <= 0, soft output with T <= 0, misaligned workspace),
  * BP_ERR_UNSUPPORTED (label count outside [2, 256], 16-bit messages with
  * checkpointing), BP_ERR_WORKSPACE_TOO_SMALL, BP_ERR_HIP.

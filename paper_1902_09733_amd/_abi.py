@@ -18,6 +18,18 @@ BP_ERR_HIP = -4
 BP_MSG_F32, BP_MSG_F16, BP_MSG_BF16 = 0, 1, 2
 
 
+class BpPair(ctypes.Structure):
+    _fields_ = [
+        ("left", ctypes.c_void_p),
+        ("right", ctypes.c_void_p),
+        ("channels", ctypes.c_int32),
+        ("downsample", ctypes.c_int32),
+        ("row_stride_bytes", ctypes.c_int64),
+        ("data_trunc", ctypes.c_float),
+        ("rgb_mode", ctypes.c_int32),
+    ]
+
+
 class BpProblem(ctypes.Structure):
     _fields_ = [
         ("width", ctypes.c_int32),
@@ -27,6 +39,7 @@ class BpProblem(ctypes.Structure):
         ("disparity", ctypes.c_void_p),
         ("soft_disparity", ctypes.c_void_p),
         ("messages_out", ctypes.c_void_p),
+        ("pair", ctypes.POINTER(BpPair)),
     ]
 
 

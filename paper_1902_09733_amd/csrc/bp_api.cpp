@@ -36,9 +36,19 @@ bool valid_params(const bp_params *p)
     return true;
 }
 
+bool valid_pair(const bp_pair *pr, int w, int h)
+{
+    if (!pr || !pr->left || !pr->right || (pr->channels != 1 && pr->channels != 3) || pr->downsample < 1) return false;
+    if ((int64_t)w * pr->downsample > INT32_MAX || (int64_t)h * pr->downsample > INT32_MAX) return false;
+    if (pr->row_stride_bytes < (int64_t)w * pr->downsample * pr->channels) return false;
+    if (!(pr->data_trunc >= 0.0f) || !std::isfinite(pr->data_trunc)) return false;
+    return pr->rgb_mode == 0 || pr->rgb_mode == 1;
+}
+
 bool valid_problem(const bp_problem &q, const bp_params &p)
 {
-    if (q.width <= 0 || q.height <= 0 || !q.cost) return false;
+    if (q.width <= 0 || q.height <= 0) return false;
+    if (!q.cost && !valid_pair(q.pair, q.width, q.height)) return false;
     if (q.soft_disparity && !(p.temperature > 0.0f)) return false;
     // Every level keeps at least one pixel.
     return true;
@@ -114,6 +124,10 @@ bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
         // The adjoint kernels work on label-major states.
         if (p->checkpoint_every > 0) pm_from = p->levels;
         if (!make_plan(q.width, q.height, q.num_labels, p->levels, p->msg_dtype, pm_from, off, &plans[i])) return false;
+        if (!q.cost) {
+            plans[i].pair_off = off + plans[i].bytes;
+            plans[i].bytes += align_up((size_t)2 * q.width * q.height * sizeof(uint32_t));
+        }
         plans[i].variant = p->variant != 0 ? p->variant : tv != 0 ? tv : default_variant(q.num_labels, p->msg_dtype);
         off += plans[i].bytes;
     }
@@ -149,8 +163,10 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
     const int n = pl.levels, K = p.iters_per_level;
     // Out-of-grid slots of every level and the coarsest level's messages start at zero.
     if ((st = launch_init_messages(pl, ws, s)) != BP_OK) return st;
-    if ((st = launch_split_cost(q.cost, pl, ws, s)) != BP_OK) return st;
-    for (int l = 1; l < n; ++l)
+    int done = 1;
+    if ((st = q.cost ? launch_split_cost(q.cost, pl, ws, s) : launch_pair_cost(*q.pair, pl, ws, s, &done)) != BP_OK)
+        return st;
+    for (int l = done; l < n; ++l)
         if ((st = launch_pyramid_level(pl, l, ws, s)) != BP_OK) return st;
     // The finest level's last half-sweep also reads out its senders' labels.
     const bool fuse_ro = q.disparity && !q.soft_disparity && K >= 1;
@@ -241,8 +257,11 @@ bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans,
     const int n = p.levels, K = p.iters_per_level;
     for (int i = 0; i < count; ++i) {
         if ((st = launch_init_messages(plans[i], ws, s)) != BP_OK) return st;
-        if ((st = launch_split_cost(probs[i].cost, plans[i], ws, s)) != BP_OK) return st;
-        for (int l = 1; l < n; ++l)
+        int done = 1;
+        if ((st = probs[i].cost ? launch_split_cost(probs[i].cost, plans[i], ws, s)
+                                : launch_pair_cost(*probs[i].pair, plans[i], ws, s, &done)) != BP_OK)
+            return st;
+        for (int l = done; l < n; ++l)
             if ((st = launch_pyramid_level(plans[i], l, ws, s)) != BP_OK) return st;
     }
     // Problems grouped by lane split (classes of one launch each).
@@ -366,7 +385,9 @@ size_t bp_workspace_size(const bp_problem *probs, int32_t count, const bp_params
 {
     if (!probs || count < 1 || !valid_params(params)) return 0;
     for (int i = 0; i < count; ++i)
-        if (probs[i].width <= 0 || probs[i].height <= 0 || !supported_labels(probs[i].num_labels)) return 0;
+        if (probs[i].width <= 0 || probs[i].height <= 0 || !supported_labels(probs[i].num_labels) ||
+            (!probs[i].cost && !valid_pair(probs[i].pair, probs[i].width, probs[i].height)))
+            return 0;
     Plan *plans = new Plan[count];
     size_t total = 0;
     bool ok = plan_all(probs, count, params, plans, &total);

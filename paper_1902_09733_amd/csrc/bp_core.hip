@@ -20,6 +20,7 @@ bool make_plan(int w, int h, int L, int levels, int msg_fmt, int pm_from, size_t
     p->L = L;
     p->levels = levels;
     p->variant = 0;
+    p->pair_off = 0;
     size_t off = base;
     int lw = w, lh = h;
     int S, R;

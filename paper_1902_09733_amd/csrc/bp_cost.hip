@@ -1,10 +1,15 @@
 // a1 + a2 on gfx950: optional s x s block-mean downsampling of the rectified
 // pair fused with the truncated absolute-difference data term of Eq. 1.
 //
-// One 256-thread block produces one output row segment of 256 pixels for all
-// labels: the downsampled left pixels of the segment and the right pixels it
-// can match (segment start - (L-1) .. end) are computed once into LDS, then
-// every label plane is written with coalesced 1 KB row stores.
+// bp_cost_volume: one 256-thread block produces one output row segment of 256
+// pixels for all labels: the downsampled left pixels of the segment and the
+// right pixels it can match (segment start - (L-1) .. end) are computed once
+// into LDS, then every label plane is written with coalesced 1 KB row stores.
+//
+// bp_run from a pair: the downsampled pair is first packed (one 32-bit word
+// per pixel) into the workspace, then the data term is written straight into
+// the finest level's colour-split layout (pixel-major or label-major), so the
+// planar volume never exists.
 #include <hip/hip_runtime.h>
 
 #include "bp_internal.h"
@@ -30,6 +35,23 @@ __device__ __forceinline__ uint32_t pixel_ds(const uint8_t *__restrict__ img, in
 }
 
 constexpr int kSeg = 256;
+
+// Data term of Eq. 1 for packed left/right pixels lv, rv (label d with x - d >= 0).
+template <int C>
+__device__ __forceinline__ float ad_cost(uint32_t lv, uint32_t rv, int rgb_mode, float trunc)
+{
+    float a;
+    if constexpr (C == 1) {
+        a = (float)abs((int)lv - (int)rv);
+    } else {
+        int sum = 0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+            sum += abs((int)((lv >> (8 * ch)) & 0xffu) - (int)((rv >> (8 * ch)) & 0xffu));
+        a = rgb_mode == 0 ? (float)((sum + 1) / 3) : (float)sum / 3.0f;
+    }
+    return fminf(a, trunc);
+}
 
 template <int C>
 __global__ void __launch_bounds__(256) k_cost(const uint8_t *__restrict__ left, const uint8_t *__restrict__ right,
@@ -57,21 +79,7 @@ __global__ void __launch_bounds__(256) k_cost(const uint8_t *__restrict__ left, 
     const int64_t plane = (int64_t)wo * ho;
     float *out = cost + (int64_t)y * wo + x;
     for (int d = 0; d < L; ++d) {
-        float v = trunc;
-        if (x - d >= 0) {
-            const uint32_t rv = rpx[tid + (L - 1) - d];
-            float a;
-            if constexpr (C == 1) {
-                a = (float)abs((int)lv - (int)rv);
-            } else {
-                int sum = 0;
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch)
-                    sum += abs((int)((lv >> (8 * ch)) & 0xffu) - (int)((rv >> (8 * ch)) & 0xffu));
-                a = rgb_mode == 0 ? (float)((sum + 1) / 3) : (float)sum / 3.0f;
-            }
-            v = fminf(a, trunc);
-        }
+        const float v = x - d >= 0 ? ad_cost<C>(lv, rpx[tid + (L - 1) - d], rgb_mode, trunc) : trunc;
         out[(int64_t)d * plane] = v;
     }
 }
@@ -109,6 +117,185 @@ bp_status launch_downsample(const uint8_t *in, int w, int h, int ch, int64_t str
     const unsigned grid = (unsigned)((n + 255) / 256);
     if (ch == 1) k_downsample<1><<<grid, 256, 0, s>>>(in, stride, ds, wo, ho, out);
     else k_downsample<3><<<grid, 256, 0, s>>>(in, stride, ds, wo, ho, out);
+    return launch_status();
+}
+
+// ------------------------------------------------------------------------
+// Finest-level data term computed from a pair (bp_problem.pair)
+// ------------------------------------------------------------------------
+
+// Both images of the pair, downsampled and packed: out[z][y][x], z = 0 left.
+template <int C>
+__global__ void __launch_bounds__(256) k_pack_pair(const uint8_t *__restrict__ left, const uint8_t *__restrict__ right,
+                                                  int64_t stride, int s, int wo, int ho, uint32_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = (int64_t)wo * ho;
+    if (i >= n) return;
+    const int x = (int)(i % wo), y = (int)(i / wo);
+    out[blockIdx.y * n + i] = pixel_ds<C>(blockIdx.y ? right : left, stride, x, y, s);
+}
+
+// One block owns row y, pixels [x0, x0 + xb) (x0 even): the packed left
+// pixels and the right pixels they can match are staged in LDS, then the
+// cost of every (pixel, label) is stored at its colour-split address
+// c * blk + label * ls + j * ps, j = y * wh + x / 2, c = (x + y) & 1.
+// Pixel-major levels (PM): consecutive lanes take consecutive labels of a
+// pixel (lp2 = L rounded up to a power of two lanes per pixel); label-major
+// levels: consecutive lanes take consecutive same-colour pixels of a label.
+template <int C, bool PM>
+__global__ void __launch_bounds__(256) k_cost_level0(const uint32_t *__restrict__ packed, int w, int h, int L,
+                                                    float trunc, int rgb_mode, int xb, int lp2, int wh, int64_t blk,
+                                                    int64_t ls, int64_t ps, float *__restrict__ out)
+{
+    extern __shared__ uint32_t lds[];
+    const int y = blockIdx.y, x0 = blockIdx.x * xb;
+    const int nx = min(xb, w - x0);
+    uint32_t *lpx = lds;             // [xb]
+    uint32_t *rpx = lds + xb;        // [xb + L - 1], rpx[i] = right pixel x0 - (L - 1) + i
+    const uint32_t *lrow = packed + (int64_t)y * w;
+    const uint32_t *rrow = packed + (int64_t)w * h + (int64_t)y * w;
+    for (int i = threadIdx.x; i < nx; i += 256) lpx[i] = lrow[x0 + i];
+    for (int i = threadIdx.x; i < nx + L - 1; i += 256) {
+        const int x = x0 - (L - 1) + i;
+        rpx[i] = x >= 0 ? rrow[x] : 0u;
+    }
+    __syncthreads();
+    // Pixels of colour 0 first, then colour 1; n0 of colour 0 in the segment.
+    const int off0 = y & 1;                       // first x (relative to x0) of colour 0
+    const int n0 = (nx - off0 + 1) / 2, n1 = (nx - (off0 ^ 1) + 1) / 2;
+    const int np = n0 + n1;
+    auto pixel = [&](int p, int &xl, int64_t &base) {
+        const int c = p < n0 ? 0 : 1;
+        const int i = c ? p - n0 : p;
+        xl = 2 * i + (c ? off0 ^ 1 : off0);
+        const int x = x0 + xl;
+        base = (int64_t)c * blk + (int64_t)(y * wh + (x >> 1)) * ps;
+    };
+    if constexpr (PM) {
+        const int f = (int)threadIdx.x % lp2;
+        const int step = 256 / lp2;
+        if (f >= L) return;
+        for (int p = (int)threadIdx.x / lp2; p < np; p += step) {
+            int xl;
+            int64_t base;
+            pixel(p, xl, base);
+            const float v = x0 + xl - f >= 0 ? ad_cost<C>(lpx[xl], rpx[xl + (L - 1) - f], rgb_mode, trunc) : trunc;
+            out[base + (int64_t)f * ls] = v;
+        }
+    } else {
+        for (int f = 0; f < L; ++f)
+            for (int p = threadIdx.x; p < np; p += 256) {
+                int xl;
+                int64_t base;
+                pixel(p, xl, base);
+                const float v = x0 + xl - f >= 0 ? ad_cost<C>(lpx[xl], rpx[xl + (L - 1) - f], rgb_mode, trunc) : trunc;
+                out[base + (int64_t)f * ls] = v;
+            }
+    }
+}
+
+// Pixel-major levels 0 and 1 together: one block owns level-1 row Y, pixels
+// [X0, X0 + xb1), i.e. level-0 rows 2Y and 2Y + 1 (if present) and pixels
+// [2 X0, 2 X0 + 2 xb1).  A lane computes the (up to four) level-0 children of
+// one level-1 pixel and label, stores them, and stores their sum, added in
+// the order (0,0), (1,0), (0,1), (1,1) as the separate pyramid step does.
+template <int C>
+__global__ void __launch_bounds__(256) k_cost_level01(const uint32_t *__restrict__ packed, int w, int h, int L,
+                                                     float trunc, int rgb_mode, int xb1, int lp2, int wh0,
+                                                     int64_t blk0, int64_t ps0, float *__restrict__ out0, int w1,
+                                                     int wh1, int64_t blk1, int64_t ps1, float *__restrict__ out1)
+{
+    extern __shared__ uint32_t lds[];
+    const int Y = blockIdx.y, X0 = blockIdx.x * xb1;
+    const int nX = min(xb1, w1 - X0);
+    const int x0 = 2 * X0, nx = min(2 * xb1, w - x0);
+    const int span = 2 * xb1 + L - 1;
+    const int rows = min(2, h - 2 * Y);
+    // Row r of the block: lpx at lds[r * (2 xb1 + span)], rpx after it.
+    for (int r = 0; r < rows; ++r) {
+        uint32_t *lpx = lds + r * (2 * xb1 + span);
+        uint32_t *rpx = lpx + 2 * xb1;
+        const int y = 2 * Y + r;
+        const uint32_t *lrow = packed + (int64_t)y * w;
+        const uint32_t *rrow = packed + (int64_t)w * h + (int64_t)y * w;
+        for (int i = threadIdx.x; i < nx; i += 256) lpx[i] = lrow[x0 + i];
+        for (int i = threadIdx.x; i < nx + L - 1; i += 256) {
+            const int x = x0 - (L - 1) + i;
+            rpx[i] = x >= 0 ? rrow[x] : 0u;
+        }
+    }
+    __syncthreads();
+    const int f = (int)threadIdx.x % lp2;
+    const int step = 256 / lp2;
+    if (f >= L) return;
+    for (int X = (int)threadIdx.x / lp2; X < nX; X += step) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 2; ++ii) {
+                const int xl = 2 * X + ii, x = x0 + xl, y = 2 * Y + jj;
+                if (xl >= nx || jj >= rows) continue;
+                const uint32_t *lpx = lds + jj * (2 * xb1 + span);
+                const uint32_t *rpx = lpx + 2 * xb1;
+                const float v = x - f >= 0 ? ad_cost<C>(lpx[xl], rpx[xl + (L - 1) - f], rgb_mode, trunc) : trunc;
+                out0[(int64_t)((x + y) & 1) * blk0 + (int64_t)(y * wh0 + (x >> 1)) * ps0 + f] = v;
+                acc += v;
+            }
+        const int Xg = X0 + X;
+        out1[(int64_t)((Xg + Y) & 1) * blk1 + (int64_t)(Y * wh1 + (Xg >> 1)) * ps1 + f] = acc;
+    }
+}
+
+bp_status launch_pair_cost(const bp_pair &pr, const Plan &p, uint8_t *ws, hipStream_t st, int *levels_done)
+{
+    const Level &v = p.lv[0];
+    const int w = v.w, h = v.h, L = p.L;
+    uint32_t *packed = (uint32_t *)(ws + p.pair_off);
+    const unsigned g1 = (unsigned)(((int64_t)w * h + 255) / 256);
+    if (pr.channels == 1)
+        k_pack_pair<1><<<dim3(g1, 2), 256, 0, st>>>(pr.left, pr.right, pr.row_stride_bytes, pr.downsample, w, h, packed);
+    else
+        k_pack_pair<3><<<dim3(g1, 2), 256, 0, st>>>(pr.left, pr.right, pr.row_stride_bytes, pr.downsample, w, h, packed);
+    int lp2 = 1;
+    while (lp2 < L) lp2 <<= 1;
+    if (p.levels >= 2 && v.layout == PIXEL_MAJOR && p.lv[1].layout == PIXEL_MAJOR) {
+        const Level &v1 = p.lv[1];
+        const int nseg1 = (v1.w + 127) / 128;
+        const int xb1 = (v1.w + nseg1 - 1) / nseg1;
+        const dim3 grid1((unsigned)((v1.w + xb1 - 1) / xb1), (unsigned)v1.h);
+        const size_t lds1 = sizeof(uint32_t) * (size_t)2 * (2 * xb1 + 2 * xb1 + L - 1);
+        float *out0 = (float *)(ws + v.cost_off), *out1 = (float *)(ws + v1.cost_off);
+        if (pr.channels == 1)
+            k_cost_level01<1><<<grid1, 256, lds1, st>>>(packed, w, h, L, pr.data_trunc, pr.rgb_mode, xb1, lp2, v.wh,
+                                                        v.blk, v.ps, out0, v1.w, v1.wh, v1.blk, v1.ps, out1);
+        else
+            k_cost_level01<3><<<grid1, 256, lds1, st>>>(packed, w, h, L, pr.data_trunc, pr.rgb_mode, xb1, lp2, v.wh,
+                                                        v.blk, v.ps, out0, v1.w, v1.wh, v1.blk, v1.ps, out1);
+        *levels_done = 2;
+        return launch_status();
+    }
+    *levels_done = 1;
+    // Row segments of at most 256 pixels, balanced, even width.
+    const int nseg = (w + 255) / 256;
+    int xb = (w + nseg - 1) / nseg;
+    xb += xb & 1;
+    const dim3 grid((unsigned)((w + xb - 1) / xb), (unsigned)h);
+    const size_t lds = sizeof(uint32_t) * (size_t)(2 * xb + L - 1);
+    float *out = (float *)(ws + v.cost_off);
+    const bool pm = v.layout == PIXEL_MAJOR;
+#define BP_COST0(CV, PMV)                                                                                    \
+    k_cost_level0<CV, PMV><<<grid, 256, lds, st>>>(packed, w, h, L, pr.data_trunc, pr.rgb_mode, xb, lp2, v.wh, \
+                                                   v.blk, v.ls, v.ps, out)
+    if (pr.channels == 1) {
+        if (pm) BP_COST0(1, true);
+        else BP_COST0(1, false);
+    } else {
+        if (pm) BP_COST0(3, true);
+        else BP_COST0(3, false);
+    }
+#undef BP_COST0
     return launch_status();
 }
 

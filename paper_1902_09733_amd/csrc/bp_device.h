@@ -169,7 +169,14 @@ __device__ __forceinline__ int dpp_i(int old, int v)
 // x + x[lane ^ D] for D in {4, 8, 16, 32}: both lanes of a pair get the same
 // bits (IEEE addition is commutative).  D = 4 composes a quad reversal with a
 // half-row mirror, D = 8 is a rotation by 8 within a 16-lane row, D = 16 and
-// D = 32 are gfx950's register-only row and half-wave swaps.
+// D = 32 are gfx950's register-only row and half-wave swaps: swapping x with
+// a copy of itself leaves one register holding the even rows' (lower
+// half's) values and the other the odd rows' (upper half's), so their sum is
+// the pair sum in every lane.  The swap is written as inline assembly: with
+// ROCm 7.2 the builtins' second result is lost after register coalescing
+// (the sum compiles to 2 * r[0]).  The s_nop pairs cover the VALU-write to
+// lane-swap-read hazard on both sides, which the compiler cannot see
+// through the asm statement.
 template <int D>
 __device__ __forceinline__ float xor_sum(float x)
 {
@@ -178,14 +185,13 @@ __device__ __forceinline__ float xor_sum(float x)
         return x + dpp_f<0x141>(x, dpp_f<0x1B>(x, x));
     } else if constexpr (D == 8) {
         return x + dpp_f<0x128>(x, x);
-    } else if constexpr (D == 16) {
-        const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x),
-                                                        __builtin_bit_cast(unsigned, x), false, false);
-        return __builtin_bit_cast(float, r[0]) + __builtin_bit_cast(float, r[1]);
     } else {
-        const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x),
-                                                        __builtin_bit_cast(unsigned, x), false, false);
-        return __builtin_bit_cast(float, r[0]) + __builtin_bit_cast(float, r[1]);
+        float a = x, b = x;
+        if constexpr (D == 16)
+            asm volatile("s_nop 2\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 2" : "+v"(a), "+v"(b));
+        else
+            asm volatile("s_nop 2\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 2" : "+v"(a), "+v"(b));
+        return a + b;
     }
 }
 

@@ -50,6 +50,7 @@ struct Plan {
     int w, h, L, levels;
     int variant;          // half-sweep kernel variant (0 = default)
     Level lv[kMaxLevels];
+    size_t pair_off;      // byte offset of the packed downsampled pair (cost from a pair)
     size_t bytes;         // total workspace bytes of this problem (aligned)
 };
 
@@ -78,6 +79,10 @@ bp_status launch_downsample(const uint8_t *in, int w, int h, int ch, int64_t str
 
 // a3: level-0 cost in the level's layout, and the sum pyramid.
 bp_status launch_split_cost(const float *planar, const Plan &p, uint8_t *ws, hipStream_t s);
+// Finest-level cost from a pair: packs the downsampled pair at p.pair_off,
+// then writes the data term in the level's layout, and level 1's pyramid sum
+// too when both levels are pixel-major (*levels_done = 2, else 1).
+bp_status launch_pair_cost(const bp_pair &pr, const Plan &p, uint8_t *ws, hipStream_t s, int *levels_done);
 bp_status launch_pyramid_level(const Plan &p, int l, uint8_t *ws, hipStream_t s);
 
 // a4: zero every level's out-of-grid slots and the coarsest level's

@@ -69,6 +69,37 @@ def cost_volume(left: torch.Tensor, right: torch.Tensor, num_labels: int, data_t
 
 
 @dataclass
+class Pair:
+    """A rectified u8 pair ([H][W] or [H][W][3]) standing in for a cost volume
+    in ``run``: the library computes the finest-level data term itself (the
+    values ``cost_volume`` gives for the same arguments) straight into its
+    internal layout, without a planar volume in memory."""
+    left: torch.Tensor
+    right: torch.Tensor
+    num_labels: int
+    data_trunc: float = 20.0
+    downsample: int = 1
+    rgb_mode: int = 0
+
+    @property
+    def shape(self):
+        w, h, _ = _img_dims(self.left)
+        return (self.num_labels, h // self.downsample, w // self.downsample)
+
+    @property
+    def device(self):
+        return self.left.device
+
+    def c(self):
+        _need_gpu(self.left, self.right)
+        if self.left.dtype != torch.uint8 or self.right.dtype != torch.uint8 or self.left.shape != self.right.shape:
+            raise ValueError("left/right must be u8 images of the same shape")
+        w, _, ch = _img_dims(self.left)
+        return _abi.BpPair(self.left.data_ptr(), self.right.data_ptr(), ch, self.downsample, w * ch,
+                           float(self.data_trunc), self.rgb_mode)
+
+
+@dataclass
 class BPParams:
     levels: int = 1
     iters: int = 10
@@ -105,13 +136,20 @@ _default_ws = Workspace()
 
 def _problems(costs, disps, softs, msgs):
     probs = (_abi.BpProblem * len(costs))()
+    pairs = []                       # BpPair structs, kept alive with the array
     for i, c in enumerate(costs):
         L, h, w = c.shape
         probs[i].width, probs[i].height, probs[i].num_labels = w, h, L
-        probs[i].cost = c.data_ptr()
+        if isinstance(c, Pair):
+            pairs.append(c.c())
+            probs[i].cost = None
+            probs[i].pair = ctypes.pointer(pairs[-1])
+        else:
+            probs[i].cost = c.data_ptr()
         probs[i].disparity = disps[i].data_ptr() if disps[i] is not None else None
         probs[i].soft_disparity = softs[i].data_ptr() if softs[i] is not None else None
         probs[i].messages_out = msgs[i].data_ptr() if msgs[i] is not None else None
+    probs._pairs = pairs
     return probs
 
 
@@ -125,15 +163,18 @@ def workspace_bytes(costs, params: BPParams) -> int:
 def run(costs, params: BPParams, *, want_disp: bool = True, want_soft: bool = False, want_msgs: bool = False,
         workspace: Workspace | None = None, checkpoints: torch.Tensor | None = None, outputs=None,
         stream=None):
-    """Hierarchical checkerboard BP on one cost volume [L][H][W] or a list of them.
+    """Hierarchical checkerboard BP on one cost volume [L][H][W] (or a
+    ``Pair``), or on a list of them.
 
     Returns a dict (or a list of dicts for a list input) with ``disp`` (int32
     [H][W]), ``soft`` (float32 [H][W]) and ``msgs`` (float32 [4][L][H][W]).
     ``outputs`` may pass preallocated dicts of the same form.
     """
-    single = isinstance(costs, torch.Tensor)
+    single = isinstance(costs, (torch.Tensor, Pair))
     costs = [costs] if single else list(costs)
     for c in costs:
+        if isinstance(c, Pair):
+            continue
         _need_gpu(c)
         if c.dtype != torch.float32 or c.dim() != 3:
             raise ValueError("cost volumes must be float32 [L][H][W]")

@@ -53,6 +53,35 @@ def test_workspace_size_grows_and_rejects(lib):
     assert lib.bp_workspace_size(_prob(16, 8, 8), 1, ctypes.byref(p2)) > 0
 
 
+def _pair(**kw):
+    d = dict(left=256, right=512, channels=3, downsample=4, row_stride_bytes=16 * 4 * 3, data_trunc=20.0,
+             rgb_mode=0)
+    d.update(kw)
+    return _abi.BpPair(**d)
+
+
+def test_pair_source_validation(lib):
+    """A problem without a cost volume needs a valid pair; the workspace then
+    also holds the packed downsampled pair (2 x W x H words)."""
+    p = _params()
+    with_cost = lib.bp_workspace_size(_prob(16, 8, 8), 1, ctypes.byref(p))
+    pr = _pair()
+    q = _prob(16, 8, 8, cost=0)
+    q[0].pair = ctypes.pointer(pr)
+    with_pair = lib.bp_workspace_size(q, 1, ctypes.byref(p))
+    assert with_pair >= with_cost + 2 * 16 * 8 * 4
+    assert lib.bp_workspace_size(_prob(16, 8, 8, cost=0), 1, ctypes.byref(p)) == 0        # neither
+    for bad in (dict(left=0), dict(right=0), dict(channels=2), dict(downsample=0),
+                dict(row_stride_bytes=16 * 4 * 3 - 1), dict(data_trunc=-1.0), dict(data_trunc=float("nan")),
+                dict(rgb_mode=2)):
+        pb = _pair(**bad)
+        qb = _prob(16, 8, 8, cost=0)
+        qb[0].pair = ctypes.pointer(pb)
+        assert lib.bp_workspace_size(qb, 1, ctypes.byref(p)) == 0, bad
+        st = lib.bp_run(qb, 1, ctypes.byref(p), ctypes.c_void_p(256), 1 << 20, None, 0, None)
+        assert st == _abi.BP_ERR_INVALID_ARGUMENT, bad
+
+
 @pytest.mark.parametrize("kw,expect", [
     (dict(lambda_=-1.0), _abi.BP_ERR_INVALID_ARGUMENT),
     (dict(tau=0.0), _abi.BP_ERR_INVALID_ARGUMENT),

@@ -253,17 +253,75 @@ def test_aerial_full_pipeline_exact(dev, aerial_full):
         g = {k: v.cpu().numpy() for k, v in out.items()}
         assert_exact(g, o, f"aerial full pm_from {pm_from}")
         del out, g
+        # The same problem with the data term computed inside bp_run from the pair.
+        out = bp.run(bp.Pair(left, right, 64, 20.0, downsample=4),
+                     bp.BPParams(levels=5, iters=10, lam=10.0, tau=2.0, pm_from=pm_from), want_msgs=True)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        assert_exact(g, o, f"aerial full from the pair, pm_from {pm_from}")
+        del out, g
     out = bp.run(c, bp.BPParams(levels=5, iters=10, lam=10.0, tau=2.0), want_msgs=True)
     up = bp.upsample(out["disp"], left, 8.0, 12.0, -1)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in out.items()}
     assert_exact(g, o, "aerial full")
-    # Upsampling on sampled rows against the oracle (the full frame is checked
-    # by the oracle's own 4.1 M-pixel run in the benchmark's CPU leg).
+    # Upsampling against the oracle on every 97th row of the 4.1 M-pixel frame.
     rows = np.arange(0, 1520, 97)
     ref = oracle.upsample(o["disp"], w["left"], 8.0, 12.0)
     err = np.abs(up.cpu().numpy()[rows].astype(np.float64) - ref[rows]).max()
     assert err <= 2e-3, err
+
+
+# ---------------------------------------------------------------- data term from the pair
+
+@pytest.mark.parametrize("w,h,ch,s,mode,L,pm_from", [
+    (160, 96, 3, 4, 0, 64, 0), (160, 96, 3, 4, 1, 64, 0), (101, 37, 1, 1, 0, 48, 0),
+    (202, 74, 3, 2, 0, 100, 1), (151, 90, 3, 1, 1, 32, 3), (77, 45, 1, 3, 0, 256, 0),
+    (9, 5, 3, 2, 0, 7, 0),
+])
+def test_pair_input_exact(dev, w, h, ch, s, mode, L, pm_from):
+    """bp_run from a pair (data term written straight into the finest level's
+    layout) equals bp_run on bp_cost_volume's volume bit for bit, and the
+    oracle on integer costs."""
+    bp = bp_mod()
+    rng = np.random.default_rng(w * h + L)
+    shp = (h * s, w * s) + ((3,) if ch == 3 else ())
+    left_np = rng.integers(0, 256, size=shp, dtype=np.uint8)
+    right_np = np.roll(left_np, 3, axis=1) // 2 + rng.integers(0, 128, size=shp, dtype=np.uint8)
+    left, right = torch.from_numpy(left_np).to(dev), torch.from_numpy(right_np).to(dev)
+    p = bp.BPParams(levels=3, iters=5, lam=10.0, tau=2.0, pm_from=pm_from)
+    c = bp.cost_volume(left, right, L, 20.0, downsample=s, rgb_mode=mode)
+    a = bp.run(c, p, want_msgs=True)
+    b = bp.run(bp.Pair(left, right, L, 20.0, downsample=s, rgb_mode=mode), p, want_msgs=True)
+    torch.cuda.synchronize()
+    ga = {k: v.cpu().numpy() for k, v in a.items()}
+    gb = {k: v.cpu().numpy() for k, v in b.items()}
+    np.testing.assert_array_equal(gb["disp"], ga["disp"])
+    np.testing.assert_array_equal(gb["msgs"], ga["msgs"])
+    if mode == 0:
+        lo, ro = (oracle.downsample(left_np, s), oracle.downsample(right_np, s)) if s > 1 else (left_np, right_np)
+        o = oracle_run(oracle.cost_volume(lo, ro, L, 20.0), 3, 5, 10.0, 2.0)
+        assert_exact(gb, o, f"pair {w}x{h}x{L} s{s}")
+
+
+def test_pair_and_volume_problems_batched(dev):
+    """One batched call mixing pair-sourced problems and volumes."""
+    bp = bp_mod()
+    items, refs = [], []
+    for i, (w, h, L) in enumerate([(60, 40, 32), (90, 50, 64), (33, 21, 96), (47, 29, 64)]):
+        left_np, right_np, _ = aerial(2 * w, 2 * h, 2 * L, 40 + i, channels=3)
+        lo, ro = oracle.downsample(left_np, 2), oracle.downsample(right_np, 2)
+        cost = oracle.cost_volume(lo, ro, L, 20.0)
+        refs.append(oracle_run(cost, 3, 6, 10.0, 2.0))
+        if i % 2 == 0:
+            items.append(bp.Pair(torch.from_numpy(left_np).to(dev), torch.from_numpy(right_np).to(dev), L, 20.0,
+                                 downsample=2))
+        else:
+            items.append(torch.from_numpy(cost.astype(np.float32)).to(dev))
+    outs = bp.run(items, bp.BPParams(levels=3, iters=6, lam=10.0, tau=2.0), want_msgs=True)
+    torch.cuda.synchronize()
+    for i, (og, o) in enumerate(zip(outs, refs)):
+        assert_exact({k: v.cpu().numpy() for k, v in og.items()}, o, f"batched item {i}")
 
 
 # ---------------------------------------------------------------- batched form, kernel variants
