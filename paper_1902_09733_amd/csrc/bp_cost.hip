@@ -124,8 +124,46 @@ bp_status launch_downsample(const uint8_t *in, int w, int h, int ch, int64_t str
 // Finest-level data term computed from a pair (bp_problem.pair)
 // ------------------------------------------------------------------------
 
-// Both images of the pair, downsampled and packed: out[z][y][x], z = 0 left.
+// s x s block mean of an interleaved row chunk read as 32-bit words (s a
+// multiple of 4, word-aligned rows): the bytes of channel c in word i are
+// selected by a 0/1 byte mask and summed with one 4 x u8 dot product.  Byte b
+// of a pixel block's row has channel b % C; the mask pattern repeats every C
+// words.  Same rounding as pixel_ds.
 template <int C>
+__device__ __forceinline__ uint32_t pixel_ds_words(const uint8_t *__restrict__ img, int64_t stride, int x, int y,
+                                                   int s)
+{
+    const int nw = s * C / 4;
+    uint32_t acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0;
+    for (int j = 0; j < s; ++j) {
+        const uint32_t *row = (const uint32_t *)(img + (int64_t)(s * y + j) * stride + (int64_t)s * x * C);
+        for (int i = 0; i < nw; ++i) {
+            const uint32_t d = row[i];
+            if constexpr (C == 1) {
+                acc[0] = __builtin_amdgcn_udot4(d, 0x01010101u, acc[0], false);
+            } else {
+                // Word phase i % 3: byte channels (0,1,2,0), (1,2,0,1), (2,0,1,2).
+                const int ph = i % 3;
+                const uint32_t m0 = ph == 0 ? 0x01000001u : ph == 1 ? 0x00010000u : 0x00000100u;
+                const uint32_t m1 = ph == 0 ? 0x00000100u : ph == 1 ? 0x01000001u : 0x00010000u;
+                const uint32_t m2 = ph == 0 ? 0x00010000u : ph == 1 ? 0x00000100u : 0x01000001u;
+                acc[0] = __builtin_amdgcn_udot4(d, m0, acc[0], false);
+                acc[1] = __builtin_amdgcn_udot4(d, m1, acc[1], false);
+                acc[2] = __builtin_amdgcn_udot4(d, m2, acc[2], false);
+            }
+        }
+    }
+    const uint32_t n = (uint32_t)(s * s);
+    uint32_t out = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) out |= ((acc[c] + n / 2) / n) << (8 * c);
+    return out;
+}
+
+// Both images of the pair, downsampled and packed: out[z][y][x], z = 0 left.
+template <int C, bool WORDS>
 __global__ void __launch_bounds__(256) k_pack_pair(const uint8_t *__restrict__ left, const uint8_t *__restrict__ right,
                                                   int64_t stride, int s, int wo, int ho, uint32_t *__restrict__ out)
 {
@@ -133,7 +171,9 @@ __global__ void __launch_bounds__(256) k_pack_pair(const uint8_t *__restrict__ l
     const int64_t n = (int64_t)wo * ho;
     if (i >= n) return;
     const int x = (int)(i % wo), y = (int)(i / wo);
-    out[blockIdx.y * n + i] = pixel_ds<C>(blockIdx.y ? right : left, stride, x, y, s);
+    const uint8_t *img = blockIdx.y ? right : left;
+    if constexpr (WORDS) out[blockIdx.y * n + i] = pixel_ds_words<C>(img, stride, x, y, s);
+    else out[blockIdx.y * n + i] = pixel_ds<C>(img, stride, x, y, s);
 }
 
 // One block owns row y, pixels [x0, x0 + xb) (x0 even): the packed left
@@ -197,12 +237,15 @@ __global__ void __launch_bounds__(256) k_cost_level0(const uint32_t *__restrict_
 
 // Pixel-major levels 0 and 1 together: one block owns level-1 row Y, pixels
 // [X0, X0 + xb1), i.e. level-0 rows 2Y and 2Y + 1 (if present) and pixels
-// [2 X0, 2 X0 + 2 xb1).  A lane computes the (up to four) level-0 children of
-// one level-1 pixel and label, stores them, and stores their sum, added in
-// the order (0,0), (1,0), (0,1), (1,1) as the separate pyramid step does.
+// [2 X0, 2 X0 + 2 xb1).  A lane takes four consecutive labels of one level-1
+// pixel (q4 lanes per pixel, q4 = ceil(L/4) rounded up to a power of two),
+// computes the (up to four) level-0 children, stores each as one 16-byte
+// vector, and stores their sum, added in the order (0,0), (1,0), (0,1), (1,1)
+// as the separate pyramid step does.  Labels past L (inside the level's
+// padded row) get the truncation value; no kernel reads them.
 template <int C>
 __global__ void __launch_bounds__(256) k_cost_level01(const uint32_t *__restrict__ packed, int w, int h, int L,
-                                                     float trunc, int rgb_mode, int xb1, int lp2, int wh0,
+                                                     float trunc, int rgb_mode, int xb1, int q4, int wh0,
                                                      int64_t blk0, int64_t ps0, float *__restrict__ out0, int w1,
                                                      int wh1, int64_t blk1, int64_t ps1, float *__restrict__ out1)
 {
@@ -212,7 +255,8 @@ __global__ void __launch_bounds__(256) k_cost_level01(const uint32_t *__restrict
     const int x0 = 2 * X0, nx = min(2 * xb1, w - x0);
     const int span = 2 * xb1 + L - 1;
     const int rows = min(2, h - 2 * Y);
-    // Row r of the block: lpx at lds[r * (2 xb1 + span)], rpx after it.
+    // Row r of the block: lpx at lds[r * (2 xb1 + span)], rpx after it
+    // (rpx[i] = right pixel x0 - (L - 1) + i).
     for (int r = 0; r < rows; ++r) {
         uint32_t *lpx = lds + r * (2 * xb1 + span);
         uint32_t *rpx = lpx + 2 * xb1;
@@ -226,11 +270,12 @@ __global__ void __launch_bounds__(256) k_cost_level01(const uint32_t *__restrict
         }
     }
     __syncthreads();
-    const int f = (int)threadIdx.x % lp2;
-    const int step = 256 / lp2;
-    if (f >= L) return;
-    for (int X = (int)threadIdx.x / lp2; X < nX; X += step) {
-        float acc = 0.0f;
+    const int q = (int)threadIdx.x % q4;
+    const int f0 = 4 * q;
+    if (f0 >= L) return;
+    const int step = 256 / q4;
+    for (int X = (int)threadIdx.x / q4; X < nX; X += step) {
+        float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
@@ -239,12 +284,22 @@ __global__ void __launch_bounds__(256) k_cost_level01(const uint32_t *__restrict
                 if (xl >= nx || jj >= rows) continue;
                 const uint32_t *lpx = lds + jj * (2 * xb1 + span);
                 const uint32_t *rpx = lpx + 2 * xb1;
-                const float v = x - f >= 0 ? ad_cost<C>(lpx[xl], rpx[xl + (L - 1) - f], rgb_mode, trunc) : trunc;
-                out0[(int64_t)((x + y) & 1) * blk0 + (int64_t)(y * wh0 + (x >> 1)) * ps0 + f] = v;
-                acc += v;
+                const uint32_t lv = lpx[xl];
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int f = f0 + e;
+                    v[e] = (f < L && x - f >= 0) ? ad_cost<C>(lv, rpx[xl + (L - 1) - f], rgb_mode, trunc) : trunc;
+                }
+                *(float4 *)(out0 + (int64_t)((x + y) & 1) * blk0 + (int64_t)(y * wh0 + (x >> 1)) * ps0 + f0) =
+                    make_float4(v[0], v[1], v[2], v[3]);
+                acc.x += v[0];
+                acc.y += v[1];
+                acc.z += v[2];
+                acc.w += v[3];
             }
         const int Xg = X0 + X;
-        out1[(int64_t)((Xg + Y) & 1) * blk1 + (int64_t)(Y * wh1 + (Xg >> 1)) * ps1 + f] = acc;
+        *(float4 *)(out1 + (int64_t)((Xg + Y) & 1) * blk1 + (int64_t)(Y * wh1 + (Xg >> 1)) * ps1 + f0) = acc;
     }
 }
 
@@ -254,24 +309,35 @@ bp_status launch_pair_cost(const bp_pair &pr, const Plan &p, uint8_t *ws, hipStr
     const int w = v.w, h = v.h, L = p.L;
     uint32_t *packed = (uint32_t *)(ws + p.pair_off);
     const unsigned g1 = (unsigned)(((int64_t)w * h + 255) / 256);
-    if (pr.channels == 1)
-        k_pack_pair<1><<<dim3(g1, 2), 256, 0, st>>>(pr.left, pr.right, pr.row_stride_bytes, pr.downsample, w, h, packed);
-    else
-        k_pack_pair<3><<<dim3(g1, 2), 256, 0, st>>>(pr.left, pr.right, pr.row_stride_bytes, pr.downsample, w, h, packed);
+    // Word loads when every pixel block's row chunk is word-aligned.
+    const bool words = pr.downsample % 4 == 0 && pr.row_stride_bytes % 4 == 0 && ((uintptr_t)pr.left % 4) == 0 &&
+                       ((uintptr_t)pr.right % 4) == 0;
+#define BP_PACK(CV, WV) \
+    k_pack_pair<CV, WV><<<dim3(g1, 2), 256, 0, st>>>(pr.left, pr.right, pr.row_stride_bytes, pr.downsample, w, h, packed)
+    if (pr.channels == 1) {
+        if (words) BP_PACK(1, true);
+        else BP_PACK(1, false);
+    } else {
+        if (words) BP_PACK(3, true);
+        else BP_PACK(3, false);
+    }
+#undef BP_PACK
     int lp2 = 1;
     while (lp2 < L) lp2 <<= 1;
     if (p.levels >= 2 && v.layout == PIXEL_MAJOR && p.lv[1].layout == PIXEL_MAJOR) {
         const Level &v1 = p.lv[1];
-        const int nseg1 = (v1.w + 127) / 128;
-        const int xb1 = (v1.w + nseg1 - 1) / nseg1;
+        // 16-byte stores need every pixel's row (lp labels) to be a multiple of 4.
+        int q4 = 1;
+        while (4 * q4 < L) q4 <<= 1;
+        const int xb1 = 32;
         const dim3 grid1((unsigned)((v1.w + xb1 - 1) / xb1), (unsigned)v1.h);
         const size_t lds1 = sizeof(uint32_t) * (size_t)2 * (2 * xb1 + 2 * xb1 + L - 1);
         float *out0 = (float *)(ws + v.cost_off), *out1 = (float *)(ws + v1.cost_off);
         if (pr.channels == 1)
-            k_cost_level01<1><<<grid1, 256, lds1, st>>>(packed, w, h, L, pr.data_trunc, pr.rgb_mode, xb1, lp2, v.wh,
+            k_cost_level01<1><<<grid1, 256, lds1, st>>>(packed, w, h, L, pr.data_trunc, pr.rgb_mode, xb1, q4, v.wh,
                                                         v.blk, v.ps, out0, v1.w, v1.wh, v1.blk, v1.ps, out1);
         else
-            k_cost_level01<3><<<grid1, 256, lds1, st>>>(packed, w, h, L, pr.data_trunc, pr.rgb_mode, xb1, lp2, v.wh,
+            k_cost_level01<3><<<grid1, 256, lds1, st>>>(packed, w, h, L, pr.data_trunc, pr.rgb_mode, xb1, q4, v.wh,
                                                         v.blk, v.ps, out0, v1.w, v1.wh, v1.blk, v1.ps, out1);
         *levels_done = 2;
         return launch_status();

@@ -277,7 +277,7 @@ def test_aerial_full_pipeline_exact(dev, aerial_full):
 @pytest.mark.parametrize("w,h,ch,s,mode,L,pm_from", [
     (160, 96, 3, 4, 0, 64, 0), (160, 96, 3, 4, 1, 64, 0), (101, 37, 1, 1, 0, 48, 0),
     (202, 74, 3, 2, 0, 100, 1), (151, 90, 3, 1, 1, 32, 3), (77, 45, 1, 3, 0, 256, 0),
-    (9, 5, 3, 2, 0, 7, 0),
+    (9, 5, 3, 2, 0, 7, 0), (40, 24, 3, 8, 0, 32, 0), (33, 20, 1, 8, 0, 17, 0), (35, 21, 1, 4, 0, 100, 0),
 ])
 def test_pair_input_exact(dev, w, h, ch, s, mode, L, pm_from):
     """bp_run from a pair (data term written straight into the finest level's
@@ -302,6 +302,28 @@ def test_pair_input_exact(dev, w, h, ch, s, mode, L, pm_from):
         lo, ro = (oracle.downsample(left_np, s), oracle.downsample(right_np, s)) if s > 1 else (left_np, right_np)
         o = oracle_run(oracle.cost_volume(lo, ro, L, 20.0), 3, 5, 10.0, 2.0)
         assert_exact(gb, o, f"pair {w}x{h}x{L} s{s}")
+
+
+def test_pair_input_unaligned_images(dev):
+    """Images at an odd byte address take the byte-load downsampling path."""
+    bp = bp_mod()
+    w, h, s, L = 64, 36, 4, 48
+    rng = np.random.default_rng(3)
+    left_np = rng.integers(0, 256, size=(h * s, w * s, 3), dtype=np.uint8)
+    right_np = np.roll(left_np, 5, axis=1)
+    n = left_np.size
+    buf = torch.empty(2 * n + 2, dtype=torch.uint8, device=dev)
+    left = buf[1:1 + n].view(h * s, w * s, 3)
+    right = buf[n + 2:].view(h * s, w * s, 3)
+    left.copy_(torch.from_numpy(left_np))
+    right.copy_(torch.from_numpy(right_np))
+    assert left.data_ptr() % 4 != 0
+    out = bp.run(bp.Pair(left, right, L, 20.0, downsample=s), bp.BPParams(levels=3, iters=5, lam=10.0, tau=2.0),
+                 want_msgs=True)
+    torch.cuda.synchronize()
+    o = oracle_run(oracle.cost_volume(oracle.downsample(left_np, s), oracle.downsample(right_np, s), L, 20.0),
+                   3, 5, 10.0, 2.0)
+    assert_exact({k: v.cpu().numpy() for k, v in out.items()}, o, "unaligned pair")
 
 
 def test_pair_and_volume_problems_batched(dev):
