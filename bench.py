@@ -44,9 +44,10 @@ def parse():
     ap.add_argument("--volume", action="store_true",
                     help="materialise the planar cost volume with bp_cost_volume inside the step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint"],
-                    help="pair: the benchmarked single-pair path (default); the others measure the "
-                         "batched, 16-bit-message and differentiation forms")
+    ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint", "counters"],
+                    help="pair: the benchmarked single-pair path (default); batch, precision, adjoint "
+                         "measure the other forms; counters runs the pair path eagerly plus a plain "
+                         "copy of known size, for rocprofv3 --pmc passes")
     return ap.parse_args()
 
 
@@ -171,7 +172,8 @@ def main():
 
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": stored_traffic() if args.msg_dtype == "f32" else None,
         "kernel": f"k_iter_pm level-0 checkerboard half-sweep ({w}x{h}x{L}, {args.msg_dtype} messages)",
         "avg_launch_us": round(l0_ms * 1e3, 2), "launches_per_step": lv_n[0],
         "bytes_per_launch": lv_bytes[0], "bytes_per_update": BYTES_PER_UPDATE[args.msg_dtype],
@@ -406,8 +408,65 @@ def form_adjoint(args):
             "forward_updates_per_s": round(units / t_f, 1)}
 
 
+COPY_BYTES = 256 << 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_iter_pm_aerial676x380_L64_f32.txt")
+TRAFFIC_SOURCES = ["paper_1902_09733_amd/csrc/bp_iter_pm.hip", "paper_1902_09733_amd/csrc/bp_device.h",
+                   "paper_1902_09733_amd/csrc/bp_internal.h"]
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per level-0 half-sweep launch from the committed counter
+    passes (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading
+    for a plain copy of known size), or None when the kernel sources changed
+    since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.split(None, 1) for line in fh if line.strip() and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("sources_sha256", "").strip() != sources_digest():
+        return None
+    return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+
+
+def form_counters(args):
+    """The pair path three times without a graph (every dispatch visible to a
+    counter pass), then three plain device-to-device copies of 256 MiB."""
+    import torch
+
+    import paper_1902_09733_amd as bp
+    from synth import workload
+    wl = workload("aerial2704x1520_s4_L64")
+    W0, H0, S, L = wl["width"], wl["height"], wl["downsample"], wl["num_labels"]
+    dev = torch.device("cuda:0")
+    left = torch.from_numpy(wl["left"]).to(dev)
+    right = torch.from_numpy(wl["right"]).to(dev)
+    params = bp.BPParams(levels=wl["levels"], iters=wl["iters"], lam=wl["lam"], tau=wl["tau"])
+    pair = bp.Pair(left, right, L, wl["data_trunc"], downsample=S)
+    for _ in range(3):
+        bp.run(pair, params)
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"form": "counters", "copy_bytes": COPY_BYTES, "pair_runs": 3, "copies": 3,
+            "sources_sha256": sources_digest()}
+
+
 def run_form(form, args):
-    return {"batch": form_batch, "precision": form_precision, "adjoint": form_adjoint}[form](args)
+    return {"batch": form_batch, "precision": form_precision, "adjoint": form_adjoint,
+            "counters": form_counters}[form](args)
 
 
 if __name__ == "__main__":
