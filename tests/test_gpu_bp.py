@@ -304,6 +304,31 @@ def test_pair_input_exact(dev, w, h, ch, s, mode, L, pm_from):
         assert_exact(gb, o, f"pair {w}x{h}x{L} s{s}")
 
 
+@pytest.mark.parametrize("trunc,levels", [(600.0, 3), (2048.0, 2), (2049.0, 2), (7.0, 6), (20.5, 3)])
+def test_pair_input_truncations(dev, trunc, levels):
+    """The pair route with large, boundary and non-integral truncations and
+    deep pyramids (pyramid sums up to 4^5 * 7): bit-exact for integral
+    truncations, within tolerance otherwise."""
+    bp = bp_mod()
+    w, h, s, L = 70, 44, 2, 40
+    rng = np.random.default_rng(int(trunc) + levels)
+    left_np = rng.integers(0, 256, size=(h * s, w * s), dtype=np.uint8)
+    right_np = np.roll(left_np, 4, axis=1)
+    right_np = np.clip(right_np.astype(int) + rng.integers(-3, 4, size=right_np.shape), 0, 255).astype(np.uint8)
+    left, right = torch.from_numpy(left_np).to(dev), torch.from_numpy(right_np).to(dev)
+    p = bp.BPParams(levels=levels, iters=4, lam=10.0, tau=2.0)
+    out = bp.run(bp.Pair(left, right, L, trunc, downsample=s), p, want_msgs=True)
+    torch.cuda.synchronize()
+    cost = oracle.cost_volume(oracle.downsample(left_np, s), oracle.downsample(right_np, s), L, trunc)
+    o = oracle_run(cost, levels, 4, 10.0, 2.0)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    if trunc == int(trunc):
+        assert_exact(g, o, f"pair trunc {trunc}")
+    else:
+        np.testing.assert_array_equal(g["disp"], o["disp"])
+        assert np.abs(g["msgs"] - o["msgs"]).max() <= MSG_TOL_REL * 10.0 * 2.0
+
+
 def test_pair_input_unaligned_images(dev):
     """Images at an odd byte address take the byte-load downsampling path."""
     bp = bp_mod()
