@@ -248,7 +248,13 @@ bool batched(const Plan *plans, int32_t count, const bp_params &p)
 
 // Table entries of the batched form: per level, three kinds of half-sweep
 // (t = 0, odd t, even t >= 2), per problem.
-size_t batch_table_bytes(int32_t count, int levels) { return align_up((size_t)levels * 3 * count * sizeof(BatchEntry)); }
+// Launch entries of the batched form: (level, kind) x problems for the kinds
+// {t = 0, odd t, even t > 0}, plus the finest level's last half-sweep with its
+// fused readout.
+size_t batch_table_bytes(int32_t count, int levels)
+{
+    return align_up(((size_t)levels * 3 + 1) * count * sizeof(BatchEntry));
+}
 
 bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans, const bp_params &p, uint8_t *ws,
                       size_t table_off, hipStream_t s)
@@ -282,16 +288,24 @@ bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans,
         }
         cls_of[i] = c;
     }
-    // Entries for every (level, kind), grouped by class; written once.
-    BatchEntry *host = new BatchEntry[(size_t)n * 3 * count];
+    // The finest level's last half-sweep also reads out its senders' labels
+    // (problems asking for argmin labels only); the readout pass then covers
+    // the other colour.
+    bool *fuse = new bool[count];
+    for (int i = 0; i < count; ++i) fuse[i] = probs[i].disparity && !probs[i].soft_disparity && K >= 1;
+    // Entries for every (level, kind), grouped by class; written once.  Kind
+    // 3 (level 0 only) is the last half-sweep with the fused readout.
+    const size_t nslot = ((size_t)n * 3 + 1) * ncls;
+    BatchEntry *host = new BatchEntry[((size_t)n * 3 + 1) * count];
     BatchEntry *dev = (BatchEntry *)(ws + table_off);
-    int *start = new int[(size_t)n * 3 * ncls], *num = new int[(size_t)n * 3 * ncls], *blocks = new int[(size_t)n * 3 * ncls];
+    int *start = new int[nslot], *num = new int[nslot], *blocks = new int[nslot];
     int e = 0;
     for (int l = 0; l < n; ++l)
-        for (int kind = 0; kind < 3; ++kind) {
-            const int t = kind == 0 ? 0 : (kind == 1 ? 1 : 2);
+        for (int kind = 0; kind < (l == 0 ? 4 : 3); ++kind) {
+            // Half-sweep index the entries stand for (its parity and whether it is 0).
+            const int t = kind == 0 ? 0 : kind == 1 ? 1 : kind == 2 ? 2 : (K >= 1 ? K - 1 : 0);
             for (int c = 0; c < ncls; ++c) {
-                const int slot = (l * 3 + kind) * ncls + c;
+                const int slot = (kind == 3 ? n * 3 : l * 3 + kind) * ncls + c;
                 start[slot] = e;
                 num[slot] = 0;
                 int b0 = 0;
@@ -299,9 +313,10 @@ bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans,
                     if (cls_of[i] != c) continue;
                     const Plan &pl = plans[i];
                     int src_mode = 0;
-                    if (kind == 0 && l < n - 1 && K >= 2 && pl.lv[l].fmt == pl.lv[l + 1].fmt) src_mode = 1;
+                    if (t == 0 && l < n - 1 && K >= 2 && pl.lv[l].fmt == pl.lv[l + 1].fmt) src_mode = 1;
+                    int32_t *ro = (kind == 3 && fuse[i]) ? probs[i].disparity : nullptr;
                     BatchEntry &be = host[e++];
-                    be.a = make_iter_args(pl, l, t, src_mode, p.lambda, p.tau, nullptr, ws);
+                    be.a = make_iter_args(pl, l, t, src_mode, p.lambda, p.tau, ro, ws);
                     be.block0 = b0;
                     b0 += pm_blocks(be.a.ncomp, cls_S[c]);
                     ++num[slot];
@@ -317,22 +332,26 @@ bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans,
                 if (!(K >= 2 && c.fmt == pa.fmt)) st = launch_parent_copy(plans[i], l, ws, s);
             }
         for (int t = 0; t < K && st == BP_OK; ++t) {
-            const int kind = t == 0 ? 0 : (t & 1 ? 1 : 2);
+            const bool last = l == 0 && t == K - 1;
+            const int kind = last ? 3 : t == 0 ? 0 : (t & 1 ? 1 : 2);
             for (int c = 0; c < ncls && st == BP_OK; ++c) {
-                const int slot = (l * 3 + kind) * ncls + c;
+                const int slot = (kind == 3 ? n * 3 : l * 3 + kind) * ncls + c;
                 if (num[slot] == 0) continue;
                 const int fmt = plans[0].lv[l].fmt;   // every problem has the same levels
                 st = launch_iteration_batch(dev + start[slot], num[slot], blocks[slot], fmt, cls_S[c], cls_R[c],
-                                            cls_X[c], s);
+                                            cls_X[c], last, s);
             }
         }
     }
     for (int i = 0; i < count && st == BP_OK; ++i) {
         const bp_problem &q = probs[i];
-        if (q.disparity || q.soft_disparity)
-            st = launch_readout(plans[i], 3, q.disparity, q.soft_disparity, p.temperature, ws, s);
+        if (q.disparity || q.soft_disparity) {
+            const int mask = fuse[i] ? (1 << (K & 1)) : 3;
+            st = launch_readout(plans[i], mask, q.disparity, q.soft_disparity, p.temperature, ws, s);
+        }
         if (st == BP_OK && q.messages_out) st = launch_export(plans[i], q.messages_out, ws, s);
     }
+    delete[] fuse;
     delete[] host;
     delete[] start;
     delete[] num;

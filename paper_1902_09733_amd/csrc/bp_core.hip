@@ -292,6 +292,24 @@ __global__ void __launch_bounds__(256) k_parent_copy(const uint8_t *__restrict__
     SC::st(make_rsrc(cm, cm_bytes), v, (uint32_t)(dst * SC::bytes), 0);
 }
 
+// Pixel-major levels: lanes along (pixel, label) with the label fastest, so
+// both the parent's and the child's label rows are read and written
+// contiguously.  grid (w * L / 256, h, 4 slots).
+template <typename SP, typename SC>
+__global__ void __launch_bounds__(256) k_parent_copy_pm(const uint8_t *__restrict__ pm, uint32_t pm_bytes,
+                                                       LevelDesc pd, uint8_t *__restrict__ cm, uint32_t cm_bytes,
+                                                       LevelDesc cd, int L)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, k = blockIdx.z;
+    if (i >= cd.w * L) return;
+    const int x = i / L, f = i - x * L;
+    const int px = x >> 1, py = y >> 1;
+    const int64_t src = msg_idx((px + py) & 1, k, f, py * pd.wh + (px >> 1), pd.blk, pd.ls, pd.ps);
+    const int64_t dst = msg_idx((x + y) & 1, k, f, y * cd.wh + (x >> 1), cd.blk, cd.ls, cd.ps);
+    const float v = SP::ld(make_rsrc(pm, pm_bytes), (uint32_t)(src * SP::bytes), 0);
+    SC::st(make_rsrc(cm, cm_bytes), v, (uint32_t)(dst * SC::bytes), 0);
+}
+
 template <typename F>
 static bp_status with_store(int fmt, F &&fn)
 {
@@ -309,8 +327,14 @@ bp_status launch_parent_copy(const Plan &p, int l, uint8_t *ws, hipStream_t s)
         return with_store(c.fmt, [&](auto sc) {
             using SP = decltype(sp);
             using SC = decltype(sc);
-            k_parent_copy<SP, SC><<<dim3(cdiv(c.w, 256), c.h, 4 * p.L), 256, 0, s>>>(
-                ws + pa.msg_off, (uint32_t)pa.msg_bytes, desc(pa), ws + c.msg_off, (uint32_t)c.msg_bytes, desc(c), p.L);
+            if (c.layout == PIXEL_MAJOR && pa.layout == PIXEL_MAJOR)
+                k_parent_copy_pm<SP, SC><<<dim3(cdiv((int64_t)c.w * p.L, 256), c.h, 4), 256, 0, s>>>(
+                    ws + pa.msg_off, (uint32_t)pa.msg_bytes, desc(pa), ws + c.msg_off, (uint32_t)c.msg_bytes, desc(c),
+                    p.L);
+            else
+                k_parent_copy<SP, SC><<<dim3(cdiv(c.w, 256), c.h, 4 * p.L), 256, 0, s>>>(
+                    ws + pa.msg_off, (uint32_t)pa.msg_bytes, desc(pa), ws + c.msg_off, (uint32_t)c.msg_bytes, desc(c),
+                    p.L);
             return launch_status();
         });
     });

@@ -167,7 +167,9 @@ int pm_blocks(int ncomp, int S);
 bp_status launch_write_entries(BatchEntry *dst, const BatchEntry *src, int n, hipStream_t s);
 IterArgs make_iter_args(const Plan &p, int l, int t, int src_mode, float lambda, float tau, int32_t *disp,
                         uint8_t *ws);
-bp_status launch_iteration_batch(const BatchEntry *tab, int n, int blocks, int fmt, int S, int R, bool xchg,
+// One batched half-sweep over a table of `n` launch entries; `ro` also writes
+// each entry's senders' labels (entries with disp == NULL skip that).
+bp_status launch_iteration_batch(const BatchEntry *tab, int n, int blocks, int fmt, int S, int R, bool xchg, bool ro,
                                  hipStream_t s);
 
 }  // namespace bpk

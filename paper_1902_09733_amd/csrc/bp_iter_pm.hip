@@ -115,7 +115,7 @@ __device__ __forceinline__ void pm_sweep(const IterArgs &a, uint32_t block)
             }
         }
         seg_argmin<SEG>(bv, bi);
-        if (k == 0 && s == 0) a.disp[(int64_t)y * a.w + x] = bi;
+        if (k == 0 && s == 0 && a.disp) a.disp[(int64_t)y * a.w + x] = bi;
     }
 
     float hmin = inf;
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(256) k_iter_pm(const IterArgs a)
 
 // Batched half-sweep: the problems of one launch share the lane split; block
 // b belongs to the last table entry whose first block is <= b.
-template <int SEG, int R, typename S, bool XCHG>
+template <int SEG, int R, typename S, bool XCHG, bool RO>
 __global__ void __launch_bounds__(256) k_iter_pm_batch(const BatchEntry *__restrict__ tab, int n)
 {
     int lo = 0, hi = n - 1;
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) k_iter_pm_batch(const BatchEntry *__restr
         else hi = mid - 1;
     }
     const IterArgs a = tab[lo].a;
-    pm_sweep<SEG, R, S, false, false, XCHG>(a, blockIdx.x - (uint32_t)tab[lo].block0);
+    pm_sweep<SEG, R, S, false, RO, XCHG>(a, blockIdx.x - (uint32_t)tab[lo].block0);
 }
 
 // Table of batch entries written from kernel arguments (capture-safe: no
@@ -213,19 +213,24 @@ bp_status launch_write_entries(BatchEntry *dst, const BatchEntry *src, int n, hi
 }
 
 template <int SEG, int R, typename S>
-static bp_status launch_pm_batch(const BatchEntry *tab, int n, int blocks, bool xchg, hipStream_t st)
+static bp_status launch_pm_batch(const BatchEntry *tab, int n, int blocks, bool xchg, bool ro, hipStream_t st)
 {
-    if (xchg) k_iter_pm_batch<SEG, R, S, true><<<blocks, 256, 0, st>>>(tab, n);
-    else k_iter_pm_batch<SEG, R, S, false><<<blocks, 256, 0, st>>>(tab, n);
+    if (xchg) {
+        if (ro) k_iter_pm_batch<SEG, R, S, true, true><<<blocks, 256, 0, st>>>(tab, n);
+        else k_iter_pm_batch<SEG, R, S, true, false><<<blocks, 256, 0, st>>>(tab, n);
+    } else {
+        if (ro) k_iter_pm_batch<SEG, R, S, false, true><<<blocks, 256, 0, st>>>(tab, n);
+        else k_iter_pm_batch<SEG, R, S, false, false><<<blocks, 256, 0, st>>>(tab, n);
+    }
     return launch_status();
 }
 
 template <typename S>
-static bp_status dispatch_pm_batch(const BatchEntry *tab, int n, int blocks, int SEGV, int R, bool xchg,
+static bp_status dispatch_pm_batch(const BatchEntry *tab, int n, int blocks, int SEGV, int R, bool xchg, bool ro,
                                    hipStream_t st)
 {
 #define BP_PMB(SV, RV) \
-    if (SEGV == SV && R == RV) return launch_pm_batch<SV, RV, S>(tab, n, blocks, xchg, st);
+    if (SEGV == SV && R == RV) return launch_pm_batch<SV, RV, S>(tab, n, blocks, xchg, ro, st);
     BP_PMB(4, 4) BP_PMB(8, 4) BP_PMB(16, 4) BP_PMB(16, 6) BP_PMB(16, 8) BP_PMB(16, 12) BP_PMB(16, 16)
     BP_PMB(4, 8) BP_PMB(8, 8) BP_PMB(8, 12) BP_PMB(8, 16)
 #undef BP_PMB
@@ -233,12 +238,12 @@ static bp_status dispatch_pm_batch(const BatchEntry *tab, int n, int blocks, int
 }
 
 bp_status launch_iteration_batch(const BatchEntry *tab, int n, int blocks, int fmt, int SEGV, int R, bool xchg,
-                                 hipStream_t st)
+                                 bool ro, hipStream_t st)
 {
     switch (fmt) {
-    case FMT_F16: return dispatch_pm_batch<StoreF16>(tab, n, blocks, SEGV, R, xchg, st);
-    case FMT_BF16: return dispatch_pm_batch<StoreBF16>(tab, n, blocks, SEGV, R, xchg, st);
-    default: return dispatch_pm_batch<StoreF32>(tab, n, blocks, SEGV, R, xchg, st);
+    case FMT_F16: return dispatch_pm_batch<StoreF16>(tab, n, blocks, SEGV, R, xchg, ro, st);
+    case FMT_BF16: return dispatch_pm_batch<StoreBF16>(tab, n, blocks, SEGV, R, xchg, ro, st);
+    default: return dispatch_pm_batch<StoreF32>(tab, n, blocks, SEGV, R, xchg, ro, st);
     }
 }
 

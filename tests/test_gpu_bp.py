@@ -392,6 +392,22 @@ def test_batched_mixed_problems_exact(dev, fmt, mode):
         assert_exact(g, o, f"batched {shp} {fmt}")
 
 
+def test_batched_soft_readout(dev):
+    """Batched problems with the soft-argmin readout (the last half-sweep
+    then leaves the whole readout to the readout pass)."""
+    bp = bp_mod()
+    lam, tau, T = 7.3, 2.6, 0.5
+    shapes = BATCH_SHAPES[:3]
+    costs = [real_case(w, h, L, 11 + i) for i, (w, h, L) in enumerate(shapes)]
+    vols = [torch.from_numpy(c.astype(np.float32)).to(dev) for c in costs]
+    outs = bp.run(vols, bp.BPParams(levels=2, iters=5, lam=lam, tau=tau, temperature=T), want_soft=True)
+    torch.cuda.synchronize()
+    for c, og in zip(costs, outs):
+        o = oracle_run(c, 2, 5, lam, tau, want_soft=True, temperature=T)
+        assert np.abs(og["soft"].cpu().numpy() - o["soft"]).max() <= 2e-3
+        assert (np.abs(og["disp"].cpu().numpy() - o["disp"]) > 1).mean() <= BAD_PIXEL_MAX
+
+
 @pytest.mark.parametrize("K", [1, 2, 5])
 def test_batched_iteration_counts(dev, K):
     bp = bp_mod()
