@@ -227,7 +227,8 @@ bp_status bp_upsample(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const 
  * Requires params->levels == 1, msg_dtype == BP_MSG_F32, checkpoint_every > 0,
  * temperature > 0 and the same problems, params and checkpoints as the
  * forward call.  Errors: BP_ERR_INVALID_ARGUMENT, BP_ERR_UNSUPPORTED (more
- * levels or 16-bit messages), BP_ERR_WORKSPACE_TOO_SMALL, BP_ERR_HIP.
+ * levels, 16-bit messages or more than 128 labels), BP_ERR_WORKSPACE_TOO_SMALL,
+ * BP_ERR_HIP.
  */
 bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *params,
                       const void *checkpoints, size_t ckpt_bytes, const float *grad_soft,

@@ -41,15 +41,18 @@ struct BwdArgs {
     float lambda, tau;
 };
 
-// One reverse half-sweep.  64 threads per block: 16 sender pixels x 4
-// outgoing messages.  grid = ceil(ncomp / 16).
-template <int LP, bool EXACT>
-__global__ void __launch_bounds__(64) k_bwd_step(const BwdArgs a)
+// One reverse half-sweep of one problem, block `block` of it.  64 threads per
+// block: 16 sender pixels x 4 outgoing messages; ceil(ncomp / 16) blocks.
+template <int LP>
+__device__ __forceinline__ void bwd_step(const BwdArgs &a, uint32_t block)
 {
     extern __shared__ float hb_all[];          // [64][LP]
     float *hb = hb_all + threadIdx.x * LP;
-    const int nl = EXACT ? LP : a.L;
-    const int j = blockIdx.x * 16 + (threadIdx.x >> 2);
+    // Labels past L (up to the register row length LP) are inactive.  The
+    // label count stays a runtime value even when it equals LP: that keeps
+    // the loads conditional and the register count low.
+    const int nl = a.L;
+    const int j = (int)block * 16 + (threadIdx.x >> 2);
     const int q = threadIdx.x & 3;
     const float inf = __builtin_huge_valf();
     float lsum = 0.0f, tsum = 0.0f;
@@ -72,42 +75,64 @@ __global__ void __launch_bounds__(64) k_bwd_step(const BwdArgs a)
 #pragma unroll
     for (int k = 0; k < 4; ++k) moff[k] = (((uint32_t)a.colour * 4u + (uint32_t)k) * a.blk + jj) * 4u;
 
-    // Distance transform of h with winners (registers, fully unrolled).
+    // Distance transform of h with winners (registers, fully unrolled).  The
+    // winner of label f (< 256) is kept as a byte of srcp[f / 4].  Loads are
+    // issued 8 labels at a time (scheduling barriers), which bounds the
+    // registers they hold.
     float A[LP];
-    int src[LP];
+    uint32_t srcp[LP / 4];
+    auto set_src = [&](int f, uint32_t g) {
+        const int sh = 8 * (f & 3);
+        srcp[f >> 2] = (srcp[f >> 2] & ~(0xffu << sh)) | (g << sh);
+    };
+    auto get_src = [&](int f) { return (srcp[f >> 2] >> (8 * (f & 3))) & 0xffu; };
+#pragma unroll
+    for (int i = 0; i < LP / 4; ++i) srcp[i] = 0u;
     float hmin = inf;
     int gmin = 0;
 #pragma unroll
-    for (int f = 0; f < LP; ++f) {
-        float h = inf;
-        if (EXACT || f < nl) {
-            h = ld_f32(rc, cost_off, (uint32_t)f * cls);
+    for (int f0 = 0; f0 < LP; f0 += 8) {
+        float hv[8];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float m = ld_f32(rm, moff[k], (uint32_t)f * cls);
-                h += (k == q) ? 0.0f : m;
+        for (int e = 0; e < 8; ++e) {
+            const int f = f0 + e;
+            float h = inf;
+            if (f < nl) {
+                h = ld_f32(rc, cost_off, (uint32_t)f * cls);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float m = ld_f32(rm, moff[k], (uint32_t)f * cls);
+                    h += (k == q) ? 0.0f : m;
+                }
+            }
+            hv[e] = h;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int f = f0 + e;
+            const float h = hv[e];
+            if (h < hmin) {
+                hmin = h;
+                gmin = f;
+            }
+            if (f == 0) {
+                A[0] = h;
+                set_src(0, 0u);
+            } else {
+                const float v = A[f - 1] + a.lambda;
+                const bool keep = h <= v;
+                A[f] = keep ? h : v;
+                set_src(f, keep ? (uint32_t)f : get_src(f - 1));
             }
         }
-        if (h < hmin) {
-            hmin = h;
-            gmin = f;
-        }
-        if (f == 0) {
-            A[0] = h;
-            src[0] = 0;
-        } else {
-            const float v = A[f - 1] + a.lambda;
-            const bool keep = h <= v;
-            A[f] = keep ? h : v;
-            src[f] = keep ? f : src[f - 1];
-        }
+        __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int f = LP - 2; f >= 0; --f) {
         const float v = A[f + 1] + a.lambda;
         if (v < A[f]) {
             A[f] = v;
-            src[f] = src[f + 1];
+            set_src(f, get_src(f + 1));
         }
     }
     const float cap = hmin + a.lambda * a.tau;
@@ -124,37 +149,54 @@ __global__ void __launch_bounds__(64) k_bwd_step(const BwdArgs a)
         else ny = y + 1;
         roff = ((uint32_t)((a.colour ^ 1) * 4 + (q ^ 1)) * a.blk + (uint32_t)(ny * a.wh + (nx >> 1))) * 4u;
     }
+    if (hq) {
 #pragma unroll
-    for (int f = 0; f < LP; ++f) {
-        if (!(EXACT || f < nl)) continue;
-        if (!hq) continue;
-        const float mb = ld_f32(rb, roff, (uint32_t)f * cls);
-        if (cap < A[f]) {
-            lsum += mb * a.tau;
-            tsum += mb * a.lambda;
-        } else {
-            hb[src[f]] += mb;
-            hb[gmin] -= mb;
-            lsum += mb * fabsf((float)(f - src[f]));
+        for (int f0 = 0; f0 < LP; f0 += 8) {
+            float mbv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                mbv[e] = (f0 + e < nl) ? ld_f32(rb, roff, (uint32_t)(f0 + e) * cls) : 0.0f;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int f = f0 + e;
+                if (!(f < nl)) continue;
+                const float mb = mbv[e];
+                if (cap < A[f]) {
+                    lsum += mb * a.tau;
+                    tsum += mb * a.lambda;
+                } else {
+                    const int g = (int)get_src(f);
+                    hb[g] += mb;
+                    hb[gmin] -= mb;
+                    lsum += mb * fabsf((float)(f - g));
+                }
+                st_f32(rb, 0.0f, roff, (uint32_t)f * cls);
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
-        st_f32(rb, 0.0f, roff, (uint32_t)f * cls);
     }
 
     // Sender side: cost-bar += sum_q hbar_q; slot k adjoint += sum_{q != k} hbar_q.
+    // Read-modify-writes are batched 8 labels at a time.
     const int64_t plane = (int64_t)a.h * a.w;
-    for (int f = 0; f < nl; ++f) {
-        const float hv = hb[f];
-        const float tot = group_sum<4>(hv);
-        if (live) {
-            if (has[q]) {
-                const uint32_t so = (uint32_t)f * cls;
-                const float cur = ld_f32(rb, moff[q], so);
-                st_f32(rb, cur + (tot - hv), moff[q], so);
-            }
-            if (q == 0) {
-                float *gc = a.grad_cost + (int64_t)f * plane + (int64_t)y * a.w + x;
-                *gc += tot;
-            }
+    float *gc0 = a.grad_cost + (int64_t)y * a.w + x;
+#pragma unroll 1
+    for (int f0 = 0; f0 < nl; f0 += 8) {
+        float hv[8], tot[8], cur[8], gcv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int f = f0 + e < nl ? f0 + e : nl - 1;
+            hv[e] = f0 + e < nl ? hb[f] : 0.0f;
+            tot[e] = group_sum<4>(hv[e]);
+            cur[e] = (live && has[q] && f0 + e < nl) ? ld_f32(rb, moff[q], (uint32_t)f * cls) : 0.0f;
+            gcv[e] = (live && q == 0 && f0 + e < nl) ? gc0[(int64_t)f * plane] : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int f = f0 + e;
+            if (!live || f >= nl) continue;
+            if (has[q]) st_f32(rb, cur[e] + (tot[e] - hv[e]), moff[q], (uint32_t)f * cls);
+            if (q == 0) gc0[(int64_t)f * plane] = gcv[e] + tot[e];
         }
     }
 
@@ -165,9 +207,40 @@ __global__ void __launch_bounds__(64) k_bwd_step(const BwdArgs a)
         tsum += __shfl_xor(tsum, o, 64);
     }
     if (threadIdx.x == 0) {
-        a.partial[2 * blockIdx.x] = lsum;
-        a.partial[2 * blockIdx.x + 1] = tsum;
+        a.partial[2 * block] = lsum;
+        a.partial[2 * block + 1] = tsum;
     }
+}
+
+// The reverse half-sweep of several problems (same label count) in one
+// launch: block b belongs to the last entry whose first block is <= b.
+struct BwdEntry {
+    BwdArgs a;
+    int block0;
+    int pad[3];
+};
+constexpr int kBwdChunk = 16;
+struct BwdChunk {
+    BwdEntry e[kBwdChunk];
+    int n;
+};
+
+__global__ void k_write_bwd_entries(BwdEntry *__restrict__ dst, BwdChunk c)
+{
+    const int i = threadIdx.x;
+    if (i < c.n) dst[i] = c.e[i];
+}
+
+template <int LP>
+__global__ void __launch_bounds__(64) k_bwd_step_batch(const BwdEntry *__restrict__ tab, int n)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].block0 <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    bwd_step<LP>(tab[lo].a, blockIdx.x - (uint32_t)tab[lo].block0);
 }
 
 // Readout adjoint: b = cost + sum of the four incoming messages of M_K,
@@ -223,16 +296,34 @@ __global__ void __launch_bounds__(256) k_bwd_readout(const float *__restrict__ c
 }
 
 // Deterministic sum of the per-block partials (fixed order), one thread.
-__global__ void k_bwd_finish(const float *__restrict__ partial, int n, float *grad_lambda, float *grad_tau)
+// Deterministic sum of the (lambda, tau) partials: thread i of one 1024-thread
+// block adds partials i, i + 1024, ... in FP64 in that order, then a fixed
+// binary tree over the threads combines them.  The order never depends on
+// scheduling, so repeated calls give identical bits.
+__global__ void __launch_bounds__(1024) k_bwd_finish(const float *__restrict__ partial, int n, float *grad_lambda,
+                                                    float *grad_tau)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double sl[1024], st[1024];
+    const int i = threadIdx.x;
     double l = 0.0, t = 0.0;
-    for (int i = 0; i < n; ++i) {
-        l += partial[2 * i];
-        t += partial[2 * i + 1];
+    for (int k = i; k < n; k += 1024) {
+        l += partial[2 * k];
+        t += partial[2 * k + 1];
     }
-    *grad_lambda = (float)l;
-    *grad_tau = (float)t;
+    sl[i] = l;
+    st[i] = t;
+    __syncthreads();
+    for (int h = 512; h >= 1; h >>= 1) {
+        if (i < h) {
+            sl[i] += sl[i + h];
+            st[i] += st[i + h];
+        }
+        __syncthreads();
+    }
+    if (i == 0) {
+        *grad_lambda = (float)sl[0];
+        *grad_tau = (float)st[0];
+    }
 }
 
 // Byte copy with 16-byte words (sizes are multiples of 256).
@@ -264,49 +355,82 @@ bp_status launch_bwd_readout(const Plan &p, const uint8_t *msg, float *mbar, con
     return launch_status();
 }
 
-bp_status launch_bwd_step(const Plan &p, int t, const uint8_t *msg, float *mbar, float *grad_cost, float *partial,
-                          float lambda, float tau, uint8_t *ws, hipStream_t s)
+size_t bwd_table_bytes(int count) { return align_up((size_t)count * sizeof(BwdEntry)); }
+
+bp_status launch_bwd_step_batch(const BwdProblem *probs, int count, int t, float lambda, float tau, uint8_t *table,
+                                hipStream_t s)
 {
-    const Level &v = p.lv[0];
-    BwdArgs a;
-    a.cost = (const float *)(ws + v.cost_off);
-    a.cost_bytes = (uint32_t)v.cost_bytes;
-    a.msg = msg;
-    a.msg_bytes = (uint32_t)v.msg_bytes;
-    a.mbar = mbar;
-    a.mbar_bytes = (uint32_t)v.msg_bytes;
-    a.grad_cost = grad_cost;
-    a.partial = partial;
-    a.w = v.w;
-    a.h = v.h;
-    a.wh = v.wh;
-    a.blk = (uint32_t)v.blk;
-    a.ls = (uint32_t)v.ls;
-    a.colour = t & 1;
-    a.L = p.L;
-    a.ncomp = v.h * v.wh;
-    a.lambda = lambda;
-    a.tau = tau;
-    const unsigned grid = (unsigned)bwd_step_blocks(p);
-    const int L = p.L;
-#define BP_BWD(LV, EX)                                                             \
-    k_bwd_step<LV, EX><<<grid, 64, 64 * LV * sizeof(float), s>>>(a);               \
-    return launch_status();
-    if (L == 16) { BP_BWD(16, true) }
-    if (L == 32) { BP_BWD(32, true) }
-    if (L == 64) { BP_BWD(64, true) }
-    if (L == 128) { BP_BWD(128, true) }
-    if (L < 16) { BP_BWD(16, false) }
-    if (L < 32) { BP_BWD(32, false) }
-    if (L < 64) { BP_BWD(64, false) }
-    if (L < 128) { BP_BWD(128, false) }
+    BwdEntry *dev = (BwdEntry *)table;
+    // One launch per label count (the kernel's register row length).
+    bool *done = new bool[count]();
+    BwdEntry *host = new BwdEntry[count];
+    bp_status st = BP_OK;
+    int used = 0;
+    for (int i = 0; i < count && st == BP_OK; ++i) {
+        if (done[i]) continue;
+        const int L = probs[i].plan->L;
+        const int first = used;
+        int blocks = 0;
+        for (int k = i; k < count; ++k) {
+            if (done[k] || probs[k].plan->L != L) continue;
+            done[k] = true;
+            const Plan &p = *probs[k].plan;
+            const Level &v = p.lv[0];
+            BwdEntry &e = host[used++];
+            BwdArgs &a = e.a;
+            a.cost = (const float *)(probs[k].ws + v.cost_off);
+            a.cost_bytes = (uint32_t)v.cost_bytes;
+            a.msg = probs[k].state;
+            a.msg_bytes = (uint32_t)v.msg_bytes;
+            a.mbar = probs[k].mbar;
+            a.mbar_bytes = (uint32_t)v.msg_bytes;
+            a.grad_cost = probs[k].grad_cost;
+            a.partial = probs[k].partial;
+            a.w = v.w;
+            a.h = v.h;
+            a.wh = v.wh;
+            a.blk = (uint32_t)v.blk;
+            a.ls = (uint32_t)v.ls;
+            a.colour = t & 1;
+            a.L = p.L;
+            a.ncomp = v.h * v.wh;
+            a.lambda = lambda;
+            a.tau = tau;
+            e.block0 = blocks;
+            blocks += bwd_step_blocks(p);
+        }
+        // Entries of this group: written by value through kernel arguments.
+        for (int c0 = first; c0 < used && st == BP_OK; c0 += kBwdChunk) {
+            BwdChunk c;
+            c.n = used - c0 < kBwdChunk ? used - c0 : kBwdChunk;
+            for (int k = 0; k < c.n; ++k) c.e[k] = host[c0 + k];
+            k_write_bwd_entries<<<1, 64, 0, s>>>(dev + c0, c);
+            st = launch_status();
+        }
+        if (st != BP_OK) break;
+        const int n = used - first;
+        const BwdEntry *tab = dev + first;
+#define BP_BWD(LV)                                                                            \
+    {                                                                                         \
+        k_bwd_step_batch<LV><<<blocks, 64, 64 * LV * sizeof(float), s>>>(tab, n);            \
+        st = launch_status();                                                                 \
+        continue;                                                                             \
+    }
+        if (L <= 16) BP_BWD(16)
+        if (L <= 32) BP_BWD(32)
+        if (L <= 64) BP_BWD(64)
+        if (L <= 128) BP_BWD(128)
 #undef BP_BWD
-    return BP_ERR_UNSUPPORTED;
+        st = BP_ERR_UNSUPPORTED;
+    }
+    delete[] done;
+    delete[] host;
+    return st;
 }
 
 bp_status launch_bwd_finish(const float *partial, int n, float *grad_lambda, float *grad_tau, hipStream_t s)
 {
-    k_bwd_finish<<<1, 64, 0, s>>>(partial, n, grad_lambda, grad_tau);
+    k_bwd_finish<<<1, 1024, 0, s>>>(partial, n, grad_lambda, grad_tau);
     return launch_status();
 }
 

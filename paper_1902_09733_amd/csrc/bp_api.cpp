@@ -531,7 +531,7 @@ bp_status bp_upsample(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const 
 // rebuilt from checkpoints) and the message adjoint, then the (lambda, tau)
 // partials of every reverse step of every problem.
 static bool backward_layout(const bp_problem *probs, int32_t count, const bp_params *params, Plan *plans,
-                            size_t *mbar_off, size_t *partial_off, int *n_partial, size_t *total)
+                            size_t *mbar_off, size_t *partial_off, int *n_partial, size_t *table_off, size_t *total)
 {
     size_t off = 0;
     int np = 0;
@@ -547,6 +547,8 @@ static bool backward_layout(const bp_problem *probs, int32_t count, const bp_par
     *partial_off = off;
     *n_partial = np;
     off += align_up((size_t)(np > 0 ? np : 1) * 2 * sizeof(float));
+    *table_off = off;
+    off += bwd_table_bytes(count);
     *total = off;
     return true;
 }
@@ -564,11 +566,13 @@ static bool valid_backward(const bp_problem *probs, int32_t count, const bp_para
 size_t bp_backward_workspace_size(const bp_problem *probs, int32_t count, const bp_params *params)
 {
     if (!valid_backward(probs, count, params)) return 0;
+    for (int i = 0; i < count; ++i)
+        if (probs[i].num_labels > kMaxBackwardLabels) return 0;
     Plan *plans = new Plan[count];
     size_t *mo = new size_t[count];
-    size_t po = 0, total = 0;
+    size_t po = 0, to = 0, total = 0;
     int np = 0;
-    bool ok = backward_layout(probs, count, params, plans, mo, &po, &np, &total);
+    bool ok = backward_layout(probs, count, params, plans, mo, &po, &np, &to, &total);
     delete[] plans;
     delete[] mo;
     return ok ? total : 0;
@@ -584,13 +588,15 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
     if (!checkpoints || !grad_soft || !grad_cost || !grad_lambda || !grad_tau || !workspace) return BP_ERR_INVALID_ARGUMENT;
     if (((uintptr_t)workspace % kAlign) != 0 || ((uintptr_t)checkpoints % kAlign) != 0) return BP_ERR_INVALID_ARGUMENT;
     if (!valid_backward(probs, count, params)) return BP_ERR_INVALID_ARGUMENT;
+    for (int i = 0; i < count; ++i)
+        if (probs[i].num_labels > kMaxBackwardLabels) return BP_ERR_UNSUPPORTED;
     Plan *plans = new Plan[count];
     size_t *mo = new size_t[count];
-    size_t po = 0, total = 0;
+    size_t po = 0, to = 0, total = 0;
     int np = 0;
     bp_status st = BP_OK;
     const int K = params->iters_per_level, every = params->checkpoint_every;
-    if (!backward_layout(probs, count, params, plans, mo, &po, &np, &total)) st = BP_ERR_UNSUPPORTED;
+    if (!backward_layout(probs, count, params, plans, mo, &po, &np, &to, &total)) st = BP_ERR_UNSUPPORTED;
     size_t ck_total = 0;
     for (int i = 0; st == BP_OK && i < count; ++i) ck_total += checkpoint_bytes_of(plans[i], K, every);
     if (st == BP_OK && (ws_bytes < total || ckpt_bytes < ck_total)) st = BP_ERR_WORKSPACE_TOO_SMALL;
@@ -602,38 +608,47 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
     (void)hipGetLastError();
     uint8_t *ws = (uint8_t *)workspace;
     float *partial = (float *)(ws + po);
-    const uint8_t *ck = (const uint8_t *)checkpoints;
-    size_t soft_off = 0, cost_off = 0;
+    const int nst = checkpoint_states(K, every);
+    // Per problem: its checkpoints, state buffer, adjoints; the readout adjoint
+    // from the final state initialises the message adjoint and grad_cost.
+    const uint8_t **ck = new const uint8_t *[count];
+    BwdProblem *bp = new BwdProblem[count];
+    {
+        const uint8_t *c = (const uint8_t *)checkpoints;
+        size_t soft_off = 0, cost_off = 0;
+        for (int i = 0; i < count && st == BP_OK; ++i) {
+            const Plan &pl = plans[i];
+            const size_t sb = pl.lv[0].msg_bytes;
+            ck[i] = c;
+            c += (size_t)nst * sb;
+            bp[i] = BwdProblem{&pl, ws, ws + pl.lv[0].msg_off, (float *)(ws + mo[i]), grad_cost + cost_off, nullptr};
+            if ((st = launch_split_cost(probs[i].cost, pl, ws, stream)) != BP_OK) break;
+            st = launch_bwd_readout(pl, ck[i] + (size_t)(nst - 1) * sb, bp[i].mbar, grad_soft + soft_off,
+                                    bp[i].grad_cost, params->temperature, ws, stream);
+            soft_off += (size_t)probs[i].height * probs[i].width;
+            cost_off += (size_t)probs[i].num_labels * probs[i].height * probs[i].width;
+        }
+    }
+    // Reverse half-sweeps, newest first: rebuild every problem's M_t (restore
+    // the last saved state at or before t, replay), then one batched step.
     int part = 0;
-    for (int i = 0; i < count && st == BP_OK; ++i) {
-        const Plan &pl = plans[i];
-        const Level &v = pl.lv[0];
-        const size_t sb = v.msg_bytes;
-        uint8_t *state = ws + v.msg_off;
-        float *mbar = (float *)(ws + mo[i]);
-        float *gc = grad_cost + cost_off;
-        const int nst = checkpoint_states(K, every);
-        if ((st = launch_split_cost(probs[i].cost, pl, ws, stream)) != BP_OK) break;
-        // Readout adjoint from the final state.
-        if ((st = launch_bwd_readout(pl, ck + (size_t)(nst - 1) * sb, mbar, grad_soft + soft_off, gc,
-                                     params->temperature, ws, stream)) != BP_OK)
-            break;
-        for (int t = K - 1; t >= 0 && st == BP_OK; --t) {
-            // Rebuild M_t: restore the last saved state at or before t, replay.
-            const int t0 = (t / every) * every;
+    for (int t = K - 1; t >= 0 && st == BP_OK; --t) {
+        const int t0 = (t / every) * every;
+        for (int i = 0; i < count && st == BP_OK; ++i) {
+            const Plan &pl = plans[i];
+            const size_t sb = pl.lv[0].msg_bytes;
+            uint8_t *state = ws + pl.lv[0].msg_off;
             if (t0 == 0) st = launch_init_messages(pl, ws, stream);
-            else st = launch_copy(ck + (size_t)(t0 / every - 1) * sb, state, sb, stream);
+            else st = launch_copy(ck[i] + (size_t)(t0 / every - 1) * sb, state, sb, stream);
             for (int r = t0; r < t && st == BP_OK; ++r)
                 st = launch_iteration(pl, 0, r, 0, params->lambda, params->tau, nullptr, pl.variant, ws, stream);
-            if (st == BP_OK)
-                st = launch_bwd_step(pl, t, state, mbar, gc, partial + 2 * part, params->lambda, params->tau, ws,
-                                     stream);
+            bp[i].partial = partial + 2 * part;
             part += bwd_step_blocks(pl);
         }
-        ck += (size_t)nst * sb;
-        soft_off += (size_t)probs[i].height * probs[i].width;
-        cost_off += (size_t)probs[i].num_labels * probs[i].height * probs[i].width;
+        if (st == BP_OK) st = launch_bwd_step_batch(bp, count, t, params->lambda, params->tau, ws + to, stream);
     }
+    delete[] ck;
+    delete[] bp;
     if (st == BP_OK) st = launch_bwd_finish(partial, np, grad_lambda, grad_tau, stream);
     delete[] plans;
     delete[] mo;

@@ -138,8 +138,22 @@ bp_status launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 int bwd_step_blocks(const Plan &p);
 bp_status launch_bwd_readout(const Plan &p, const uint8_t *msg, float *mbar, const float *grad_soft,
                              float *grad_cost, float temperature, uint8_t *ws, hipStream_t s);
-bp_status launch_bwd_step(const Plan &p, int t, const uint8_t *msg, float *mbar, float *grad_cost, float *partial,
-                          float lambda, float tau, uint8_t *ws, hipStream_t s);
+// One problem's buffers for a reverse half-sweep.
+struct BwdProblem {
+    const Plan *plan;
+    uint8_t *ws;            // workspace holding the plan's cost
+    const uint8_t *state;   // message state M_t
+    float *mbar;            // message adjoint
+    float *grad_cost;       // planar [L][h][w]
+    float *partial;         // bwd_step_blocks(plan) (lambda, tau) pairs
+};
+size_t bwd_table_bytes(int count);
+// The reverse step keeps a pixel's message row in registers: up to 128 labels.
+constexpr int kMaxBackwardLabels = 128;
+// Reverse half-sweep t of every problem, one launch per label count; the
+// launch entries are written into `table` (bwd_table_bytes(count) bytes).
+bp_status launch_bwd_step_batch(const BwdProblem *probs, int count, int t, float lambda, float tau, uint8_t *table,
+                                hipStream_t s);
 bp_status launch_bwd_finish(const float *partial, int n, float *grad_lambda, float *grad_tau, hipStream_t s);
 bp_status dispatch_iter_pm(const IterArgs &a, int fmt, int S, int R, bool ro, bool xchg, hipStream_t s);
 

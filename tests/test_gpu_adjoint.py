@@ -45,7 +45,8 @@ def gpu_grad(costs, g, K, lam, tau, T, every, dev):
 
 
 @pytest.mark.parametrize("shape,K,every", [((16, 12, 20), 1, 1), ((32, 12, 20), 5, 2), ((64, 9, 14), 8, 2),
-                                           ((32, 7, 11), 6, 3), ((20, 10, 13), 4, 4), ((64, 1, 33), 7, 2)])
+                                           ((32, 7, 11), 6, 3), ((20, 10, 13), 4, 4), ((64, 1, 33), 7, 2),
+                                           ((5, 9, 13), 3, 1), ((100, 6, 9), 4, 2), ((128, 5, 7), 3, 3)])
 def test_adjoint_matches_oracle_adjoint(dev, shape, K, every):
     L, H, W = shape
     rng = np.random.default_rng(L + H + K)
@@ -65,6 +66,27 @@ def test_adjoint_matches_oracle_adjoint(dev, shape, K, every):
         V = np.random.default_rng(i).normal(size=shape)
         a, b = (gc[i] * V).sum(), (gc_o * V).sum()
         assert abs(a - b) <= DIR_TOL * max(abs(b), np.abs(gc_o).sum() * 1e-3), (a, b)
+    assert abs(gl - ol) <= DIR_TOL * max(1.0, abs(ol)), (gl, ol)
+    assert abs(gt - ot) <= DIR_TOL * max(1.0, abs(ot)), (gt, ot)
+
+
+def test_adjoint_mixed_label_counts(dev):
+    """One backward call over problems of different sizes and label counts
+    (one batched reverse launch per label count)."""
+    shapes = [(20, 9, 14), (33, 7, 12), (20, 5, 6), (64, 8, 10)]
+    K, every, lam, tau, T = 5, 2, 3.0, 2.5, 0.5
+    costs = [jittered(sh, 40 + i) for i, sh in enumerate(shapes)]
+    rng = np.random.default_rng(9)
+    g = [rng.normal(size=sh[1:]) for sh in shapes]
+    soft, gc, gl, gt = gpu_grad(costs, g, K, lam, tau, T, every, dev)
+    ol = ot = 0.0
+    for i, c in enumerate(costs):
+        s_o, gc_o, gl_o, gt_o = oracle.backward(c, K, lam, tau, T, g[i])
+        ol += gl_o
+        ot += gt_o
+        scale = np.abs(gc_o).max()
+        close = np.abs(gc[i] - gc_o) <= 1e-3 * scale + 1e-5
+        assert close.mean() >= 0.999, (i, close.mean())
     assert abs(gl - ol) <= DIR_TOL * max(1.0, abs(ol)), (gl, ol)
     assert abs(gt - ot) <= DIR_TOL * max(1.0, abs(ot)), (gt, ot)
 
