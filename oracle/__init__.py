@@ -48,6 +48,7 @@ def lib():
         L.bpo_run.argtypes = [_dp, i, i, i, i, i, d, d, i, i, _u8p, _dp, _dp, _i32p, _dp, d, i]
         L.bpo_pyramid.argtypes = [_dp, i, i, i, i, _dp]
         L.bpo_upsample.argtypes = [_i32p, i, i, _u8p, i, i, i, d, d, i, _dp, i]
+        L.bpo_triangulate.argtypes = [_dp, i, i, d, d, d, d, d, d, d, _dp]
         L.bpo_round_f16.argtypes = [d]
         L.bpo_round_f16.restype = d
         L.bpo_round_bf16.argtypes = [d]
@@ -147,6 +148,17 @@ def upsample(disp_lo, guide, sigma_s: float = 8.0, sigma_r: float = 12.0, radius
     out = np.empty((hh, wh), dtype=np.float64)
     _check(lib().bpo_upsample(_p(d, _i32p), wl, hl, _p(g, _u8p), wh, hh, C, float(sigma_s),
                               float(sigma_r), int(radius), _p(out, _dp), int(nthreads)), "upsample")
+    return out
+
+
+def triangulate(disp, scale: float, baseline: float, focal: float, du: float, dv: float, u0: float, v0: float):
+    """Eq. 3: camera-frame points [H][W][3] of a full-resolution disparity map
+    (in 1/scale pixel units); NaN where the disparity is not positive."""
+    dd = np.ascontiguousarray(disp, dtype=np.float64)
+    h, w = dd.shape
+    out = np.empty((h, w, 3), dtype=np.float64)
+    _check(lib().bpo_triangulate(_p(dd, _dp), w, h, float(scale), float(baseline), float(focal), float(du),
+                                 float(dv), float(u0), float(v0), _p(out, _dp)), "triangulate")
     return out
 
 

@@ -18,6 +18,8 @@
  *                    E_X(d) = E_D,X(d) + sum_Y M_{Y,X}(d) (Eq. 1), or the
  *                    soft-argmin of the same energy
  *   bpo_upsample     joint bilateral upsampling of the disparity (Eq. 2)
+ *   bpo_triangulate  camera-frame point of every full-resolution pixel from
+ *                    its disparity (Eq. 3)
  *
  * Message slot convention: m[k][d][y][x] is the message pixel (x,y) received
  * from its neighbour on side k, k = 0 left, 1 right, 2 up, 3 down.
@@ -487,4 +489,40 @@ int bpo_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Triangulation (Eq. 3).                                              */
+/* ------------------------------------------------------------------ */
+
+/* Eq. 3, first line: a camera-frame point (x, y, z) projects to
+ *   u = f x / (du z) + u0,  v = f y / (dv z) + v0,  d = f B / (du z).
+ * Solving for the point with the disparity d in pixels:
+ *   z = f B / (du d),  x = (u - u0) du z / f = (B / d)(u - u0),
+ *   y = (v - v0) dv z / f = (B / d)(v - v0) dv / du,
+ * so [x, y, z] = (B / d) [u - u0, (v - v0) dv / du, f / du].  (The printed
+ * second line has f B / du as its last entry, which would make z grow with
+ * B^2; the first line fixes it as f / du.)
+ * disp: full-resolution disparity [h][w] in units of 1/scale pixels (the
+ * upsampled low-resolution labels), so d = scale * disp; (u, v) = (column,
+ * row) of the pixel.  Pixels with d <= 0 (no finite depth) get NaN.
+ * out: [h][w][3] (x, y, z). */
+int bpo_triangulate(const double *disp, int w, int h, double scale, double B, double f, double du, double dv,
+                    double u0, double v0, double *out)
+{
+    if (!disp || !out || w <= 0 || h <= 0 || !(scale > 0) || !(f > 0) || !(du > 0) || !(dv > 0)) return BPO_EINVAL;
+    for (int v = 0; v < h; ++v)
+        for (int u = 0; u < w; ++u) {
+            const double d = scale * disp[(size_t)v * w + u];
+            double *o = out + ((size_t)v * w + u) * 3;
+            if (!(d > 0)) {
+                o[0] = o[1] = o[2] = NAN;
+                continue;
+            }
+            const double k = B / d;
+            o[0] = k * (u - u0);
+            o[1] = k * (v - v0) * dv / du;
+            o[2] = k * f / du;
+        }
+    return BPO_OK;
 }
