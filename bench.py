@@ -43,10 +43,11 @@ def parse():
     ap.add_argument("--volume", action="store_true",
                     help="materialise the planar cost volume with bp_cost_volume inside the step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint", "counters"],
+    ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint", "points", "counters"],
                     help="pair: the benchmarked single-pair path (default); batch, precision, adjoint "
-                         "measure the other forms; counters runs the pair path eagerly plus a plain "
-                         "copy of known size, for rocprofv3 --pmc passes")
+                         "measure the other forms; points the JBU with fused triangulation; counters "
+                         "runs the pair path eagerly plus a plain copy of known size, for rocprofv3 "
+                         "--pmc passes")
     return ap.parse_args()
 
 
@@ -432,6 +433,42 @@ def stored_traffic():
     return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
 
 
+def form_points(args):
+    """JBU of the benchmarked pair's disparity to 2704x1520, alone and with
+    the fused Eq. 3 triangulation (float32 [1520][2704][3], 49.3 MB), timed
+    with HIP events on the current stream."""
+    import torch
+
+    import paper_1902_09733_amd as bp
+    from synth import workload
+    wl = workload("aerial2704x1520_s4_L64")
+    dev = torch.device("cuda:0")
+    left = torch.from_numpy(wl["left"]).to(dev)
+    right = torch.from_numpy(wl["right"]).to(dev)
+    S, L = wl["downsample"], wl["num_labels"]
+    params = bp.BPParams(levels=wl["levels"], iters=wl["iters"], lam=wl["lam"], tau=wl["tau"])
+    disp = bp.run(bp.Pair(left, right, L, wl["data_trunc"], downsample=S), params)["disp"]
+    W0, H0 = wl["width"], wl["height"]
+    cam = bp.Camera(baseline=0.5, focal=2.77e-3, du=1.55e-6, dv=1.55e-6, u0=W0 / 2.0, v0=H0 / 2.0)
+    up = torch.empty((H0, W0), dtype=torch.float32, device=dev)
+    pts = torch.empty((H0, W0, 3), dtype=torch.float32, device=dev)
+
+    def ev_time(fn, reps=20):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    t_jbu = ev_time(lambda: bp.upsample(disp, left, wl["sigma_s"], wl["sigma_r"], -1, out=up))
+    t_pts = ev_time(lambda: bp.upsample_points(disp, left, cam, wl["sigma_s"], wl["sigma_r"], -1, out=(up, pts)))
+    return {"form": "points", "workload": "aerial2704x1520_s4_L64", "jbu_ms": round(t_jbu, 4),
+            "jbu_points_ms": round(t_pts, 4), "points_bytes": int(pts.numel() * 4),
+            "epilogue_us": round((t_pts - t_jbu) * 1e3, 2)}
+
+
 def form_counters(args):
     """The pair path three times without a graph (every dispatch visible to a
     counter pass), then three plain device-to-device copies of 256 MiB."""
@@ -459,7 +496,7 @@ def form_counters(args):
 
 
 def run_form(form, args):
-    return {"batch": form_batch, "precision": form_precision, "adjoint": form_adjoint,
+    return {"batch": form_batch, "precision": form_precision, "adjoint": form_adjoint, "points": form_points,
             "counters": form_counters}[form](args)
 
 

@@ -210,6 +210,33 @@ bp_status bp_upsample(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const 
                       float sigma_s, float sigma_r, int32_t radius_lo, float *disp_hi,
                       hipStream_t stream);
 
+/* Pinhole camera of the full-resolution frame for bp_upsample_points. */
+typedef struct {
+    float baseline;   /* B: distance between the two views; points come out in its unit */
+    float focal;      /* f > 0, in the unit of du and dv */
+    float du, dv;     /* pixel pitch, horizontal and vertical, > 0 */
+    float u0, v0;     /* principal point, full-resolution pixel coordinates (column, row) */
+} bp_camera;
+
+/*
+ * a7 with its consumer fused (Eq. 3): joint bilateral upsampling as
+ * bp_upsample, and in the same pass the camera-frame point of every
+ * full-resolution pixel (u, v) = (column, row) with disparity
+ * d = scale * D_p pixels:
+ *   [x, y, z] = (B / d) [u - u0, (v - v0) dv / du, f / du]
+ * which inverts Eq. 3's projection [u, v, d] = (1/z)[f x/du, f y/dv, f B/du]
+ * + [u0, v0, 0] (the last entry of the printed inverse reads f B / du; the
+ * projection fixes it as f / du).  Pixels with d <= 0 get NaN coordinates.
+ *   disp_hi   float32 [h_hi][w_hi] as bp_upsample, or NULL to skip it
+ *   points    float32 [h_hi][w_hi][3] (x, y, z), written fully
+ * Errors: as bp_upsample, plus BP_ERR_INVALID_ARGUMENT for a NULL camera or
+ * points, non-finite camera values, or focal, du or dv not positive.
+ */
+bp_status bp_upsample_points(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const uint8_t *guide_hi,
+                             int32_t w_hi, int32_t h_hi, int32_t channels, int64_t guide_row_stride,
+                             float sigma_s, float sigma_r, int32_t radius_lo, const bp_camera *camera,
+                             float *disp_hi, float *points, hipStream_t stream);
+
 /*
  * a8. Adjoint of bp_run's single-level soft-argmin form: given the gradient
  * of a loss with respect to every problem's soft_disparity, returns its

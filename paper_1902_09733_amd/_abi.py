@@ -43,6 +43,17 @@ class BpProblem(ctypes.Structure):
     ]
 
 
+class BpCamera(ctypes.Structure):
+    _fields_ = [
+        ("baseline", ctypes.c_float),
+        ("focal", ctypes.c_float),
+        ("du", ctypes.c_float),
+        ("dv", ctypes.c_float),
+        ("u0", ctypes.c_float),
+        ("v0", ctypes.c_float),
+    ]
+
+
 class BpParams(ctypes.Structure):
     _fields_ = [
         ("levels", ctypes.c_int32),
@@ -104,6 +115,8 @@ def lib():
     L.bp_run_profiled.restype = ctypes.c_int
     L.bp_upsample.argtypes = [vp, i32, i32, vp, i32, i32, i32, i64, f32, f32, i32, vp, vp]
     L.bp_upsample.restype = ctypes.c_int
+    L.bp_upsample_points.argtypes = [vp, i32, i32, vp, i32, i32, i32, i64, f32, f32, i32, P(BpCamera), vp, vp, vp]
+    L.bp_upsample_points.restype = ctypes.c_int
     L.bp_backward.argtypes = [P(BpProblem), i32, P(BpParams), vp, sz, vp, vp, vp, vp, vp, sz, vp]
     L.bp_backward.restype = ctypes.c_int
     L.bp_backward_workspace_size.argtypes = [P(BpProblem), i32, P(BpParams)]

@@ -509,22 +509,53 @@ bp_status bp_run_profiled(const bp_problem *probs, int32_t count, const bp_param
     return st;
 }
 
-bp_status bp_upsample(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const uint8_t *guide_hi, int32_t w_hi,
-                      int32_t h_hi, int32_t channels, int64_t guide_row_stride, float sigma_s, float sigma_r,
-                      int32_t radius_lo, float *disp_hi, hipStream_t stream)
+static bp_status upsample_args(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const uint8_t *guide_hi,
+                               int32_t w_hi, int32_t h_hi, int32_t channels, int64_t guide_row_stride, float sigma_s,
+                               float sigma_r, int32_t radius_lo, int *R)
 {
-    if (!disp_lo || !guide_hi || !disp_hi || w_lo <= 0 || h_lo <= 0 || w_hi <= 0 || h_hi <= 0)
-        return BP_ERR_INVALID_ARGUMENT;
+    if (!disp_lo || !guide_hi || w_lo <= 0 || h_lo <= 0 || w_hi <= 0 || h_hi <= 0) return BP_ERR_INVALID_ARGUMENT;
     if ((channels != 1 && channels != 3) || guide_row_stride < (int64_t)w_hi * channels) return BP_ERR_INVALID_ARGUMENT;
     if (w_hi % w_lo || h_hi % h_lo || w_hi / w_lo != h_hi / h_lo) return BP_ERR_INVALID_ARGUMENT;
     if (!(sigma_s > 0.0f) || !(sigma_r > 0.0f) || !std::isfinite(sigma_s) || !std::isfinite(sigma_r))
         return BP_ERR_INVALID_ARGUMENT;
     const int s = w_hi / w_lo;
-    int R = radius_lo < 0 ? (int)std::ceil(2.0 * sigma_s / s) : radius_lo;
-    if (R > 8) return BP_ERR_UNSUPPORTED;
+    *R = radius_lo < 0 ? (int)std::ceil(2.0 * sigma_s / s) : radius_lo;
+    if (*R > 8) return BP_ERR_UNSUPPORTED;
+    return BP_OK;
+}
+
+bp_status bp_upsample(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const uint8_t *guide_hi, int32_t w_hi,
+                      int32_t h_hi, int32_t channels, int64_t guide_row_stride, float sigma_s, float sigma_r,
+                      int32_t radius_lo, float *disp_hi, hipStream_t stream)
+{
+    if (!disp_hi) return BP_ERR_INVALID_ARGUMENT;
+    int R = 0;
+    const bp_status st = upsample_args(disp_lo, w_lo, h_lo, guide_hi, w_hi, h_hi, channels, guide_row_stride, sigma_s,
+                                       sigma_r, radius_lo, &R);
+    if (st != BP_OK) return st;
     (void)hipGetLastError();
     return launch_upsample(disp_lo, w_lo, h_lo, guide_hi, w_hi, h_hi, channels, guide_row_stride, sigma_s, sigma_r,
-                           R, disp_hi, stream);
+                           R, disp_hi, nullptr, nullptr, stream);
+}
+
+bp_status bp_upsample_points(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const uint8_t *guide_hi,
+                             int32_t w_hi, int32_t h_hi, int32_t channels, int64_t guide_row_stride, float sigma_s,
+                             float sigma_r, int32_t radius_lo, const bp_camera *camera, float *disp_hi, float *points,
+                             hipStream_t stream)
+{
+    if (!camera || !points) return BP_ERR_INVALID_ARGUMENT;
+    const bp_camera &c = *camera;
+    if (!std::isfinite(c.baseline) || !(c.focal > 0.0f) || !(c.du > 0.0f) || !(c.dv > 0.0f) ||
+        !std::isfinite(c.focal) || !std::isfinite(c.du) || !std::isfinite(c.dv) || !std::isfinite(c.u0) ||
+        !std::isfinite(c.v0))
+        return BP_ERR_INVALID_ARGUMENT;
+    int R = 0;
+    const bp_status st = upsample_args(disp_lo, w_lo, h_lo, guide_hi, w_hi, h_hi, channels, guide_row_stride, sigma_s,
+                                       sigma_r, radius_lo, &R);
+    if (st != BP_OK) return st;
+    (void)hipGetLastError();
+    return launch_upsample(disp_lo, w_lo, h_lo, guide_hi, w_hi, h_hi, channels, guide_row_stride, sigma_s, sigma_r,
+                           R, disp_hi, camera, points, stream);
 }
 
 // Backward workspace: per problem its forward plan (cost + a message state

@@ -102,9 +102,9 @@ bp_status launch_readout(const Plan &p, int colour_mask, int32_t *disp, float *s
 bp_status launch_export(const Plan &p, float *out, uint8_t *ws, hipStream_t s);
 
 // a7: joint bilateral upsampling.
-bp_status launch_upsample(const int32_t *disp_lo, int wl, int hl, const uint8_t *guide, int wh, int hh,
-                          int ch, int64_t stride, float sigma_s, float sigma_r, int radius, float *out,
-                          hipStream_t s);
+bp_status launch_upsample(const int32_t *disp_lo, int wl, int hl, const uint8_t *guide, int wh, int hh, int ch,
+                          int64_t stride, float sigma_s, float sigma_r, int radius, float *out, const bp_camera *cam,
+                          float *xyz, hipStream_t s);
 
 // Label-major half-sweep variants: count for a label count and the variant's
 // lanes per pixel (1, 2 or 4); variant 0 = default.

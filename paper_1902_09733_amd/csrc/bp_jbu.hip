@@ -1,4 +1,5 @@
-// a7 on gfx950: joint bilateral upsampling of the disparity (Eq. 2).
+// a7 on gfx950: joint bilateral upsampling of the disparity (Eq. 2), with an
+// optional fused triangulation of every output pixel (Eq. 3).
 //
 // A 256-thread block owns 16 x 16 full-resolution pixels.  The low-resolution
 // taps every pixel of the block can reach (disparity and the guide sample
@@ -29,10 +30,18 @@ __device__ __forceinline__ uint32_t guide_px(const uint8_t *__restrict__ g, int6
     else return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
 }
 
-template <int R, int C>
+// Eq. 3 epilogue: the camera-frame point of a full-resolution pixel (u, v)
+// with disparity d = s * D_p pixels is (B / d) [u - u0, (v - v0) dv / du, f / du]
+// (the last entry from Eq. 3's projection, d = f B / (z du)); NaN where d <= 0.
+struct PointArgs {
+    float *xyz;                 // [hh][wh][3], or NULL
+    float baseline, f_du, dv_du, u0, v0;
+};
+
+template <int R, int C, bool PTS>
 __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, int wl, int hl,
                                             const uint8_t *__restrict__ guide, int wh, int hh, int64_t stride,
-                                            int s, float ksp, float krg, float *__restrict__ out)
+                                            int s, float ksp, float krg, float *__restrict__ out, PointArgs pa)
 {
     __shared__ float t_d[kMaxTap * kMaxTap];
     // Per tap: packed guide colour and |I_q|^2 (+inf outside the grid, which
@@ -104,21 +113,51 @@ __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, i
             num = fmaf(w, t_d[(oy + dy) * kMaxTap + ox + dx], num);
             den += w;
         }
-    out[(int64_t)py * wh + px] = num / den;
+    const float dp = num / den;
+    if (out) out[(int64_t)py * wh + px] = dp;
+    if constexpr (PTS) {
+        const float d = (float)s * dp;
+        float x = __builtin_nanf(""), y = x, z = x;
+        if (d > 0.0f) {
+            const float k = pa.baseline / d;
+            x = k * ((float)px - pa.u0);
+            y = k * ((float)py - pa.v0) * pa.dv_du;
+            z = k * pa.f_du;
+        }
+        float *o = pa.xyz + ((int64_t)py * wh + px) * 3;
+        o[0] = x;
+        o[1] = y;
+        o[2] = z;
+    }
 }
 
 bp_status launch_upsample(const int32_t *disp_lo, int wl, int hl, const uint8_t *guide, int wh, int hh, int ch,
-                          int64_t stride, float sigma_s, float sigma_r, int radius, float *out, hipStream_t st)
+                          int64_t stride, float sigma_s, float sigma_r, int radius, float *out, const bp_camera *cam,
+                          float *xyz, hipStream_t st)
 {
     const int s = wh / wl;
     const float log2e = 1.4426950408889634f;
     const float ksp = log2e / (2.0f * sigma_s * sigma_s);
     const float krg = log2e / (2.0f * sigma_r * sigma_r);
+    PointArgs pa{xyz, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (cam) {
+        pa.baseline = cam->baseline;
+        pa.f_du = cam->focal / cam->du;
+        pa.dv_du = cam->dv / cam->du;
+        pa.u0 = cam->u0;
+        pa.v0 = cam->v0;
+    }
+    const bool pts = xyz != nullptr;
     dim3 grid((wh + kTile - 1) / kTile, (hh + kTile - 1) / kTile);
-#define BP_JBU_CASE(RV)                                                                                   \
-    case RV:                                                                                              \
-        if (ch == 1) k_jbu<RV, 1><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, ksp, krg, out); \
-        else k_jbu<RV, 3><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, ksp, krg, out);       \
+#define BP_JBU_CASE(RV)                                                                                       \
+    case RV:                                                                                                  \
+        if (ch == 1) {                                                                                        \
+            if (pts) k_jbu<RV, 1, true><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, ksp, krg, out, pa); \
+            else k_jbu<RV, 1, false><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, ksp, krg, out, pa);    \
+        } else {                                                                                              \
+            if (pts) k_jbu<RV, 3, true><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, ksp, krg, out, pa); \
+            else k_jbu<RV, 3, false><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, ksp, krg, out, pa);    \
+        }                                                                                                     \
         break;
     switch (radius) {
         BP_JBU_CASE(0)

@@ -264,5 +264,43 @@ def upsample(disp_lo: torch.Tensor, guide: torch.Tensor, sigma_s: float = 8.0, s
     return out
 
 
+@dataclass
+class Camera:
+    """Pinhole camera of the full-resolution frame (Eq. 3): baseline B, focal
+    length f and pixel pitch du, dv in one length unit, principal point (u0, v0)
+    in pixels."""
+    baseline: float
+    focal: float
+    du: float
+    dv: float
+    u0: float
+    v0: float
+
+    def c(self):
+        return _abi.BpCamera(self.baseline, self.focal, self.du, self.dv, self.u0, self.v0)
+
+
+def upsample_points(disp_lo: torch.Tensor, guide: torch.Tensor, camera: Camera, sigma_s: float = 8.0,
+                    sigma_r: float = 12.0, radius: int = -1, want_disp: bool = True, out=None, stream=None):
+    """Joint bilateral upsampling fused with triangulation (Eq. 2 + Eq. 3).
+    Returns (disp_hi float32 [H][W] or None, points float32 [H][W][3])."""
+    _need_gpu(disp_lo, guide)
+    if disp_lo.dtype != torch.int32 or guide.dtype != torch.uint8:
+        raise ValueError("disp_lo must be int32 and guide u8")
+    hl, wl = disp_lo.shape
+    w, h, c = _img_dims(guide)
+    disp_hi, pts = out if out is not None else (None, None)
+    if want_disp and disp_hi is None:
+        disp_hi = torch.empty((h, w), dtype=torch.float32, device=guide.device)
+    if pts is None:
+        pts = torch.empty((h, w, 3), dtype=torch.float32, device=guide.device)
+    cam = camera.c()
+    st = _abi.lib().bp_upsample_points(_ptr(disp_lo), wl, hl, _ptr(guide), w, h, c, w * c, float(sigma_s),
+                                       float(sigma_r), int(radius), ctypes.byref(cam),
+                                       _ptr(disp_hi) if want_disp else None, _ptr(pts), _stream(stream))
+    _abi.check("bp_upsample_points", st)
+    return (disp_hi if want_disp else None), pts
+
+
 def variant_count(num_labels: int) -> int:
     return _abi.lib().bp_variant_count(num_labels)

@@ -146,3 +146,17 @@ def test_tune_table_loading(lib, tmp_path):
     assert lib.bp_load_tune_table(str(t).encode()) == 0
     assert lib.bp_load_tune_table(str(tmp_path / "missing.txt").encode()) == _abi.BP_ERR_INVALID_ARGUMENT
     assert lib.bp_load_tune_table(None) == 0
+
+
+def test_upsample_points_validation(lib):
+    """bp_upsample_points rejects a missing or degenerate camera before any launch."""
+    cam_ok = dict(baseline=0.5, focal=3e-3, du=1.5e-6, dv=1.5e-6, u0=10.0, v0=8.0)
+    args = lambda cam, pts: (ctypes.c_void_p(256), 4, 4, ctypes.c_void_p(512), 16, 16, 1, 16, 8.0, 12.0, -1,
+                             cam, None, pts, None)
+    assert lib.bp_upsample_points(*args(None, ctypes.c_void_p(1024))) == _abi.BP_ERR_INVALID_ARGUMENT
+    c = _abi.BpCamera(**cam_ok)
+    assert lib.bp_upsample_points(*args(ctypes.byref(c), None)) == _abi.BP_ERR_INVALID_ARGUMENT
+    for bad in (dict(focal=0.0), dict(du=-1.0), dict(dv=0.0), dict(u0=float("inf")), dict(baseline=float("nan"))):
+        cb = _abi.BpCamera(**dict(cam_ok, **bad))
+        assert lib.bp_upsample_points(*args(ctypes.byref(cb), ctypes.c_void_p(1024))) == \
+            _abi.BP_ERR_INVALID_ARGUMENT, bad

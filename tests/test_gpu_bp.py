@@ -272,6 +272,38 @@ def test_aerial_full_pipeline_exact(dev, aerial_full):
     assert err <= 2e-3, err
 
 
+# ---------------------------------------------------------------- triangulation (Eq. 3)
+
+CAM = dict(baseline=0.5, focal=3.0e-3, du=1.5e-6, dv=1.6e-6, u0=1352.0, v0=760.0)
+
+
+@pytest.mark.parametrize("s,R,ch", [(4, -1, 3), (2, 3, 1), (3, 0, 3)])
+def test_upsample_points(dev, s, R, ch):
+    """The fused epilogue: the disparity equals bp_upsample's bit for bit, the
+    points equal the oracle's Eq. 3 applied to that disparity (FP32 rounding:
+    a few ulps), and zero disparities give NaN."""
+    bp = bp_mod()
+    wl, hl = 61, 37
+    rng = np.random.default_rng(s * 10 + ch)
+    d_lo = rng.integers(0, 40, size=(hl, wl)).astype(np.int32)
+    d_lo[:20, :20] = 0          # a region whose windows see only zero disparity
+    shape = (hl * s, wl * s) + ((3,) if ch == 3 else ())
+    guide_np = rng.integers(0, 256, size=shape, dtype=np.uint8)
+    dl, guide = torch.from_numpy(d_lo).to(dev), torch.from_numpy(guide_np).to(dev)
+    cam = bp.Camera(**CAM)
+    up = bp.upsample(dl, guide, 8.0, 12.0, R)
+    disp_hi, pts = bp.upsample_points(dl, guide, cam, 8.0, 12.0, R)
+    _, pts2 = bp.upsample_points(dl, guide, cam, 8.0, 12.0, R, want_disp=False)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(disp_hi.cpu().numpy(), up.cpu().numpy())
+    np.testing.assert_array_equal(pts2.cpu().numpy(), pts.cpu().numpy())
+    g = pts.cpu().numpy().astype(np.float64)
+    ref = oracle.triangulate(disp_hi.cpu().numpy().astype(np.float64), s, **CAM)
+    np.testing.assert_allclose(g, ref, rtol=2e-6, atol=1e-9)
+    zero = disp_hi.cpu().numpy() <= 0
+    assert zero.any() and np.isnan(g[zero]).all() and np.isfinite(g[~zero]).all()
+
+
 # ---------------------------------------------------------------- data term from the pair
 
 @pytest.mark.parametrize("w,h,ch,s,mode,L,pm_from", [
