@@ -49,6 +49,7 @@ def lib():
         L.bpo_pyramid.argtypes = [_dp, i, i, i, i, _dp]
         L.bpo_upsample.argtypes = [_i32p, i, i, _u8p, i, i, i, d, d, i, _dp, i]
         L.bpo_triangulate.argtypes = [_dp, i, i, d, d, d, d, d, d, d, _dp]
+        L.bpo_undistort.argtypes = [_u8p, i, i, i, ctypes.POINTER(ctypes.c_float), _u8p]
         L.bpo_round_f16.argtypes = [d]
         L.bpo_round_f16.restype = d
         L.bpo_round_bf16.argtypes = [d]
@@ -159,6 +160,16 @@ def triangulate(disp, scale: float, baseline: float, focal: float, du: float, dv
     out = np.empty((h, w, 3), dtype=np.float64)
     _check(lib().bpo_triangulate(_p(dd, _dp), w, h, float(scale), float(baseline), float(focal), float(du),
                                  float(dv), float(u0), float(v0), _p(out, _dp)), "triangulate")
+    return out
+
+
+def undistort(img, fx: float, fy: float, cx: float, cy: float, k1: float = 0.0, k2: float = 0.0, k3: float = 0.0):
+    """Radial-only undistortion with bilinear sampling (Sec. 2.1), u8 in, u8 out."""
+    g, h, w, C = _img(img)
+    K = np.array([fx, fy, cx, cy, k1, k2, k3], dtype=np.float32)
+    out = np.empty_like(g)
+    _check(lib().bpo_undistort(_p(g, _u8p), w, h, C, K.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                               _p(out, _u8p)), "undistort")
     return out
 
 
