@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--volume", action="store_true",
                     help="materialise the planar cost volume with bp_cost_volume inside the step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint", "points", "counters"],
+    ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint", "points", "undistort",
+                                                  "counters"],
                     help="pair: the benchmarked single-pair path (default); batch, precision, adjoint "
                          "measure the other forms; points the JBU with fused triangulation; counters "
                          "runs the pair path eagerly plus a plain copy of known size, for rocprofv3 "
@@ -469,6 +470,37 @@ def form_points(args):
             "epilogue_us": round((t_pts - t_jbu) * 1e3, 2)}
 
 
+def form_undistort(args):
+    """Radial-only undistortion of both 2704x1520 RGB frames of the benchmarked
+    pair (HIP events on the current stream; 2 x 12.3 MB read, 2 x 12.3 MB written)."""
+    import torch
+
+    import paper_1902_09733_amd as bp
+    from synth import workload
+    wl = workload("aerial2704x1520_s4_L64")
+    dev = torch.device("cuda:0")
+    left = torch.from_numpy(wl["left"]).to(dev)
+    right = torch.from_numpy(wl["right"]).to(dev)
+    K = bp.Intrinsics(1600.0, 1600.0, 1351.5, 759.5, -0.12, 0.02, -0.001)
+    lo, ro = torch.empty_like(left), torch.empty_like(right)
+
+    def step():
+        bp.undistort(left, K, out=lo)
+        bp.undistort(right, K, out=ro)
+    step()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 50
+    e0.record()
+    for _ in range(reps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 4 * left.numel()
+    return {"form": "undistort", "workload": "aerial2704x1520 RGB pair", "pair_ms": round(ms, 4),
+            "per_frame_us": round(ms * 500, 2), "GBps_algorithmic": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
 def form_counters(args):
     """The pair path three times without a graph (every dispatch visible to a
     counter pass), then three plain device-to-device copies of 256 MiB."""
@@ -497,7 +529,7 @@ def form_counters(args):
 
 def run_form(form, args):
     return {"batch": form_batch, "precision": form_precision, "adjoint": form_adjoint, "points": form_points,
-            "counters": form_counters}[form](args)
+            "undistort": form_undistort, "counters": form_counters}[form](args)
 
 
 if __name__ == "__main__":

@@ -126,6 +126,34 @@ bp_status bp_cost_volume(const uint8_t *left, const uint8_t *right, int32_t widt
                          int32_t num_labels, float data_trunc, int32_t rgb_mode, float *cost,
                          hipStream_t stream);
 
+/* Intrinsics of the distorted frame: pinhole focal lengths and principal point
+ * in pixels, radial distortion coefficients (no tangential terms, Sec. 2.1). */
+typedef struct {
+    float fx, fy;     /* > 0 */
+    float cx, cy;
+    float k1, k2, k3;
+} bp_intrinsics;
+
+/*
+ * Undistortion before matching (Sec. 2.1: radial-only model, every frame
+ * undistorted and remapped).  Output pixel (u, v) = (column, row) samples
+ * the input at
+ *   xn = (u - cx) / fx, yn = (v - cy) / fy, r2 = xn^2 + yn^2,
+ *   g = 1 + k1 r2 + k2 r2^2 + k3 r2^3,  (us, vs) = (cx + (u - cx) g, cy + (v - cy) g)
+ * by bilinear interpolation of each channel, rounded half up; 0 where
+ * (us, vs) lies outside [0, width-1] x [0, height-1].  Evaluated in FP32
+ * with every operation rounded separately (1/fx and 1/fy once, as the
+ * reciprocals in float), Horner form for g.  Zero coefficients reproduce the
+ * input exactly.
+ *   in, out   device images [height][stride] bytes, `channels` (1 or 3)
+ *             interleaved u8 samples per pixel; must not overlap
+ * Errors: BP_ERR_INVALID_ARGUMENT for NULL pointers, non-positive sizes,
+ * channels not 1/3, strides < width * channels, non-finite intrinsics or
+ * fx, fy not positive.
+ */
+bp_status bp_undistort(const uint8_t *in, int32_t width, int32_t height, int32_t channels, int64_t in_stride,
+                       const bp_intrinsics *intrinsics, uint8_t *out, int64_t out_stride, hipStream_t stream);
+
 /*
  * a1 alone: s x s block mean rounded half up, out [height/s][width/s][channels]
  * packed.  Same argument rules as bp_cost_volume.

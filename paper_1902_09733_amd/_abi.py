@@ -43,6 +43,10 @@ class BpProblem(ctypes.Structure):
     ]
 
 
+class BpIntrinsics(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in ("fx", "fy", "cx", "cy", "k1", "k2", "k3")]
+
+
 class BpCamera(ctypes.Structure):
     _fields_ = [
         ("baseline", ctypes.c_float),
@@ -115,6 +119,8 @@ def lib():
     L.bp_run_profiled.restype = ctypes.c_int
     L.bp_upsample.argtypes = [vp, i32, i32, vp, i32, i32, i32, i64, f32, f32, i32, vp, vp]
     L.bp_upsample.restype = ctypes.c_int
+    L.bp_undistort.argtypes = [vp, i32, i32, i32, i64, P(BpIntrinsics), vp, i64, vp]
+    L.bp_undistort.restype = ctypes.c_int
     L.bp_upsample_points.argtypes = [vp, i32, i32, vp, i32, i32, i32, i64, f32, f32, i32, P(BpCamera), vp, vp, vp]
     L.bp_upsample_points.restype = ctypes.c_int
     L.bp_backward.argtypes = [P(BpProblem), i32, P(BpParams), vp, sz, vp, vp, vp, vp, vp, sz, vp]

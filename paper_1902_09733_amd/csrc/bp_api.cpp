@@ -509,6 +509,21 @@ bp_status bp_run_profiled(const bp_problem *probs, int32_t count, const bp_param
     return st;
 }
 
+bp_status bp_undistort(const uint8_t *in, int32_t width, int32_t height, int32_t channels, int64_t in_stride,
+                       const bp_intrinsics *intrinsics, uint8_t *out, int64_t out_stride, hipStream_t stream)
+{
+    if (!in || !out || !intrinsics || width <= 0 || height <= 0 || (channels != 1 && channels != 3))
+        return BP_ERR_INVALID_ARGUMENT;
+    if (in_stride < (int64_t)width * channels || out_stride < (int64_t)width * channels) return BP_ERR_INVALID_ARGUMENT;
+    const bp_intrinsics &K = *intrinsics;
+    const float vals[7] = {K.fx, K.fy, K.cx, K.cy, K.k1, K.k2, K.k3};
+    for (float x : vals)
+        if (!std::isfinite(x)) return BP_ERR_INVALID_ARGUMENT;
+    if (!(K.fx > 0.0f) || !(K.fy > 0.0f)) return BP_ERR_INVALID_ARGUMENT;
+    (void)hipGetLastError();
+    return launch_undistort(in, width, height, channels, in_stride, K, out, out_stride, stream);
+}
+
 static bp_status upsample_args(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const uint8_t *guide_hi,
                                int32_t w_hi, int32_t h_hi, int32_t channels, int64_t guide_row_stride, float sigma_s,
                                float sigma_r, int32_t radius_lo, int *R)

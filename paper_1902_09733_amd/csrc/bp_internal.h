@@ -102,6 +102,8 @@ bp_status launch_readout(const Plan &p, int colour_mask, int32_t *disp, float *s
 bp_status launch_export(const Plan &p, float *out, uint8_t *ws, hipStream_t s);
 
 // a7: joint bilateral upsampling.
+bp_status launch_undistort(const uint8_t *in, int w, int h, int ch, int64_t in_stride, const bp_intrinsics &K,
+                           uint8_t *out, int64_t out_stride, hipStream_t s);
 bp_status launch_upsample(const int32_t *disp_lo, int wl, int hl, const uint8_t *guide, int wh, int hh, int ch,
                           int64_t stride, float sigma_s, float sigma_r, int radius, float *out, const bp_camera *cam,
                           float *xyz, hipStream_t s);

@@ -265,6 +265,36 @@ def upsample(disp_lo: torch.Tensor, guide: torch.Tensor, sigma_s: float = 8.0, s
 
 
 @dataclass
+class Intrinsics:
+    """Distorted-frame intrinsics (pixels) with radial coefficients only."""
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    k1: float = 0.0
+    k2: float = 0.0
+    k3: float = 0.0
+
+    def c(self):
+        return _abi.BpIntrinsics(self.fx, self.fy, self.cx, self.cy, self.k1, self.k2, self.k3)
+
+
+def undistort(img: torch.Tensor, intrinsics: Intrinsics, out: torch.Tensor | None = None, stream=None):
+    """Radial-only undistortion with bilinear sampling of a u8 [H][W] or [H][W][3] frame."""
+    _need_gpu(img)
+    if img.dtype != torch.uint8:
+        raise ValueError("undistort works on u8 images")
+    w, h, c = _img_dims(img)
+    if out is None:
+        out = torch.empty_like(img)
+    _need_gpu(out)
+    K = intrinsics.c()
+    st = _abi.lib().bp_undistort(_ptr(img), w, h, c, w * c, ctypes.byref(K), _ptr(out), w * c, _stream(stream))
+    _abi.check("bp_undistort", st)
+    return out
+
+
+@dataclass
 class Camera:
     """Pinhole camera of the full-resolution frame (Eq. 3): baseline B, focal
     length f and pixel pitch du, dv in one length unit, principal point (u0, v0)
