@@ -50,6 +50,10 @@ def lib():
         L.bpo_upsample.argtypes = [_i32p, i, i, _u8p, i, i, i, d, d, i, _dp, i]
         L.bpo_triangulate.argtypes = [_dp, i, i, d, d, d, d, d, d, d, _dp]
         L.bpo_undistort.argtypes = [_u8p, i, i, i, ctypes.POINTER(ctypes.c_float), _u8p]
+        _i64p = ctypes.POINTER(ctypes.c_int64)
+        L.bpo_harris_response.argtypes = [_u8p, i, i, _i64p]
+        L.bpo_harris_cells.argtypes = [_i64p, i, i, i, ctypes.c_int64, _i64p]
+        L.bpo_zssd_match.argtypes = [_u8p, _u8p, i, i, _i64p, i, i, i, _i64p]
         L.bpo_round_f16.argtypes = [d]
         L.bpo_round_f16.restype = d
         L.bpo_round_bf16.argtypes = [d]
@@ -170,6 +174,41 @@ def undistort(img, fx: float, fy: float, cx: float, cy: float, k1: float = 0.0, 
     out = np.empty_like(g)
     _check(lib().bpo_undistort(_p(g, _u8p), w, h, C, K.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                _p(out, _u8p)), "undistort")
+    return out
+
+
+def harris_response(img):
+    """25 R of Eq. 5 (k = 1/25) per pixel of a grey u8 frame, int64 [H][W]."""
+    g, h, w, C = _img(img)
+    if C != 1:
+        raise ValueError("grey frames only")
+    out = np.empty((h, w), dtype=np.int64)
+    _check(lib().bpo_harris_response(_p(g, _u8p), w, h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+           "harris_response")
+    return out
+
+
+def harris_cells(r25, grid: int = 30, threshold: int = 0):
+    """Per-cell corners of a g x g grid: int64 [g*g][3] (x, y, 25 R); x = -1 if none."""
+    r = np.ascontiguousarray(r25, dtype=np.int64)
+    h, w = r.shape
+    out = np.empty((grid * grid, 3), dtype=np.int64)
+    P = ctypes.POINTER(ctypes.c_int64)
+    _check(lib().bpo_harris_cells(r.ctypes.data_as(P), w, h, grid, int(threshold), out.ctypes.data_as(P)),
+           "harris_cells")
+    return out
+
+
+def zssd_match(a, b, corners, patch_radius: int, search_radius: int):
+    """ZSSD matches of the corners (rows x, y, ...) of frame a in frame b:
+    int64 [n][3] (x2, y2, n_pix * ZSSD); x2 = -1 if none."""
+    ga, h, w, _ = _img(a)
+    gb, _, _, _ = _img(b)
+    c = np.ascontiguousarray(corners, dtype=np.int64)
+    out = np.empty((c.shape[0], 3), dtype=np.int64)
+    P = ctypes.POINTER(ctypes.c_int64)
+    _check(lib().bpo_zssd_match(_p(ga, _u8p), _p(gb, _u8p), w, h, c.ctypes.data_as(P), c.shape[0],
+                                int(patch_radius), int(search_radius), out.ctypes.data_as(P)), "zssd_match")
     return out
 
 

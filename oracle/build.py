@@ -10,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["bp_oracle.c", "bp_oracle_adjoint.c", "bp_oracle_remap.c"]
+SOURCES = ["bp_oracle.c", "bp_oracle_adjoint.c", "bp_oracle_remap.c", "bp_oracle_features.c"]
 LIB = os.path.join(HERE, "libbp_oracle.so")
 
 
