@@ -44,7 +44,7 @@ def parse():
                     help="materialise the planar cost volume with bp_cost_volume inside the step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint", "points", "undistort",
-                                                  "counters"],
+                                                  "features", "counters"],
                     help="pair: the benchmarked single-pair path (default); batch, precision, adjoint "
                          "measure the other forms; points the JBU with fused triangulation; counters "
                          "runs the pair path eagerly plus a plain copy of known size, for rocprofv3 "
@@ -501,6 +501,41 @@ def form_undistort(args):
             "per_frame_us": round(ms * 500, 2), "GBps_algorithmic": round(nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
+def form_features(args):
+    """Harris response + 30 x 30 cell corners of the benchmarked pair's left
+    frame (grey 2704x1520), then ZSSD matches (11 x 11 patches, +-16 px) of
+    those corners in the right frame; HIP events on the current stream."""
+    import torch
+
+    import paper_1902_09733_amd as bp
+    from synth import workload
+    wl = workload("aerial2704x1520_s4_L64")
+    dev = torch.device("cuda:0")
+
+    def grey(rgb):
+        return ((rgb[..., 0].astype(np.int32) * 77 + rgb[..., 1].astype(np.int32) * 150 +
+                 rgb[..., 2].astype(np.int32) * 29) >> 8).astype(np.uint8)
+    a = torch.from_numpy(grey(wl["left"])).to(dev)
+    b = torch.from_numpy(grey(wl["right"])).to(dev)
+    thr = 2 * 10 ** 7
+
+    def ev_time(fn, reps=20):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    out = bp.harris(a, 30, thr)
+    t_h = ev_time(lambda: bp.harris(a, 30, thr))
+    t_m = ev_time(lambda: bp.zssd_match(a, b, out["raw"], 5, 16))
+    found = int((out["x"] >= 0).sum().item())
+    return {"form": "features", "workload": "aerial2704x1520 grey pair, 30x30 cells", "harris_ms": round(t_h, 4),
+            "zssd_ms": round(t_m, 4), "corners": found, "zssd_shifts_per_corner": 33 * 33, "patch": "11x11"}
+
+
 def form_counters(args):
     """The pair path three times without a graph (every dispatch visible to a
     counter pass), then three plain device-to-device copies of 256 MiB."""
@@ -529,7 +564,7 @@ def form_counters(args):
 
 def run_form(form, args):
     return {"batch": form_batch, "precision": form_precision, "adjoint": form_adjoint, "points": form_points,
-            "undistort": form_undistort, "counters": form_counters}[form](args)
+            "undistort": form_undistort, "features": form_features, "counters": form_counters}[form](args)
 
 
 if __name__ == "__main__":

@@ -154,6 +154,59 @@ typedef struct {
 bp_status bp_undistort(const uint8_t *in, int32_t width, int32_t height, int32_t channels, int64_t in_stride,
                        const bp_intrinsics *intrinsics, uint8_t *out, int64_t out_stride, hipStream_t stream);
 
+/* A selected Harris corner: pixel and its response 25 R (Eq. 5 with
+ * k = 1/25, an exact integer); x = y = -1 for a cell without a corner. */
+typedef struct {
+    int32_t x, y;
+    int64_t response;
+} bp_corner;
+
+/* A ZSSD match: pixel of the second frame and its cost n * ZSSD (n patch
+ * pixels, an exact integer); x = y = -1 when there is none. */
+typedef struct {
+    int32_t x, y;
+    int64_t cost;
+} bp_match;
+
+/*
+ * Harris corners of a grey frame (Sec. 2.3, Eq. 4-5, and the experiments' g x g
+ * grid of cells with a hard threshold), in exact integers:
+ *   A = I(x+1,y) - I(x-1,y), B = I(x,y+1) - I(x,y-1); M = sum w [A^2 AB; AB B^2]
+ *   over the 5 x 5 binomial window w = (1 4 6 4 1)^T (1 4 6 4 1);
+ *   response = 25 R = 25 det M - tr(M)^2 (k = 1/25), 0 within 3 pixels of
+ *   the border.
+ * Cell (i, j) covers columns [floor(j W/g), floor((j+1) W/g)) and rows
+ * likewise; its corner is the pixel of largest response above `threshold`
+ * among the 3 x 3 local maxima (no neighbour larger), first in row-major
+ * order on ties.
+ *   img        device u8 [height][stride]
+ *   response   device int64 [height][width], written fully (the response map)
+ *   corners    device bp_corner [grid * grid], cell (i, j) at i * grid + j
+ * Errors: BP_ERR_INVALID_ARGUMENT for NULL pointers, non-positive sizes,
+ * stride < width, grid outside [1, 1024].
+ */
+bp_status bp_harris(const uint8_t *img, int32_t width, int32_t height, int64_t stride, int32_t grid,
+                    int64_t threshold, int64_t *response, bp_corner *corners, hipStream_t stream);
+
+/*
+ * ZSSD patch matching of corners of frame a in frame b (Sec. 2.3: a patch
+ * around every corner, compared within a search range by zero-mean SSD):
+ * cost = n sum (a - b)^2 - (sum a - sum b)^2 over (2 patch_radius + 1)^2 = n
+ * pixels, i.e. n * ZSSD.  The match is the shift in [-search_radius,
+ * search_radius]^2 whose patch lies inside frame b with the smallest cost,
+ * the first in row-major (dy, dx) order on ties; none (-1) for a corner with
+ * x < 0 or whose own patch leaves frame a.
+ *   a, b       device u8 [height][stride], the two frames
+ *   corners    device bp_corner [n] (e.g. from bp_harris)
+ *   matches    device bp_match [n]
+ * Errors: BP_ERR_INVALID_ARGUMENT for NULL pointers, non-positive sizes,
+ * stride < width, n < 0, patch_radius outside [0, 15], search_radius
+ * outside [0, 32].
+ */
+bp_status bp_zssd_match(const uint8_t *a, const uint8_t *b, int32_t width, int32_t height, int64_t stride,
+                        const bp_corner *corners, int32_t n, int32_t patch_radius, int32_t search_radius,
+                        bp_match *matches, hipStream_t stream);
+
 /*
  * a1 alone: s x s block mean rounded half up, out [height/s][width/s][channels]
  * packed.  Same argument rules as bp_cost_volume.

@@ -43,6 +43,14 @@ class BpProblem(ctypes.Structure):
     ]
 
 
+class BpCorner(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_int32), ("y", ctypes.c_int32), ("response", ctypes.c_int64)]
+
+
+class BpMatch(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_int32), ("y", ctypes.c_int32), ("cost", ctypes.c_int64)]
+
+
 class BpIntrinsics(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in ("fx", "fy", "cx", "cy", "k1", "k2", "k3")]
 
@@ -119,6 +127,10 @@ def lib():
     L.bp_run_profiled.restype = ctypes.c_int
     L.bp_upsample.argtypes = [vp, i32, i32, vp, i32, i32, i32, i64, f32, f32, i32, vp, vp]
     L.bp_upsample.restype = ctypes.c_int
+    L.bp_harris.argtypes = [vp, i32, i32, i64, i32, i64, vp, vp, vp]
+    L.bp_harris.restype = ctypes.c_int
+    L.bp_zssd_match.argtypes = [vp, vp, i32, i32, i64, vp, i32, i32, i32, vp, vp]
+    L.bp_zssd_match.restype = ctypes.c_int
     L.bp_undistort.argtypes = [vp, i32, i32, i32, i64, P(BpIntrinsics), vp, i64, vp]
     L.bp_undistort.restype = ctypes.c_int
     L.bp_upsample_points.argtypes = [vp, i32, i32, vp, i32, i32, i32, i64, f32, f32, i32, P(BpCamera), vp, vp, vp]

@@ -509,6 +509,26 @@ bp_status bp_run_profiled(const bp_problem *probs, int32_t count, const bp_param
     return st;
 }
 
+bp_status bp_harris(const uint8_t *img, int32_t width, int32_t height, int64_t stride, int32_t grid, int64_t threshold,
+                    int64_t *response, bp_corner *corners, hipStream_t stream)
+{
+    if (!img || !response || !corners || width <= 0 || height <= 0 || stride < width) return BP_ERR_INVALID_ARGUMENT;
+    if (grid < 1 || grid > 1024) return BP_ERR_INVALID_ARGUMENT;
+    (void)hipGetLastError();
+    return launch_harris(img, width, height, stride, grid, threshold, response, corners, stream);
+}
+
+bp_status bp_zssd_match(const uint8_t *a, const uint8_t *b, int32_t width, int32_t height, int64_t stride,
+                        const bp_corner *corners, int32_t n, int32_t patch_radius, int32_t search_radius,
+                        bp_match *matches, hipStream_t stream)
+{
+    if (!a || !b || (n > 0 && (!corners || !matches)) || width <= 0 || height <= 0 || stride < width || n < 0)
+        return BP_ERR_INVALID_ARGUMENT;
+    if (patch_radius < 0 || patch_radius > 15 || search_radius < 0 || search_radius > 32) return BP_ERR_INVALID_ARGUMENT;
+    (void)hipGetLastError();
+    return launch_zssd(a, b, width, height, stride, corners, n, patch_radius, search_radius, matches, stream);
+}
+
 bp_status bp_undistort(const uint8_t *in, int32_t width, int32_t height, int32_t channels, int64_t in_stride,
                        const bp_intrinsics *intrinsics, uint8_t *out, int64_t out_stride, hipStream_t stream)
 {

@@ -102,6 +102,10 @@ bp_status launch_readout(const Plan &p, int colour_mask, int32_t *disp, float *s
 bp_status launch_export(const Plan &p, float *out, uint8_t *ws, hipStream_t s);
 
 // a7: joint bilateral upsampling.
+bp_status launch_harris(const uint8_t *img, int w, int h, int64_t stride, int g, int64_t thr, int64_t *r25,
+                        bp_corner *corners, hipStream_t s);
+bp_status launch_zssd(const uint8_t *a, const uint8_t *b, int w, int h, int64_t stride, const bp_corner *corners,
+                      int n, int pr, int sr, bp_match *out, hipStream_t s);
 bp_status launch_undistort(const uint8_t *in, int w, int h, int ch, int64_t in_stride, const bp_intrinsics &K,
                            uint8_t *out, int64_t out_stride, hipStream_t s);
 bp_status launch_upsample(const int32_t *disp_lo, int wl, int hl, const uint8_t *guide, int wh, int hh, int ch,

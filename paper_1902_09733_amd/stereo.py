@@ -264,6 +264,45 @@ def upsample(disp_lo: torch.Tensor, guide: torch.Tensor, sigma_s: float = 8.0, s
     return out
 
 
+def _records(raw: torch.Tensor):
+    """(x, y, value) views of an array of {int32 x, y; int64 value} records."""
+    v = raw.view(torch.int32).view(-1, 4)
+    return v[:, 0], v[:, 1], v[:, 2:4].contiguous().view(torch.int64).view(-1)
+
+
+def harris(img: torch.Tensor, grid: int = 30, threshold: int = 0, stream=None):
+    """Harris response (25 R, int64 [H][W]) and per-cell corners of a grey u8
+    frame (Eq. 4-5).  Returns a dict: response, x, y, corner_response (the
+    last three with grid*grid entries, x = -1 for a cell without a corner)."""
+    _need_gpu(img)
+    if img.dtype != torch.uint8 or img.dim() != 2:
+        raise ValueError("harris works on grey u8 [H][W] frames")
+    h, w = img.shape
+    resp = torch.empty((h, w), dtype=torch.int64, device=img.device)
+    raw = torch.empty((grid * grid, 2), dtype=torch.int64, device=img.device)
+    st = _abi.lib().bp_harris(_ptr(img), w, h, w, int(grid), int(threshold), _ptr(resp), _ptr(raw), _stream(stream))
+    _abi.check("bp_harris", st)
+    x, y, r = _records(raw)
+    return {"response": resp, "x": x, "y": y, "corner_response": r, "raw": raw}
+
+
+def zssd_match(a: torch.Tensor, b: torch.Tensor, corners_raw: torch.Tensor, patch_radius: int = 5,
+               search_radius: int = 16, stream=None):
+    """ZSSD matches in frame b of the corners (the `raw` records from harris)
+    of frame a.  Returns a dict: x, y, cost (n * ZSSD), x = -1 when none."""
+    _need_gpu(a, b, corners_raw)
+    if a.dtype != torch.uint8 or b.shape != a.shape or a.dim() != 2:
+        raise ValueError("zssd_match works on two grey u8 [H][W] frames of one size")
+    h, w = a.shape
+    n = corners_raw.numel() * corners_raw.element_size() // 16
+    raw = torch.empty((n, 2), dtype=torch.int64, device=a.device)
+    st = _abi.lib().bp_zssd_match(_ptr(a), _ptr(b), w, h, w, _ptr(corners_raw), n, int(patch_radius),
+                                  int(search_radius), _ptr(raw), _stream(stream))
+    _abi.check("bp_zssd_match", st)
+    x, y, c = _records(raw)
+    return {"x": x, "y": y, "cost": c}
+
+
 @dataclass
 class Intrinsics:
     """Distorted-frame intrinsics (pixels) with radial coefficients only."""
