@@ -54,6 +54,9 @@ def lib():
         L.bpo_harris_response.argtypes = [_u8p, i, i, _i64p]
         L.bpo_harris_cells.argtypes = [_i64p, i, i, i, ctypes.c_int64, _i64p]
         L.bpo_zssd_match.argtypes = [_u8p, _u8p, i, i, _i64p, i, i, i, _i64p]
+        _fp = ctypes.POINTER(ctypes.c_float)
+        L.bpo_icp_correspond.argtypes = [_fp, i, _fp, i, _fp, _fp, ctypes.c_float, _fp,
+                                         ctypes.POINTER(ctypes.c_int32), _fp]
         L.bpo_round_f16.argtypes = [d]
         L.bpo_round_f16.restype = d
         L.bpo_round_bf16.argtypes = [d]
@@ -210,6 +213,61 @@ def zssd_match(a, b, corners, patch_radius: int, search_radius: int):
     _check(lib().bpo_zssd_match(_p(ga, _u8p), _p(gb, _u8p), w, h, c.ctypes.data_as(P), c.shape[0],
                                 int(patch_radius), int(search_radius), out.ctypes.data_as(P)), "zssd_match")
     return out
+
+
+def icp_correspond(src, dst, R, T, dmax: float):
+    """One ICP correspondence step in FP32: moved points R p + T, index of the
+    nearest target within dmax (-1 if none, lowest index on ties), and the
+    squared distance."""
+    F = ctypes.POINTER(ctypes.c_float)
+    s = np.ascontiguousarray(src, dtype=np.float32)
+    d = np.ascontiguousarray(dst, dtype=np.float32)
+    r = np.ascontiguousarray(R, dtype=np.float32).reshape(9)
+    t = np.ascontiguousarray(T, dtype=np.float32).reshape(3)
+    moved = np.empty_like(s)
+    corr = np.empty(s.shape[0], dtype=np.int32)
+    d2 = np.empty(s.shape[0], dtype=np.float32)
+    dm2 = np.float32(dmax) * np.float32(dmax)
+    _check(lib().bpo_icp_correspond(s.ctypes.data_as(F), s.shape[0], d.ctypes.data_as(F), d.shape[0],
+                                    r.ctypes.data_as(F), t.ctypes.data_as(F), float(dm2), moved.ctypes.data_as(F),
+                                    corr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), d2.ctypes.data_as(F)),
+           "icp_correspond")
+    return moved, corr, d2
+
+
+def kabsch(p, q):
+    """Least-squares rotation and translation taking points p onto q
+    (centroids and the SVD of the cross-covariance, FP64, with the
+    determinant correction that excludes reflections)."""
+    p = np.asarray(p, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    pc, qc = p.mean(axis=0), q.mean(axis=0)
+    H = (p - pc).T @ (q - qc)
+    U, _, Vt = np.linalg.svd(H)
+    D = np.diag([1.0, 1.0, np.sign(np.linalg.det(Vt.T @ U.T))])
+    R = Vt.T @ D @ U.T
+    return R, qc - R @ pc
+
+
+def icp(src, dst, R0, T0, iters: int, dmax: float):
+    """Point-to-point ICP (Sec. 2.3 fine registration): per iteration the
+    FP32 correspondence step, then the FP64 least-squares update over the
+    accepted pairs composed onto the pose.  Returns (R, T, rms per iteration,
+    pairs per iteration)."""
+    R = np.asarray(R0, dtype=np.float64)
+    T = np.asarray(T0, dtype=np.float64)
+    rms, npairs = [], []
+    dst64 = np.asarray(dst, dtype=np.float64)
+    for _ in range(iters):
+        moved, corr, d2 = icp_correspond(src, dst, R.astype(np.float32), T.astype(np.float32), dmax)
+        ok = corr >= 0
+        npairs.append(int(ok.sum()))
+        rms.append(float(np.sqrt(d2[ok].astype(np.float64).mean())) if ok.any() else 0.0)
+        if ok.sum() < 3:
+            break
+        Ri, Ti = kabsch(moved[ok].astype(np.float64), dst64[corr[ok]])
+        R, T = Ri @ R, Ri @ T + Ti
+    return R, T, rms, npairs
 
 
 def round_f16(x: float) -> float:

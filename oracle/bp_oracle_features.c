@@ -1,8 +1,9 @@
 /*
- * Integer CPU oracle for the pose front end's data-parallel part (Sec. 2.3):
- * the Harris response (Eq. 4-5), the per-cell corner selection of the
- * experiments (a 30 x 30 grid of cells with a hard threshold), and ZSSD patch
- * matching within a search range.
+ * CPU oracle for the pose front end's data-parallel part (Sec. 2.3): the
+ * Harris response (Eq. 4-5), the per-cell corner selection of the
+ * experiments (a 30 x 30 grid of cells with a hard threshold), ZSSD patch
+ * matching within a search range (all in exact integers), and the
+ * correspondence step of ICP fine registration (FP32, see bpo_icp_correspond).
  *
  * TEST INFRASTRUCTURE ONLY (same rules as bp_oracle.c).
  *
@@ -134,6 +135,51 @@ int bpo_zssd_match(const uint8_t *a, const uint8_t *b, int w, int h, const int64
                     o[2] = cost;
                 }
             }
+    }
+    return BPO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* ICP correspondences (Sec. 2.3: ICP fine registration of the clouds). */
+/* ------------------------------------------------------------------ */
+
+/* One correspondence step of point-to-point ICP, decided in FP32 (the GPU
+ * kernel's precision; every operation rounded on its own, in this order):
+ *   p' = R p + T  (R row-major 3 x 3, T; p'_i = ((R_i0 p_0 + R_i1 p_1) + R_i2 p_2) + T_i)
+ *   nearest target q_j by d2 = (dx dx + dy dy) + dz dz, dx = p'_x - q_x, ...,
+ *   accepted when d2 <= dmax2; ties to the lowest j.  Brute force.
+ * moved: [n][3] p'; corr: [n] index or -1; d2: [n]. */
+int bpo_icp_correspond(const float *src, int n, const float *dst, int m, const float *R, const float *T, float dmax2,
+                       float *moved, int32_t *corr, float *d2)
+{
+    if (!src || !dst || !R || !T || !moved || !corr || !d2 || n < 0 || m < 0) return BPO_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const float *p = src + (size_t)i * 3;
+        float q[3];
+        for (int r = 0; r < 3; ++r) {
+            float acc = R[r * 3 + 0] * p[0];
+            acc = acc + R[r * 3 + 1] * p[1];
+            acc = acc + R[r * 3 + 2] * p[2];
+            q[r] = acc + T[r];
+        }
+        moved[(size_t)i * 3] = q[0];
+        moved[(size_t)i * 3 + 1] = q[1];
+        moved[(size_t)i * 3 + 2] = q[2];
+        int best = -1;
+        float bd = 0.0f;
+        for (int j = 0; j < m; ++j) {
+            const float *t = dst + (size_t)j * 3;
+            const float dx = q[0] - t[0], dy = q[1] - t[1], dz = q[2] - t[2];
+            float d = dx * dx;
+            d = d + dy * dy;
+            d = d + dz * dz;
+            if (d <= dmax2 && (best < 0 || d < bd)) {
+                best = j;
+                bd = d;
+            }
+        }
+        corr[i] = best;
+        d2[i] = best < 0 ? 0.0f : bd;
     }
     return BPO_OK;
 }
