@@ -44,7 +44,7 @@ def parse():
                     help="materialise the planar cost volume with bp_cost_volume inside the step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint", "points", "undistort",
-                                                  "features", "counters"],
+                                                  "features", "icp", "counters"],
                     help="pair: the benchmarked single-pair path (default); batch, precision, adjoint "
                          "measure the other forms; points the JBU with fused triangulation; counters "
                          "runs the pair path eagerly plus a plain copy of known size, for rocprofv3 "
@@ -536,6 +536,49 @@ def form_features(args):
             "zssd_ms": round(t_m, 4), "corners": found, "zssd_shifts_per_corner": 33 * 33, "patch": "11x11"}
 
 
+def form_icp(args):
+    """Point-to-point ICP of a 676x380-point terrain cloud (the size of a cloud
+    from the benchmarked pair's disparity) onto a copy moved by a small rigid
+    motion (the residual left by the estimated poses) with 2 cm noise, 30
+    iterations, correspondences within 1 m; HIP events on the current stream."""
+    import torch
+
+    import paper_1902_09733_amd as bp
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(11)
+    n = 676 * 380
+    xy = rng.uniform(-100.0, 100.0, size=(n, 2))
+    z = 8.0 * np.sin(0.05 * xy[:, 0]) * np.cos(0.04 * xy[:, 1]) + 0.002 * xy[:, 0] ** 2
+    src = np.column_stack([xy, z])
+    a, b, c = 0.002, -0.003, 0.004
+    Rx = np.array([[1, 0, 0], [0, np.cos(a), -np.sin(a)], [0, np.sin(a), np.cos(a)]])
+    Ry = np.array([[np.cos(b), 0, np.sin(b)], [0, 1, 0], [-np.sin(b), 0, np.cos(b)]])
+    Rz = np.array([[np.cos(c), -np.sin(c), 0], [np.sin(c), np.cos(c), 0], [0, 0, 1]])
+    R_true, T_true = Rz @ Ry @ Rx, np.array([0.5, -0.4, 0.2])
+    dst = src @ R_true.T + T_true + 0.02 * rng.normal(size=src.shape)
+    s_t = torch.from_numpy(src.astype(np.float32)).to(dev)
+    d_t = torch.from_numpy(dst.astype(np.float32)).to(dev)
+    pose = torch.tensor([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], dtype=torch.float64, device=dev)
+    ws = bp.Workspace()
+    iters = 30
+    out = bp.icp(s_t, d_t, pose, iters, 1.0, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        bp.icp(s_t, d_t, pose, iters, 1.0, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    est = out["pose"].cpu().numpy()
+    return {"form": "icp", "workload": f"terrain cloud {n} points onto a moved noisy copy", "iters": iters,
+            "icp_ms": round(ms, 3), "per_iteration_us": round(ms * 1e3 / iters, 1),
+            "final_rms_m": round(float(out["rms"][-1].item()), 5), "final_pairs": int(out["pairs"][-1].item()),
+            "rotation_error": float(np.abs(est[:9].reshape(3, 3) - R_true).max()),
+            "translation_error_m": float(np.abs(est[9:] - T_true).max())}
+
+
 def form_counters(args):
     """The pair path three times without a graph (every dispatch visible to a
     counter pass), then three plain device-to-device copies of 256 MiB."""
@@ -564,7 +607,8 @@ def form_counters(args):
 
 def run_form(form, args):
     return {"batch": form_batch, "precision": form_precision, "adjoint": form_adjoint, "points": form_points,
-            "undistort": form_undistort, "features": form_features, "counters": form_counters}[form](args)
+            "undistort": form_undistort, "features": form_features, "icp": form_icp,
+            "counters": form_counters}[form](args)
 
 
 if __name__ == "__main__":

@@ -207,6 +207,39 @@ bp_status bp_zssd_match(const uint8_t *a, const uint8_t *b, int32_t width, int32
                         const bp_corner *corners, int32_t n, int32_t patch_radius, int32_t search_radius,
                         bp_match *matches, hipStream_t stream);
 
+/* Workspace bytes of bp_icp for n source and m target points (0 on invalid sizes). */
+size_t bp_icp_workspace_size(int32_t n, int32_t m);
+
+/*
+ * Point-to-point ICP fine registration of a source cloud onto a target
+ * cloud (Sec. 2.3: the clouds of Eq. 3 registered by ICP from the estimated
+ * poses).  Per iteration:
+ *  - every source point p is moved to p' = R p + T in FP32 (each operation
+ *    rounded on its own: ((R_r0 p_0 + R_r1 p_1) + R_r2 p_2) + T_r) and paired
+ *    with its nearest target within dmax (squared distance (dx^2 + dy^2) +
+ *    dz^2 in FP32, ties to the lowest target index), or with none;
+ *  - the least-squares rigid motion taking the paired p' onto their targets
+ *    (FP64 centroids and cross-covariance, rotation by Horn's quaternion
+ *    method) is composed onto the pose in FP64: R <- Ri R, T <- Ri T + Ti;
+ *    an iteration with fewer than 3 pairs leaves the pose unchanged;
+ *  - the next correspondences use the pose rounded to FP32.
+ * Exact nearest neighbours as long as coordinates stay within about
+ * 8e4 * dmax of the origin (a spatial hash of cells of edge dmax / 0.99).
+ *   src [n][3], dst [m][3]   device float32 points (n, m >= 0)
+ *   pose_in, pose_out        device float64 [12]: R row-major, then T
+ *   rms, pairs               device [iters] per-iteration RMS distance of the
+ *                            pairs (float64) and pair count (int32), or NULL
+ *   corr                     device int32 [n]: the last iteration's pairing
+ *                            (target index or -1), or NULL
+ *   workspace                bp_icp_workspace_size(n, m) bytes, 256-byte aligned
+ * Errors: BP_ERR_INVALID_ARGUMENT for NULL points with n or m > 0, NULL
+ * poses, negative sizes or iterations, dmax not positive and finite;
+ * BP_ERR_WORKSPACE_TOO_SMALL; BP_ERR_HIP.
+ */
+bp_status bp_icp(const float *src, int32_t n, const float *dst, int32_t m, const double *pose_in, int32_t iters,
+                 float dmax, double *pose_out, double *rms, int32_t *pairs, int32_t *corr, void *workspace,
+                 size_t ws_bytes, hipStream_t stream);
+
 /*
  * a1 alone: s x s block mean rounded half up, out [height/s][width/s][channels]
  * packed.  Same argument rules as bp_cost_volume.

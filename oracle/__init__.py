@@ -252,22 +252,24 @@ def kabsch(p, q):
 def icp(src, dst, R0, T0, iters: int, dmax: float):
     """Point-to-point ICP (Sec. 2.3 fine registration): per iteration the
     FP32 correspondence step, then the FP64 least-squares update over the
-    accepted pairs composed onto the pose.  Returns (R, T, rms per iteration,
-    pairs per iteration)."""
+    accepted pairs composed onto the pose (left unchanged by an iteration
+    with fewer than 3 pairs).  Returns (R, T, rms per iteration, pairs per
+    iteration, the last iteration's correspondences)."""
     R = np.asarray(R0, dtype=np.float64)
     T = np.asarray(T0, dtype=np.float64)
     rms, npairs = [], []
     dst64 = np.asarray(dst, dtype=np.float64)
+    corr = None
     for _ in range(iters):
         moved, corr, d2 = icp_correspond(src, dst, R.astype(np.float32), T.astype(np.float32), dmax)
         ok = corr >= 0
         npairs.append(int(ok.sum()))
         rms.append(float(np.sqrt(d2[ok].astype(np.float64).mean())) if ok.any() else 0.0)
         if ok.sum() < 3:
-            break
+            continue
         Ri, Ti = kabsch(moved[ok].astype(np.float64), dst64[corr[ok]])
         R, T = Ri @ R, Ri @ T + Ti
-    return R, T, rms, npairs
+    return R, T, rms, npairs, corr
 
 
 def round_f16(x: float) -> float:

@@ -6,6 +6,6 @@ checkerboard min-sum BP (Eq. 1), argmin/soft-argmin readout and joint
 bilateral upsampling (Eq. 2), run by hand-written HIP kernels for gfx950
 behind the C ABI in include/bp.h.
 """
-from .stereo import (BPParams, Camera, Intrinsics, Pair, Workspace, backward, harris, zssd_match, checkpoint_bytes, cost_volume, downsample,  # noqa: F401
+from .stereo import (BPParams, Camera, Intrinsics, Pair, Workspace, backward, harris, icp, zssd_match, checkpoint_bytes, cost_volume, downsample,  # noqa: F401
                      run, undistort, upsample, upsample_points, variant_count, workspace_bytes)
 from .autograd import BPSoftArgmin, soft_argmin_bp  # noqa: F401

@@ -131,6 +131,10 @@ def lib():
     L.bp_harris.restype = ctypes.c_int
     L.bp_zssd_match.argtypes = [vp, vp, i32, i32, i64, vp, i32, i32, i32, vp, vp]
     L.bp_zssd_match.restype = ctypes.c_int
+    L.bp_icp_workspace_size.argtypes = [i32, i32]
+    L.bp_icp_workspace_size.restype = sz
+    L.bp_icp.argtypes = [vp, i32, vp, i32, vp, i32, f32, vp, vp, vp, vp, vp, sz, vp]
+    L.bp_icp.restype = ctypes.c_int
     L.bp_undistort.argtypes = [vp, i32, i32, i32, i64, P(BpIntrinsics), vp, i64, vp]
     L.bp_undistort.restype = ctypes.c_int
     L.bp_upsample_points.argtypes = [vp, i32, i32, vp, i32, i32, i32, i64, f32, f32, i32, P(BpCamera), vp, vp, vp]

@@ -529,6 +529,25 @@ bp_status bp_zssd_match(const uint8_t *a, const uint8_t *b, int32_t width, int32
     return launch_zssd(a, b, width, height, stride, corners, n, patch_radius, search_radius, matches, stream);
 }
 
+size_t bp_icp_workspace_size(int32_t n, int32_t m)
+{
+    if (n < 0 || m < 0 || m > (1 << 28)) return 0;
+    return icp_workspace_bytes(n, m);
+}
+
+bp_status bp_icp(const float *src, int32_t n, const float *dst, int32_t m, const double *pose_in, int32_t iters,
+                 float dmax, double *pose_out, double *rms, int32_t *pairs, int32_t *corr, void *workspace,
+                 size_t ws_bytes, hipStream_t stream)
+{
+    if (n < 0 || m < 0 || m > (1 << 28) || iters < 0 || (n > 0 && !src) || (m > 0 && !dst) || !pose_in || !pose_out)
+        return BP_ERR_INVALID_ARGUMENT;
+    if (!(dmax > 0.0f) || !std::isfinite(dmax)) return BP_ERR_INVALID_ARGUMENT;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return BP_ERR_INVALID_ARGUMENT;
+    if (ws_bytes < icp_workspace_bytes(n, m)) return BP_ERR_WORKSPACE_TOO_SMALL;
+    (void)hipGetLastError();
+    return launch_icp(src, n, dst, m, pose_in, iters, dmax, pose_out, rms, pairs, corr, (uint8_t *)workspace, stream);
+}
+
 bp_status bp_undistort(const uint8_t *in, int32_t width, int32_t height, int32_t channels, int64_t in_stride,
                        const bp_intrinsics *intrinsics, uint8_t *out, int64_t out_stride, hipStream_t stream)
 {

@@ -106,6 +106,9 @@ bp_status launch_harris(const uint8_t *img, int w, int h, int64_t stride, int g,
                         bp_corner *corners, hipStream_t s);
 bp_status launch_zssd(const uint8_t *a, const uint8_t *b, int w, int h, int64_t stride, const bp_corner *corners,
                       int n, int pr, int sr, bp_match *out, hipStream_t s);
+size_t icp_workspace_bytes(int n, int m);
+bp_status launch_icp(const float *src, int n, const float *dst, int m, const double *pose_in, int iters, float dmax,
+                     double *pose_out, double *rms, int32_t *pairs, int32_t *corr_out, uint8_t *ws, hipStream_t s);
 bp_status launch_undistort(const uint8_t *in, int w, int h, int ch, int64_t in_stride, const bp_intrinsics &K,
                            uint8_t *out, int64_t out_stride, hipStream_t s);
 bp_status launch_upsample(const int32_t *disp_lo, int wl, int hl, const uint8_t *guide, int wh, int hh, int ch,

@@ -303,6 +303,34 @@ def zssd_match(a: torch.Tensor, b: torch.Tensor, corners_raw: torch.Tensor, patc
     return {"x": x, "y": y, "cost": c}
 
 
+def icp(src: torch.Tensor, dst: torch.Tensor, pose: torch.Tensor, iters: int = 30, dmax: float = 1.0,
+        want_corr: bool = False, workspace: Workspace | None = None, stream=None):
+    """Point-to-point ICP of float32 [n][3] onto [m][3] from the float64 pose
+    [12] (R row-major, T).  Returns a dict: pose (float64 [12]), rms (float64
+    [iters]), pairs (int32 [iters]) and, if asked, corr (int32 [n])."""
+    _need_gpu(src, dst, pose)
+    if src.dtype != torch.float32 or dst.dtype != torch.float32 or pose.dtype != torch.float64:
+        raise ValueError("points must be float32 [N][3] and the pose float64 [12]")
+    n, m = src.shape[0], dst.shape[0]
+    lib = _abi.lib()
+    nbytes = lib.bp_icp_workspace_size(n, m)
+    ws = (workspace or Workspace()).get(nbytes, src.device)
+    dev = src.device
+    out = {"pose": torch.empty(12, dtype=torch.float64, device=dev),
+           "rms": torch.empty(max(iters, 1), dtype=torch.float64, device=dev),
+           "pairs": torch.empty(max(iters, 1), dtype=torch.int32, device=dev)}
+    if want_corr:
+        out["corr"] = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    st = lib.bp_icp(_ptr(src), n, _ptr(dst), m, _ptr(pose), int(iters), float(dmax), _ptr(out["pose"]),
+                    _ptr(out["rms"]), _ptr(out["pairs"]), _ptr(out["corr"]) if want_corr else None, _ptr(ws),
+                    nbytes, _stream(stream))
+    _abi.check("bp_icp", st)
+    out["rms"], out["pairs"] = out["rms"][:iters], out["pairs"][:iters]
+    if want_corr:
+        out["corr"] = out["corr"][:n]
+    return out
+
+
 @dataclass
 class Intrinsics:
     """Distorted-frame intrinsics (pixels) with radial coefficients only."""

@@ -160,3 +160,20 @@ def test_upsample_points_validation(lib):
         cb = _abi.BpCamera(**dict(cam_ok, **bad))
         assert lib.bp_upsample_points(*args(ctypes.byref(cb), ctypes.c_void_p(1024))) == \
             _abi.BP_ERR_INVALID_ARGUMENT, bad
+
+
+def test_icp_validation(lib):
+    """bp_icp rejects bad sizes, pointers, dmax and workspace before any launch."""
+    assert lib.bp_icp_workspace_size(-1, 10) == 0 and lib.bp_icp_workspace_size(10, -1) == 0
+    n, m = 1000, 2000
+    nb = lib.bp_icp_workspace_size(n, m)
+    assert nb > 0 and lib.bp_icp_workspace_size(n, 4 * m) > nb
+    P = ctypes.c_void_p
+    good = dict(src=P(256), n=n, dst=P(512), m=m, pose_in=P(768), iters=5, dmax=1.0, pose_out=P(1024),
+                rms=None, pairs=None, corr=None, ws=P(4096), nb=nb, stream=None)
+    call = lambda **kw: lib.bp_icp(*dict(good, **kw).values())
+    for bad in (dict(n=-1), dict(m=-1), dict(iters=-1), dict(src=None), dict(dst=None), dict(pose_in=None),
+                dict(pose_out=None), dict(dmax=0.0), dict(dmax=-1.0), dict(dmax=float("nan")),
+                dict(dmax=float("inf")), dict(ws=None), dict(ws=P(4096 + 8))):
+        assert call(**bad) == _abi.BP_ERR_INVALID_ARGUMENT, bad
+    assert call(nb=nb - 1) == _abi.BP_ERR_WORKSPACE_TOO_SMALL

@@ -58,7 +58,7 @@ def test_icp_recovers_rigid_motion():
     src = surface(3000, 2)
     R, T = rot(0.02, -0.03, 0.05), np.array([0.4, -0.3, 0.2])
     dst = (src.astype(np.float64) @ R.T + T).astype(np.float32)
-    Re, Te, rms, npairs = oracle.icp(src, dst, np.eye(3), np.zeros(3), iters=40, dmax=2.0)
+    Re, Te, rms, npairs, _ = oracle.icp(src, dst, np.eye(3), np.zeros(3), iters=40, dmax=2.0)
     np.testing.assert_allclose(Re, R, atol=2e-5)
     np.testing.assert_allclose(Te, T, atol=2e-4)
     assert rms[-1] < 1e-3 and rms[0] > 0.1
