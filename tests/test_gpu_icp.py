@@ -90,3 +90,51 @@ def test_icp_degenerate(dev):
     assert (g["corr"] == -1).all()
     g = gpu_icp(src, np.zeros((0, 3), np.float32), R0, T0, 2, 0.5, dev)   # empty target
     np.testing.assert_array_equal(g["pose"], pose_vec(R0, T0))
+
+
+def test_large_cloud_sampled(dev):
+    """300k points each (hash table of 2^20 buckets, several scan rounds):
+    the GPU pairing of 3000 sampled queries equals the exhaustive oracle's."""
+    src = surface(300_000, 7, noise=0.02)
+    dst = surface(300_000, 8, noise=0.02)
+    R0, T0 = rot(0.001, 0.002, -0.003), np.array([0.05, 0.02, -0.01])
+    g = gpu_icp(src, dst, R0, T0, 1, 0.5, dev)
+    idx = np.random.default_rng(9).choice(len(src), 3000, replace=False)
+    _, corr, _ = oracle.icp_correspond(src[idx], dst, R0.astype(np.float32), T0.astype(np.float32), 0.5)
+    np.testing.assert_array_equal(g["corr"][idx], corr)
+    assert (g["corr"] >= 0).mean() > 0.99
+
+
+def test_wrapped_buckets_exact(dev):
+    """Far outliers stretch the bounding box beyond what the bucket bits
+    cover, so cells wrap onto shared buckets: the pairing stays exact."""
+    src = surface(5000, 10, noise=0.02)
+    dst = surface(5000, 11, noise=0.02)
+    dst[:4] = [[4e3, -3e3, 50.0], [-4e3, 3e3, -60.0], [0.0, 0.0, 2e3], [10.3, -9.7, 1.9]]
+    R0, T0 = rot(0.01, 0.0, 0.02), np.array([0.1, 0.0, -0.1])
+    g = gpu_icp(src, dst, R0, T0, 1, 0.4, dev)
+    _, corr, _ = oracle.icp_correspond(src, dst, R0.astype(np.float32), T0.astype(np.float32), 0.4)
+    np.testing.assert_array_equal(g["corr"], corr)
+
+
+def test_collinear_pairs_give_a_rotation(dev):
+    """Collinear points leave the rotation about their line undetermined (the
+    top eigenvalue of the quaternion matrix is repeated): the update must
+    still be a proper rotation that lays the line onto its target line (a
+    slide along the line is a fixed point of ICP, as in the oracle)."""
+    t = np.linspace(-5.0, 5.0, 200)
+    src = np.column_stack([t, 0.5 * t, 0.2 * t]).astype(np.float32)
+    R, T = rot(0.0, 0.0, 0.05), np.array([0.2, -0.1, 0.05])
+    dst = (src.astype(np.float64) @ R.T + T).astype(np.float32)
+    g = gpu_icp(src, dst, np.eye(3), np.zeros(3), 20, 1.0, dev)
+    Re, Te = g["pose"][:9].reshape(3, 3), g["pose"][9:]
+    np.testing.assert_allclose(Re @ Re.T, np.eye(3), atol=1e-12)
+    assert abs(np.linalg.det(Re) - 1.0) < 1e-12
+    moved = src.astype(np.float64) @ Re.T + Te
+    d = (dst[-1] - dst[0]).astype(np.float64)
+    d /= np.linalg.norm(d)
+    off = moved - dst[0]
+    assert np.linalg.norm(off - np.outer(off @ d, d), axis=1).max() < 1e-4
+    _, _, rms, pairs, _ = oracle.icp(src, dst, np.eye(3), np.zeros(3), 20, 1.0)
+    np.testing.assert_allclose(g["rms"][-1], rms[-1], rtol=1e-3)
+    assert g["pairs"][-1] == pairs[-1]
