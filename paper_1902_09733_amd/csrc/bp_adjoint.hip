@@ -46,8 +46,11 @@ struct BwdArgs {
 template <int LP>
 __device__ __forceinline__ void bwd_step(const BwdArgs &a, uint32_t block)
 {
-    extern __shared__ float hb_all[];          // [64][LP]
-    float *hb = hb_all + threadIdx.x * LP;
+    // h-bar rows in LDS, label-major with the lane fastest ([LP][64]): a lane's
+    // entries sit in its own bank whatever label it touches, so neither the
+    // label loops nor the data-dependent scatter conflict.
+    extern __shared__ float hb_all[];
+    float *hb = hb_all + threadIdx.x;
     // Labels past L (up to the register row length LP) are inactive.  The
     // label count stays a runtime value even when it equals LP: that keeps
     // the loads conditional and the register count low.
@@ -139,7 +142,7 @@ __device__ __forceinline__ void bwd_step(const BwdArgs &a, uint32_t block)
 
     // Scatter the receiver slot's adjoint onto h-bar, then clear that slot.
 #pragma unroll
-    for (int f = 0; f < LP; ++f) hb[f] = 0.0f;
+    for (int f = 0; f < LP; ++f) hb[f * 64] = 0.0f;
     uint32_t roff = 0;
     if (hq) {
         int nx = x, ny = y;
@@ -166,8 +169,8 @@ __device__ __forceinline__ void bwd_step(const BwdArgs &a, uint32_t block)
                     tsum += mb * a.lambda;
                 } else {
                     const int g = (int)get_src(f);
-                    hb[g] += mb;
-                    hb[gmin] -= mb;
+                    hb[g * 64] += mb;
+                    hb[gmin * 64] -= mb;
                     lsum += mb * fabsf((float)(f - g));
                 }
                 st_f32(rb, 0.0f, roff, (uint32_t)f * cls);
@@ -186,7 +189,7 @@ __device__ __forceinline__ void bwd_step(const BwdArgs &a, uint32_t block)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int f = f0 + e < nl ? f0 + e : nl - 1;
-            hv[e] = f0 + e < nl ? hb[f] : 0.0f;
+            hv[e] = f0 + e < nl ? hb[f * 64] : 0.0f;
             tot[e] = group_sum<4>(hv[e]);
             cur[e] = (live && has[q] && f0 + e < nl) ? ld_f32(rb, moff[q], (uint32_t)f * cls) : 0.0f;
             gcv[e] = (live && q == 0 && f0 + e < nl) ? gc0[(int64_t)f * plane] : 0.0f;

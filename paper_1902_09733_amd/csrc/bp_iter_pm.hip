@@ -234,6 +234,15 @@ static bp_status dispatch_pm_batch(const BatchEntry *tab, int n, int blocks, int
     BP_PMB(4, 4) BP_PMB(8, 4) BP_PMB(16, 4) BP_PMB(16, 6) BP_PMB(16, 8) BP_PMB(16, 12) BP_PMB(16, 16)
     BP_PMB(4, 8) BP_PMB(8, 8) BP_PMB(8, 12) BP_PMB(8, 16)
 #undef BP_PMB
+#define BP_PMBX(SV, RV)                                                                                            \
+    if (SEGV == SV && R == RV) {                                                                                   \
+        if (!xchg) return BP_ERR_UNSUPPORTED;                                                                      \
+        if (ro) k_iter_pm_batch<SV, RV, S, true, true><<<blocks, 256, 0, st>>>(tab, n);                            \
+        else k_iter_pm_batch<SV, RV, S, true, false><<<blocks, 256, 0, st>>>(tab, n);                              \
+        return launch_status();                                                                                    \
+    }
+    BP_PMBX(4, 16) BP_PMBX(4, 24) BP_PMBX(4, 32)
+#undef BP_PMBX
     return BP_ERR_UNSUPPORTED;
 }
 
@@ -261,15 +270,17 @@ void pm_split(int L, int *S, int *R)
 }
 
 static bool pm_can_halve(int L) { return L > 16 && L <= 128; }
+static bool pm_can_quarter(int L) { return L > 32 && L <= 128; }
 
-int pm_variants(int L) { return pm_can_halve(L) ? 4 : 2; }
+int pm_variants(int L) { return pm_can_quarter(L) ? 5 : (pm_can_halve(L) ? 4 : 2); }
 
-// Measured on MI355X (676x380x64 and 1352x760x128 pyramids): with FP32
-// storage the shuffled-sum split wins from 128 labels, with 16-bit storage
-// halving the lanes per message and shuffling sums wins throughout.
+// Measured on MI355X (1352x760 5-level pyramids, 32 to 128 labels): with
+// FP32 storage the shuffled-sum split wins above 64 labels; with 16-bit
+// storage a quarter of the lanes with shuffled sums wins at 33..64 labels
+// (32-byte rows per lane), half the lanes with shuffled sums elsewhere.
 int default_variant(int L, int msg_fmt)
 {
-    if (msg_fmt != FMT_F32) return pm_can_halve(L) ? 4 : 3;
+    if (msg_fmt != FMT_F32) return (pm_can_quarter(L) && L <= 64) ? 5 : (pm_can_halve(L) ? 4 : 3);
     return L > 64 ? 3 : 1;
 }
 
@@ -278,16 +289,22 @@ int default_variant(int L, int msg_fmt)
 //   2 half the lanes per message, twice the labels per lane
 //   3 default split, each lane group reads only its own row (shuffled sums)
 //   4 half lanes and shuffled sums
+//   5 a quarter of the lanes (four times the labels per lane) and shuffled sums
 // Variant 0 means 1.
 void pm_split_variant(int L, int variant, int *S, int *R, bool *xchg)
 {
     pm_split(L, S, R);
     if (variant <= 0 || variant > pm_variants(L)) variant = 1;
     const bool half = (variant == 2 || variant == 4) && pm_can_halve(L);
+    const bool quarter = variant == 5 && pm_can_quarter(L);
     *xchg = variant >= 3;
     if (half) {
         *S /= 2;
         *R *= 2;
+    }
+    if (quarter) {
+        *S /= 4;
+        *R *= 4;
     }
 }
 
@@ -313,9 +330,21 @@ static bp_status launch_pm(const IterArgs &a, bool ro, bool xchg, hipStream_t st
     return launch_status();
 }
 
+// Splits that only the shuffled-sum form uses.
+template <int SEG, int R, typename S>
+static bp_status launch_pm_xonly(const IterArgs &a, bool ro, bool xchg, hipStream_t st)
+{
+    if (!xchg) return BP_ERR_UNSUPPORTED;
+    launch_pm_x<SEG, R, S, true>(a, ro, (unsigned)(((int64_t)a.ncomp * 4 * SEG + 255) / 256), st);
+    return launch_status();
+}
+
 template <typename S>
 static bp_status dispatch_pm(const IterArgs &a, int SEGV, int R, bool ro, bool xchg, hipStream_t st)
 {
+    if (SEGV == 4 && R == 16) return launch_pm_xonly<4, 16, S>(a, ro, xchg, st);
+    if (SEGV == 4 && R == 24) return launch_pm_xonly<4, 24, S>(a, ro, xchg, st);
+    if (SEGV == 4 && R == 32) return launch_pm_xonly<4, 32, S>(a, ro, xchg, st);
     if (SEGV == 4 && R == 4) return launch_pm<4, 4, S>(a, ro, xchg, st);
     if (SEGV == 8 && R == 4) return launch_pm<8, 4, S>(a, ro, xchg, st);
     if (SEGV == 16 && R == 4) return launch_pm<16, 4, S>(a, ro, xchg, st);
