@@ -97,7 +97,7 @@ typedef struct {
                                   levels: 1 default lane split, 2 half the lanes with twice
                                   the labels per lane, 3 and 4 the same with each direction's
                                   lanes reading only their own incoming message and sharing
-                                  sums by lane shuffles, 5 (33..128 labels) a quarter of the
+                                  sums by lane shuffles, 5 (17..128 labels) a quarter of the
                                   lanes with shuffled sums.  A number beyond what one layout has
                                   selects that layout's variant 1.  Results do not depend on it. */
     int32_t pm_from;           /* first pyramid level stored pixel-major (labels of a pixel

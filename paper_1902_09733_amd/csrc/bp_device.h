@@ -148,7 +148,7 @@ __device__ __forceinline__ void st_row(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
     }
 }
 
-// ---- DPP exchanges inside segments of SEG lanes (SEG = 4, 8 or 16) ----
+// ---- DPP exchanges inside segments of SEG lanes (SEG = 2, 4, 8 or 16) ----
 // dpp controls: row_shl:n = 0x100 + n, row_shr:n = 0x110 + n,
 // quad_perm(1,0,3,2) = 0xB1, quad_perm(2,3,0,1) = 0x4E, row_half_mirror = 0x141,
 // row_mirror = 0x140.
@@ -166,8 +166,9 @@ __device__ __forceinline__ int dpp_i(int old, int v)
     return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xF, 0xF, false);
 }
 
-// x + x[lane ^ D] for D in {4, 8, 16, 32}: both lanes of a pair get the same
-// bits (IEEE addition is commutative).  D = 4 composes a quad reversal with a
+// x + x[lane ^ D] for D in {2, 4, 8, 16, 32}: both lanes of a pair get the
+// same bits (IEEE addition is commutative).  D = 2 is a quad permutation,
+// D = 4 composes a quad reversal with a
 // half-row mirror, D = 8 is a rotation by 8 within a 16-lane row, D = 16 and
 // D = 32 are gfx950's register-only row and half-wave swaps: swapping x with
 // a copy of itself leaves one register holding the even rows' (lower
@@ -180,8 +181,10 @@ __device__ __forceinline__ int dpp_i(int old, int v)
 template <int D>
 __device__ __forceinline__ float xor_sum(float x)
 {
-    static_assert(D == 4 || D == 8 || D == 16 || D == 32, "unsupported lane distance");
-    if constexpr (D == 4) {
+    static_assert(D == 2 || D == 4 || D == 8 || D == 16 || D == 32, "unsupported lane distance");
+    if constexpr (D == 2) {
+        return x + dpp_f<0x4E>(x, x);
+    } else if constexpr (D == 4) {
         return x + dpp_f<0x141>(x, dpp_f<0x1B>(x, x));
     } else if constexpr (D == 8) {
         return x + dpp_f<0x128>(x, x);
@@ -219,7 +222,7 @@ __device__ __forceinline__ float seg_prefix_min(float v, int s)
 {
     const float inf = __builtin_huge_valf();
     v = fminf(v, seg_from_lower<SEG, 1>(v, inf, s));
-    v = fminf(v, seg_from_lower<SEG, 2>(v, inf, s));
+    if constexpr (SEG > 2) v = fminf(v, seg_from_lower<SEG, 2>(v, inf, s));
     if constexpr (SEG > 4) v = fminf(v, seg_from_lower<SEG, 4>(v, inf, s));
     if constexpr (SEG > 8) v = fminf(v, seg_from_lower<SEG, 8>(v, inf, s));
     return v;
@@ -231,7 +234,7 @@ __device__ __forceinline__ float seg_suffix_min(float v, int s)
 {
     const float inf = __builtin_huge_valf();
     v = fminf(v, seg_from_upper<SEG, 1>(v, inf, s));
-    v = fminf(v, seg_from_upper<SEG, 2>(v, inf, s));
+    if constexpr (SEG > 2) v = fminf(v, seg_from_upper<SEG, 2>(v, inf, s));
     if constexpr (SEG > 4) v = fminf(v, seg_from_upper<SEG, 4>(v, inf, s));
     if constexpr (SEG > 8) v = fminf(v, seg_from_upper<SEG, 8>(v, inf, s));
     return v;
@@ -242,7 +245,7 @@ template <int SEG, typename Op>
 __device__ __forceinline__ float seg_allreduce(float v, Op op)
 {
     v = op(v, dpp_f<0xB1>(v, v));
-    v = op(v, dpp_f<0x4E>(v, v));
+    if constexpr (SEG > 2) v = op(v, dpp_f<0x4E>(v, v));
     if constexpr (SEG > 4) v = op(v, dpp_f<0x141>(v, v));
     if constexpr (SEG > 8) v = op(v, dpp_f<0x140>(v, v));
     return v;
@@ -259,7 +262,7 @@ __device__ __forceinline__ void seg_argmin(float &v, int &i)
         }
     };
     step(dpp_f<0xB1>(v, v), dpp_i<0xB1>(i, i));
-    step(dpp_f<0x4E>(v, v), dpp_i<0x4E>(i, i));
+    if constexpr (SEG > 2) step(dpp_f<0x4E>(v, v), dpp_i<0x4E>(i, i));
     if constexpr (SEG > 4) step(dpp_f<0x141>(v, v), dpp_i<0x141>(i, i));
     if constexpr (SEG > 8) step(dpp_f<0x140>(v, v), dpp_i<0x140>(i, i));
 }

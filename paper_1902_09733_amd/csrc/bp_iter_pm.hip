@@ -241,7 +241,7 @@ static bp_status dispatch_pm_batch(const BatchEntry *tab, int n, int blocks, int
         else k_iter_pm_batch<SV, RV, S, true, false><<<blocks, 256, 0, st>>>(tab, n);                              \
         return launch_status();                                                                                    \
     }
-    BP_PMBX(4, 16) BP_PMBX(4, 24) BP_PMBX(4, 32)
+    BP_PMBX(2, 16) BP_PMBX(4, 16) BP_PMBX(4, 24) BP_PMBX(4, 32)
 #undef BP_PMBX
     return BP_ERR_UNSUPPORTED;
 }
@@ -270,13 +270,13 @@ void pm_split(int L, int *S, int *R)
 }
 
 static bool pm_can_halve(int L) { return L > 16 && L <= 128; }
-static bool pm_can_quarter(int L) { return L > 32 && L <= 128; }
+static bool pm_can_quarter(int L) { return L > 16 && L <= 128; }
 
 int pm_variants(int L) { return pm_can_quarter(L) ? 5 : (pm_can_halve(L) ? 4 : 2); }
 
 // Measured on MI355X (1352x760 5-level pyramids, 32 to 128 labels): with
 // FP32 storage the shuffled-sum split wins above 64 labels; with 16-bit
-// storage a quarter of the lanes with shuffled sums wins at 33..64 labels
+// storage a quarter of the lanes with shuffled sums wins at 17..64 labels
 // (32-byte rows per lane), half the lanes with shuffled sums elsewhere.
 int default_variant(int L, int msg_fmt)
 {
@@ -290,6 +290,7 @@ int default_variant(int L, int msg_fmt)
 //   3 default split, each lane group reads only its own row (shuffled sums)
 //   4 half lanes and shuffled sums
 //   5 a quarter of the lanes (four times the labels per lane) and shuffled sums
+//     (17..128 labels)
 // Variant 0 means 1.
 void pm_split_variant(int L, int variant, int *S, int *R, bool *xchg)
 {
@@ -342,6 +343,7 @@ static bp_status launch_pm_xonly(const IterArgs &a, bool ro, bool xchg, hipStrea
 template <typename S>
 static bp_status dispatch_pm(const IterArgs &a, int SEGV, int R, bool ro, bool xchg, hipStream_t st)
 {
+    if (SEGV == 2 && R == 16) return launch_pm_xonly<2, 16, S>(a, ro, xchg, st);
     if (SEGV == 4 && R == 16) return launch_pm_xonly<4, 16, S>(a, ro, xchg, st);
     if (SEGV == 4 && R == 24) return launch_pm_xonly<4, 24, S>(a, ro, xchg, st);
     if (SEGV == 4 && R == 32) return launch_pm_xonly<4, 32, S>(a, ro, xchg, st);

@@ -453,8 +453,8 @@ def test_batched_iteration_counts(dev, K):
         assert_exact({k: v.cpu().numpy() for k, v in o_gpu.items()}, o, f"batched K{K}")
 
 
-@pytest.mark.parametrize("L", [16, 24, 32, 64, 96, 128])
-@pytest.mark.parametrize("variant", [2, 3, 4])
+@pytest.mark.parametrize("L", [16, 17, 24, 32, 33, 48, 64, 96, 128])
+@pytest.mark.parametrize("variant", [2, 3, 4, 5])
 def test_pixel_major_variants_exact(dev, L, variant):
     cost = int_cost(53, 37, L, L + 1)
     o = oracle_run(cost, 3, 6, 10.0, 2.0)
@@ -462,7 +462,7 @@ def test_pixel_major_variants_exact(dev, L, variant):
     assert_exact(g, o, f"L{L} pixel-major variant {variant}")
 
 
-@pytest.mark.parametrize("variant", [3, 4])
+@pytest.mark.parametrize("variant", [3, 4, 5])
 def test_batched_shuffled_sum_variants_exact(dev, variant):
     bp = bp_mod()
     costs = [int_cost(w, h, L, w + 3 * h + L) for (w, h, L) in BATCH_SHAPES]
