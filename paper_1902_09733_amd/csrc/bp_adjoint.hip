@@ -80,8 +80,8 @@ __device__ __forceinline__ void bwd_step(const BwdArgs &a, uint32_t block)
 
     // Distance transform of h with winners (registers, fully unrolled).  The
     // winner of label f (< 256) is kept as a byte of srcp[f / 4].  Loads are
-    // issued 8 labels at a time (scheduling barriers), which bounds the
-    // registers they hold.
+    // issued in batches (scheduling barriers), which bounds the registers
+    // they hold.
     float A[LP];
     uint32_t srcp[LP / 4];
     auto set_src = [&](int f, uint32_t g) {
@@ -93,27 +93,31 @@ __device__ __forceinline__ void bwd_step(const BwdArgs &a, uint32_t block)
     for (int i = 0; i < LP / 4; ++i) srcp[i] = 0u;
     float hmin = inf;
     int gmin = 0;
+    // Each lane loads the cost and only its own incoming slot q; the four
+    // slots' values reach every lane of the pixel's quad by DPP broadcasts, and
+    // h is summed in the same order as in the forward kernel.  Loads are
+    // issued kB1 labels at a time.
+    constexpr int kB1 = LP < 32 ? LP : 32;
 #pragma unroll
-    for (int f0 = 0; f0 < LP; f0 += 8) {
-        float hv[8];
+    for (int f0 = 0; f0 < LP; f0 += kB1) {
+        float cv[kB1], mv[kB1];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < kB1; ++e) {
+            const int f = f0 + e;
+            cv[e] = f < nl ? ld_f32(rc, cost_off, (uint32_t)f * cls) : 0.0f;
+            mv[e] = f < nl ? ld_f32(rm, moff[q], (uint32_t)f * cls) : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < kB1; ++e) {
             const int f = f0 + e;
             float h = inf;
             if (f < nl) {
-                h = ld_f32(rc, cost_off, (uint32_t)f * cls);
+                const float m4[4] = {dpp_f<0x00>(mv[e], mv[e]), dpp_f<0x55>(mv[e], mv[e]), dpp_f<0xAA>(mv[e], mv[e]),
+                                     dpp_f<0xFF>(mv[e], mv[e])};
+                h = cv[e];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const float m = ld_f32(rm, moff[k], (uint32_t)f * cls);
-                    h += (k == q) ? 0.0f : m;
-                }
+                for (int k = 0; k < 4; ++k) h += (k == q) ? 0.0f : m4[k];
             }
-            hv[e] = h;
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int f = f0 + e;
-            const float h = hv[e];
             if (h < hmin) {
                 hmin = h;
                 gmin = f;
@@ -154,13 +158,13 @@ __device__ __forceinline__ void bwd_step(const BwdArgs &a, uint32_t block)
     }
     if (hq) {
 #pragma unroll
-        for (int f0 = 0; f0 < LP; f0 += 8) {
-            float mbv[8];
+        for (int f0 = 0; f0 < LP; f0 += kB1) {
+            float mbv[kB1];
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
+            for (int e = 0; e < kB1; ++e)
                 mbv[e] = (f0 + e < nl) ? ld_f32(rb, roff, (uint32_t)(f0 + e) * cls) : 0.0f;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
+            for (int e = 0; e < kB1; ++e) {
                 const int f = f0 + e;
                 if (!(f < nl)) continue;
                 const float mb = mbv[e];
@@ -180,14 +184,15 @@ __device__ __forceinline__ void bwd_step(const BwdArgs &a, uint32_t block)
     }
 
     // Sender side: cost-bar += sum_q hbar_q; slot k adjoint += sum_{q != k} hbar_q.
-    // Read-modify-writes are batched 8 labels at a time.
+    // Read-modify-writes are batched kB3 labels at a time.
+    constexpr int kB3 = LP < 16 ? LP : 16;
     const int64_t plane = (int64_t)a.h * a.w;
     float *gc0 = a.grad_cost + (int64_t)y * a.w + x;
 #pragma unroll 1
-    for (int f0 = 0; f0 < nl; f0 += 8) {
-        float hv[8], tot[8], cur[8], gcv[8];
+    for (int f0 = 0; f0 < nl; f0 += kB3) {
+        float hv[kB3], tot[kB3], cur[kB3], gcv[kB3];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < kB3; ++e) {
             const int f = f0 + e < nl ? f0 + e : nl - 1;
             hv[e] = f0 + e < nl ? hb[f * 64] : 0.0f;
             tot[e] = group_sum<4>(hv[e]);
@@ -195,7 +200,7 @@ __device__ __forceinline__ void bwd_step(const BwdArgs &a, uint32_t block)
             gcv[e] = (live && q == 0 && f0 + e < nl) ? gc0[(int64_t)f * plane] : 0.0f;
         }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < kB3; ++e) {
             const int f = f0 + e;
             if (!live || f >= nl) continue;
             if (has[q]) st_f32(rb, cur[e] + (tot[e] - hv[e]), moff[q], (uint32_t)f * cls);

@@ -723,10 +723,17 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
             const Plan &pl = plans[i];
             const size_t sb = pl.lv[0].msg_bytes;
             uint8_t *state = ws + pl.lv[0].msg_off;
-            if (t0 == 0) st = launch_init_messages(pl, ws, stream);
-            else st = launch_copy(ck[i] + (size_t)(t0 / every - 1) * sb, state, sb, stream);
-            for (int r = t0; r < t && st == BP_OK; ++r)
-                st = launch_iteration(pl, 0, r, 0, params->lambda, params->tau, nullptr, pl.variant, ws, stream);
+            const uint8_t *saved = t0 > 0 ? ck[i] + (size_t)(t0 / every - 1) * sb : nullptr;
+            if (saved && t == t0) {
+                // M_t is a saved state: the reverse step reads it in place.
+                bp[i].state = saved;
+            } else {
+                bp[i].state = state;
+                if (!saved) st = launch_init_messages(pl, ws, stream);
+                else st = launch_copy(saved, state, sb, stream);
+                for (int r = t0; r < t && st == BP_OK; ++r)
+                    st = launch_iteration(pl, 0, r, 0, params->lambda, params->tau, nullptr, pl.variant, ws, stream);
+            }
             bp[i].partial = partial + 2 * part;
             part += bwd_step_blocks(pl);
         }
