@@ -226,6 +226,7 @@ size_t bp_icp_workspace_size(int32_t n, int32_t m);
  *  - the next correspondences use the pose rounded to FP32.
  * Exact nearest neighbours as long as coordinates stay within about
  * 8e4 * dmax of the origin (a spatial hash of cells of edge dmax / 0.99).
+ * Points with a non-finite coordinate never pair.
  *   src [n][3], dst [m][3]   device float32 points (n, m >= 0)
  *   pose_in, pose_out        device float64 [12]: R row-major, then T
  *   rms, pairs               device [iters] per-iteration RMS distance of the

@@ -55,7 +55,15 @@ __device__ __forceinline__ uint32_t cell_bucket(const IcpHash &h, int ix, int iy
            ((((uint32_t)iy - (uint32_t)h.oy) & h.my) << h.sy);
 }
 
-__device__ __forceinline__ int cell_of(float v, float inv_cell) { return (int)__builtin_floorf(v * inv_cell); }
+// Integer cell of a floored coordinate, clamped to +-2^30 so that huge or
+// non-finite coordinates (NaN clamps to -2^30) still convert to a defined
+// integer; such points never pair anyway (their distances are not <= dmax^2).
+__device__ __forceinline__ int cell_index(float fl)
+{
+    return (int)__builtin_fminf(__builtin_fmaxf(fl, -0x1p30f), 0x1p30f);
+}
+
+__device__ __forceinline__ int cell_of(float v, float inv_cell) { return cell_index(__builtin_floorf(v * inv_cell)); }
 
 __device__ __forceinline__ uint32_t bucket_of(const IcpHash &h, float x, float y, float z, float inv_cell)
 {
@@ -280,7 +288,7 @@ __global__ void __launch_bounds__(kIcpBlock) k_icp_corr(const float4 *__restrict
         const float sv = q[a] * g.inv_cell;
         const float fl = __builtin_floorf(sv);
         const float fr = sv - fl;
-        c[a] = (int)fl;
+        c[a] = cell_index(fl);
         const float margin = (__builtin_fabsf(fl) + 4.0f) * (g.cell * 0x1p-22f);
         lo[a] = __builtin_fmaxf(fr * g.cell - margin, 0.0f);
         hi[a] = __builtin_fmaxf((1.0f - fr) * g.cell - margin, 0.0f);

@@ -138,3 +138,19 @@ def test_collinear_pairs_give_a_rotation(dev):
     _, _, rms, pairs, _ = oracle.icp(src, dst, np.eye(3), np.zeros(3), 20, 1.0)
     np.testing.assert_allclose(g["rms"][-1], rms[-1], rtol=1e-3)
     assert g["pairs"][-1] == pairs[-1]
+
+
+def test_non_finite_points_never_pair(dev):
+    """NaN and infinite coordinates (a hole in a disparity map, a point at
+    infinity) are paired with nothing and leave the other pairings as the
+    oracle makes them."""
+    src = surface(3000, 12, noise=0.02)
+    dst = surface(3000, 13, noise=0.02)
+    src[[5, 50, 500]] = [[np.nan, 0.0, 0.0], [np.inf, 1.0, 2.0], [0.0, -np.inf, np.nan]]
+    dst[[7, 70]] = [[np.nan, np.nan, np.nan], [1.0, np.inf, 0.0]]
+    R0, T0 = rot(0.01, 0.0, 0.0), np.array([0.05, 0.0, 0.0])
+    g = gpu_icp(src, dst, R0, T0, 1, 0.6, dev)
+    _, corr, _ = oracle.icp_correspond(src, dst, R0.astype(np.float32), T0.astype(np.float32), 0.6)
+    np.testing.assert_array_equal(g["corr"], corr)
+    assert (g["corr"][[5, 50, 500]] == -1).all() and not np.isin([7, 70], g["corr"]).any()
+    assert np.isfinite(g["pose"]).all()
