@@ -139,6 +139,17 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     bp_ms = e0.elapsed_time(e1) / reps
+    # The same bp_run captured once in a HIP graph and replayed (how the step
+    # runs it): launch gaps between its ~60 kernels shrink.
+    g_bp = _graph(lambda: bp.run(src, params, workspace=ws, outputs=outs))
+    g_bp.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        g_bp.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    bp_graph_ms = e0.elapsed_time(e1) / reps
 
     # Dominant kernel: the level-0 half-sweep (k_iter_pm), timed with a HIP
     # event pair recorded on its launch stream around the level's K
@@ -210,6 +221,8 @@ def main():
         "updates_per_step": updates,
         "bp_run_ms": round(bp_ms, 4),
         "bp_run_updates_per_s": round(updates / (bp_ms * 1e-3), 1),
+        "bp_run_graph_ms": round(bp_graph_ms, 4),
+        "bp_run_graph_updates_per_s": round(updates / (bp_graph_ms * 1e-3), 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
