@@ -303,7 +303,6 @@ __global__ void __launch_bounds__(256) k_bwd_readout(const float *__restrict__ c
     }
 }
 
-// Deterministic sum of the per-block partials (fixed order), one thread.
 // Deterministic sum of the (lambda, tau) partials: thread i of one 1024-thread
 // block adds partials i, i + 1024, ... in FP64 in that order, then a fixed
 // binary tree over the threads combines them.  The order never depends on
