@@ -303,35 +303,60 @@ __global__ void __launch_bounds__(256) k_bwd_readout(const float *__restrict__ c
     }
 }
 
-// Deterministic sum of the (lambda, tau) partials: thread i of one 1024-thread
-// block adds partials i, i + 1024, ... in FP64 in that order, then a fixed
-// binary tree over the threads combines them.  The order never depends on
-// scheduling, so repeated calls give identical bits.
-__global__ void __launch_bounds__(1024) k_bwd_finish(const float *__restrict__ partial, int n, float *grad_lambda,
-                                                    float *grad_tau)
+// Deterministic sum of the (lambda, tau) partials in two passes.  Pass 1:
+// block b of kFinishBlocks takes the contiguous chunk b of the partials;
+// thread t adds entries t, t + 256, ... of the chunk in FP64 in that order,
+// then a fixed binary tree over the threads.  Pass 2: one block adds the
+// block sums with the same tree.  The order depends only on the number of
+// partials, so repeated calls give identical bits.
+constexpr int kFinishBlocks = 256;
+
+__device__ __forceinline__ void tree_sum_256(double &l, double &t, double *sl, double *st)
 {
-    __shared__ double sl[1024], st[1024];
     const int i = threadIdx.x;
-    double l = 0.0, t = 0.0;
-    for (int k = i; k < n; k += 1024) {
-        l += partial[2 * k];
-        t += partial[2 * k + 1];
-    }
     sl[i] = l;
     st[i] = t;
     __syncthreads();
-    for (int h = 512; h >= 1; h >>= 1) {
+    for (int h = 128; h >= 1; h >>= 1) {
         if (i < h) {
             sl[i] += sl[i + h];
             st[i] += st[i + h];
         }
         __syncthreads();
     }
-    if (i == 0) {
-        *grad_lambda = (float)sl[0];
-        *grad_tau = (float)st[0];
+    l = sl[0];
+    t = st[0];
+}
+
+__global__ void __launch_bounds__(256) k_bwd_finish_part(const float2 *__restrict__ partial, int n, int chunk,
+                                                        double2 *__restrict__ out)
+{
+    __shared__ double sl[256], st[256];
+    const int lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    double l = 0.0, t = 0.0;
+    for (int k = lo + (int)threadIdx.x; k < hi; k += 256) {
+        const float2 v = partial[k];
+        l += v.x;
+        t += v.y;
+    }
+    tree_sum_256(l, t, sl, st);
+    if (threadIdx.x == 0) out[blockIdx.x] = make_double2(l, t);
+}
+
+__global__ void __launch_bounds__(256) k_bwd_finish(const double2 *__restrict__ sums, float *grad_lambda,
+                                                   float *grad_tau)
+{
+    __shared__ double sl[256], st[256];
+    const double2 v = sums[threadIdx.x];
+    double l = v.x, t = v.y;
+    tree_sum_256(l, t, sl, st);
+    if (threadIdx.x == 0) {
+        *grad_lambda = (float)l;
+        *grad_tau = (float)t;
     }
 }
+
+size_t bwd_finish_bytes() { return align_up((size_t)kFinishBlocks * sizeof(double2)); }
 
 // Byte copy with 16-byte words (sizes are multiples of 256).
 __global__ void __launch_bounds__(256) k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n)
@@ -435,9 +460,13 @@ bp_status launch_bwd_step_batch(const BwdProblem *probs, int count, int t, float
     return st;
 }
 
-bp_status launch_bwd_finish(const float *partial, int n, float *grad_lambda, float *grad_tau, hipStream_t s)
+bp_status launch_bwd_finish(const float *partial, int n, float *grad_lambda, float *grad_tau, uint8_t *scratch,
+                            hipStream_t s)
 {
-    k_bwd_finish<<<1, 1024, 0, s>>>(partial, n, grad_lambda, grad_tau);
+    double2 *sums = (double2 *)scratch;
+    const int chunk = (n + kFinishBlocks - 1) / kFinishBlocks;
+    k_bwd_finish_part<<<kFinishBlocks, 256, 0, s>>>((const float2 *)partial, n, chunk > 0 ? chunk : 1, sums);
+    k_bwd_finish<<<1, 256, 0, s>>>(sums, grad_lambda, grad_tau);
     return launch_status();
 }
 

@@ -111,6 +111,10 @@ bool tuned_choice(int w, int h, int L, int fmt, int levels, int *pm_from, int *v
     return true;
 }
 
+// The adjoint works on label-major states when the caller asks for them
+// (pm_from = levels), otherwise on pixel-major ones.
+static bool adjoint_label_major(const bp_params &p) { return p.pm_from == p.levels; }
+
 // Problem plans laid out back to back in the workspace.
 bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *plans, size_t *total)
 {
@@ -121,14 +125,18 @@ bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
         if (pm_from < 0 && !(p->variant == 0 && tuned_choice(q.width, q.height, q.num_labels, p->msg_dtype,
                                                              p->levels, &pm_from, &tv)))
             pm_from = default_pm_from(q.width, q.height, q.num_labels, p->levels, p->msg_dtype);
-        // The adjoint kernels work on label-major states.
-        if (p->checkpoint_every > 0) pm_from = p->levels;
+        // A forward call that saves states for the adjoint stores them
+        // pixel-major (or label-major when asked with pm_from = levels), the
+        // layouts the two adjoints read.
+        if (p->checkpoint_every > 0) pm_from = adjoint_label_major(*p) ? p->levels : 0;
         if (!make_plan(q.width, q.height, q.num_labels, p->levels, p->msg_dtype, pm_from, off, &plans[i])) return false;
         if (!q.cost) {
             plans[i].pair_off = off + plans[i].bytes;
             plans[i].bytes += align_up((size_t)2 * q.width * q.height * sizeof(uint32_t));
         }
         plans[i].variant = p->variant != 0 ? p->variant : tv != 0 ? tv : default_variant(q.num_labels, p->msg_dtype);
+        // The pixel-major adjoint repeats the sums of the plain-load split.
+        if (p->checkpoint_every > 0 && pm_from == 0) plans[i].variant = 1;
         off += plans[i].bytes;
     }
     *total = align_up(off);
@@ -613,27 +621,32 @@ bp_status bp_upsample_points(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo,
 }
 
 // Backward workspace: per problem its forward plan (cost + a message state
-// rebuilt from checkpoints) and the message adjoint, then the (lambda, tau)
-// partials of every reverse step of every problem.
+// rebuilt from checkpoints), the message adjoint and, for pixel-major states,
+// the cost adjoint in the cost's layout; then the (lambda, tau) partials of
+// every reverse step of every problem and the launch table.
 static bool backward_layout(const bp_problem *probs, int32_t count, const bp_params *params, Plan *plans,
-                            size_t *mbar_off, size_t *partial_off, int *n_partial, size_t *table_off, size_t *total)
+                            size_t *mbar_off, size_t *gcost_off, size_t *partial_off, int *n_partial,
+                            size_t *table_off, size_t *total)
 {
+    const bool lm = adjoint_label_major(*params);
     size_t off = 0;
     int np = 0;
     for (int i = 0; i < count; ++i) {
         const bp_problem &q = probs[i];
-        if (!make_plan(q.width, q.height, q.num_labels, 1, BP_MSG_F32, 1, off, &plans[i])) return false;
-        plans[i].variant = params->variant;
+        if (!make_plan(q.width, q.height, q.num_labels, 1, BP_MSG_F32, lm ? 1 : 0, off, &plans[i])) return false;
+        plans[i].variant = lm ? params->variant : 1;
         off += plans[i].bytes;
         mbar_off[i] = off;
         off += plans[i].lv[0].msg_bytes;
-        np += params->iters_per_level * bwd_step_blocks(plans[i]);
+        gcost_off[i] = off;
+        if (!lm) off += plans[i].lv[0].cost_bytes;
+        np += params->iters_per_level * (lm ? bwd_step_blocks(plans[i]) : bwd_pm_blocks(plans[i]));
     }
     *partial_off = off;
     *n_partial = np;
     off += align_up((size_t)(np > 0 ? np : 1) * 2 * sizeof(float));
     *table_off = off;
-    off += bwd_table_bytes(count);
+    off += std::max(bwd_table_bytes(count), bwd_pm_table_bytes(count)) + bwd_finish_bytes();
     *total = off;
     return true;
 }
@@ -654,12 +667,13 @@ size_t bp_backward_workspace_size(const bp_problem *probs, int32_t count, const 
     for (int i = 0; i < count; ++i)
         if (probs[i].num_labels > kMaxBackwardLabels) return 0;
     Plan *plans = new Plan[count];
-    size_t *mo = new size_t[count];
+    size_t *mo = new size_t[count], *go = new size_t[count];
     size_t po = 0, to = 0, total = 0;
     int np = 0;
-    bool ok = backward_layout(probs, count, params, plans, mo, &po, &np, &to, &total);
+    bool ok = backward_layout(probs, count, params, plans, mo, go, &po, &np, &to, &total);
     delete[] plans;
     delete[] mo;
+    delete[] go;
     return ok ? total : 0;
 }
 
@@ -676,18 +690,20 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
     for (int i = 0; i < count; ++i)
         if (probs[i].num_labels > kMaxBackwardLabels) return BP_ERR_UNSUPPORTED;
     Plan *plans = new Plan[count];
-    size_t *mo = new size_t[count];
+    size_t *mo = new size_t[count], *go = new size_t[count];
     size_t po = 0, to = 0, total = 0;
     int np = 0;
     bp_status st = BP_OK;
     const int K = params->iters_per_level, every = params->checkpoint_every;
-    if (!backward_layout(probs, count, params, plans, mo, &po, &np, &to, &total)) st = BP_ERR_UNSUPPORTED;
+    const bool lm = adjoint_label_major(*params);
+    if (!backward_layout(probs, count, params, plans, mo, go, &po, &np, &to, &total)) st = BP_ERR_UNSUPPORTED;
     size_t ck_total = 0;
     for (int i = 0; st == BP_OK && i < count; ++i) ck_total += checkpoint_bytes_of(plans[i], K, every);
     if (st == BP_OK && (ws_bytes < total || ckpt_bytes < ck_total)) st = BP_ERR_WORKSPACE_TOO_SMALL;
     if (st != BP_OK) {
         delete[] plans;
         delete[] mo;
+        delete[] go;
         return st;
     }
     (void)hipGetLastError();
@@ -695,9 +711,10 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
     float *partial = (float *)(ws + po);
     const int nst = checkpoint_states(K, every);
     // Per problem: its checkpoints, state buffer, adjoints; the readout adjoint
-    // from the final state initialises the message adjoint and grad_cost.
+    // from the final state initialises the message adjoint and the cost adjoint.
     const uint8_t **ck = new const uint8_t *[count];
     BwdProblem *bp = new BwdProblem[count];
+    BwdPmProblem *bq = new BwdPmProblem[count];
     {
         const uint8_t *c = (const uint8_t *)checkpoints;
         size_t soft_off = 0, cost_off = 0;
@@ -706,10 +723,17 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
             const size_t sb = pl.lv[0].msg_bytes;
             ck[i] = c;
             c += (size_t)nst * sb;
-            bp[i] = BwdProblem{&pl, ws, ws + pl.lv[0].msg_off, (float *)(ws + mo[i]), grad_cost + cost_off, nullptr};
+            float *mbar = (float *)(ws + mo[i]);
+            bp[i] = BwdProblem{&pl, ws, ws + pl.lv[0].msg_off, mbar, grad_cost + cost_off, nullptr};
+            bq[i] = BwdPmProblem{&pl, ws, ws + pl.lv[0].msg_off, mbar, (float *)(ws + go[i]), nullptr};
             if ((st = launch_split_cost(probs[i].cost, pl, ws, stream)) != BP_OK) break;
-            st = launch_bwd_readout(pl, ck[i] + (size_t)(nst - 1) * sb, bp[i].mbar, grad_soft + soft_off,
-                                    bp[i].grad_cost, params->temperature, ws, stream);
+            const uint8_t *last = ck[i] + (size_t)(nst - 1) * sb;
+            if (lm)
+                st = launch_bwd_readout(pl, last, mbar, grad_soft + soft_off, bp[i].grad_cost, params->temperature, ws,
+                                        stream);
+            else
+                st = launch_bwd_readout_pm(pl, last, mbar, bq[i].gcost, grad_soft + soft_off, params->temperature, ws,
+                                           stream);
             soft_off += (size_t)probs[i].height * probs[i].width;
             cost_off += (size_t)probs[i].num_labels * probs[i].height * probs[i].width;
         }
@@ -724,26 +748,40 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
             const size_t sb = pl.lv[0].msg_bytes;
             uint8_t *state = ws + pl.lv[0].msg_off;
             const uint8_t *saved = t0 > 0 ? ck[i] + (size_t)(t0 / every - 1) * sb : nullptr;
+            const uint8_t *mt = state;
             if (saved && t == t0) {
                 // M_t is a saved state: the reverse step reads it in place.
-                bp[i].state = saved;
+                mt = saved;
             } else {
-                bp[i].state = state;
                 if (!saved) st = launch_init_messages(pl, ws, stream);
                 else st = launch_copy(saved, state, sb, stream);
                 for (int r = t0; r < t && st == BP_OK; ++r)
                     st = launch_iteration(pl, 0, r, 0, params->lambda, params->tau, nullptr, pl.variant, ws, stream);
             }
-            bp[i].partial = partial + 2 * part;
-            part += bwd_step_blocks(pl);
+            bp[i].state = bq[i].state = mt;
+            bp[i].partial = bq[i].partial = partial + 2 * part;
+            part += lm ? bwd_step_blocks(pl) : bwd_pm_blocks(pl);
         }
-        if (st == BP_OK) st = launch_bwd_step_batch(bp, count, t, params->lambda, params->tau, ws + to, stream);
+        if (st != BP_OK) break;
+        if (lm) st = launch_bwd_step_batch(bp, count, t, params->lambda, params->tau, ws + to, stream);
+        else st = launch_bwd_step_pm_batch(bq, count, t, t == K - 1, params->lambda, params->tau, ws + to, stream);
+    }
+    if (!lm) {
+        size_t cost_off = 0;
+        for (int i = 0; i < count && st == BP_OK; ++i) {
+            st = launch_gcost_to_planar(plans[i], bq[i].gcost, grad_cost + cost_off, stream);
+            cost_off += (size_t)probs[i].num_labels * probs[i].height * probs[i].width;
+        }
     }
     delete[] ck;
     delete[] bp;
-    if (st == BP_OK) st = launch_bwd_finish(partial, np, grad_lambda, grad_tau, stream);
+    delete[] bq;
+    if (st == BP_OK)
+        st = launch_bwd_finish(partial, np, grad_lambda, grad_tau,
+                               ws + to + std::max(bwd_table_bytes(count), bwd_pm_table_bytes(count)), stream);
     delete[] plans;
     delete[] mo;
+    delete[] go;
     return st;
 }
 

@@ -239,7 +239,9 @@ __global__ void __launch_bounds__(256) k_init_msgs(InitArgs a)
     const int l = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (l == a.levels) {
-        if (i < a.coarsest_words) ((uint32_t *)a.msg[a.levels - 1])[i] = 0u;
+        // The coarsest level's whole state, 16 bytes per thread (its size is
+        // a multiple of 256 bytes).
+        if (i < a.coarsest_words / 4) ((uint4 *)a.msg[a.levels - 1])[i] = make_uint4(0u, 0u, 0u, 0u);
         return;
     }
     const LevelDesc &d = a.d[l];
@@ -271,7 +273,7 @@ bp_status launch_init_messages(const Plan &p, uint8_t *ws, hipStream_t s)
     a.L = p.L;
     a.levels = p.levels;
     a.coarsest_words = (int64_t)(p.lv[p.levels - 1].msg_bytes / 4);
-    if (a.coarsest_words > most) most = a.coarsest_words;
+    if (a.coarsest_words / 4 > most) most = a.coarsest_words / 4;
     k_init_msgs<<<dim3(cdiv(most, 256), p.levels + 1), 256, 0, s>>>(a);
     return launch_status();
 }

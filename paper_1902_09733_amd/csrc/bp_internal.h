@@ -159,11 +159,32 @@ struct BwdProblem {
 size_t bwd_table_bytes(int count);
 // The reverse step keeps a pixel's message row in registers: up to 128 labels.
 constexpr int kMaxBackwardLabels = 128;
+
+// a8 on pixel-major states (bp_adjoint_pm.hip): the same steps with the
+// forward kernel's lane split; the cost adjoint is accumulated pixel-major
+// (`gcost`, laid out like the level's cost) and written planar at the end.
+struct BwdPmProblem {
+    const Plan *plan;
+    uint8_t *ws;            // workspace holding the plan's cost
+    const uint8_t *state;   // message state M_t
+    float *mbar;            // message adjoint
+    float *gcost;           // cost adjoint, pixel-major
+    float *partial;         // bwd_pm_blocks(plan) (lambda, tau) pairs
+};
+int bwd_pm_blocks(const Plan &p);
+size_t bwd_pm_table_bytes(int count);
+bp_status launch_bwd_readout_pm(const Plan &p, const uint8_t *msg, float *mbar, float *gcost, const float *grad_soft,
+                                float temperature, uint8_t *ws, hipStream_t s);
+bp_status launch_bwd_step_pm_batch(const BwdPmProblem *probs, int count, int t, bool first_step, float lambda,
+                                   float tau, uint8_t *table, hipStream_t s);
+bp_status launch_gcost_to_planar(const Plan &p, const float *gcost, float *grad_cost, hipStream_t s);
 // Reverse half-sweep t of every problem, one launch per label count; the
 // launch entries are written into `table` (bwd_table_bytes(count) bytes).
 bp_status launch_bwd_step_batch(const BwdProblem *probs, int count, int t, float lambda, float tau, uint8_t *table,
                                 hipStream_t s);
-bp_status launch_bwd_finish(const float *partial, int n, float *grad_lambda, float *grad_tau, hipStream_t s);
+size_t bwd_finish_bytes();
+bp_status launch_bwd_finish(const float *partial, int n, float *grad_lambda, float *grad_tau, uint8_t *scratch,
+                            hipStream_t s);
 bp_status dispatch_iter_pm(const IterArgs &a, int fmt, int S, int R, bool ro, bool xchg, hipStream_t s);
 
 // Pixel-major kernel variants (1 default split; 2 half the lanes per message,

@@ -31,9 +31,12 @@ def jittered(shape, seed):
     return (rng.integers(0, 20, size=shape) + rng.uniform(0.0, 0.5, size=shape)).astype(np.float32).astype(np.float64)
 
 
-def gpu_grad(costs, g, K, lam, tau, T, every, dev):
+def gpu_grad(costs, g, K, lam, tau, T, every, dev, layout="pm"):
+    """Forward with checkpoints and backward; layout "pm" is the default
+    pixel-major adjoint, "lm" the label-major one (pm_from = levels)."""
     import paper_1902_09733_amd as bp
-    p = bp.BPParams(levels=1, iters=K, lam=lam, tau=tau, temperature=T, checkpoint_every=every)
+    p = bp.BPParams(levels=1, iters=K, lam=lam, tau=tau, temperature=T, checkpoint_every=every,
+                    pm_from=1 if layout == "lm" else -1)
     vols = [torch.from_numpy(c.astype(np.float32)).to(dev) for c in costs]
     ck = torch.empty(bp.checkpoint_bytes(vols, p), dtype=torch.uint8, device=dev)
     outs = bp.run(vols, p, want_disp=False, want_soft=True, checkpoints=ck)
@@ -47,13 +50,14 @@ def gpu_grad(costs, g, K, lam, tau, T, every, dev):
 @pytest.mark.parametrize("shape,K,every", [((16, 12, 20), 1, 1), ((32, 12, 20), 5, 2), ((64, 9, 14), 8, 2),
                                            ((32, 7, 11), 6, 3), ((20, 10, 13), 4, 4), ((64, 1, 33), 7, 2),
                                            ((5, 9, 13), 3, 1), ((100, 6, 9), 4, 2), ((128, 5, 7), 3, 3)])
-def test_adjoint_matches_oracle_adjoint(dev, shape, K, every):
+@pytest.mark.parametrize("layout", ["pm", "lm"])
+def test_adjoint_matches_oracle_adjoint(dev, shape, K, every, layout):
     L, H, W = shape
     rng = np.random.default_rng(L + H + K)
     costs = [jittered(shape, 11 + i) for i in range(2)]
     g = [rng.normal(size=(H, W)) for _ in costs]
     lam, tau, T = 3.0, 2.5, 0.5
-    soft, gc, gl, gt = gpu_grad(costs, g, K, lam, tau, T, every, dev)
+    soft, gc, gl, gt = gpu_grad(costs, g, K, lam, tau, T, every, dev, layout)
     ol = ot = 0.0
     for i, c in enumerate(costs):
         s_o, gc_o, gl_o, gt_o = oracle.backward(c, K, lam, tau, T, g[i])
@@ -70,15 +74,16 @@ def test_adjoint_matches_oracle_adjoint(dev, shape, K, every):
     assert abs(gt - ot) <= DIR_TOL * max(1.0, abs(ot)), (gt, ot)
 
 
-def test_adjoint_mixed_label_counts(dev):
+@pytest.mark.parametrize("layout", ["pm", "lm"])
+def test_adjoint_mixed_label_counts(dev, layout):
     """One backward call over problems of different sizes and label counts
-    (one batched reverse launch per label count)."""
+    (one batched reverse launch per label count or lane split)."""
     shapes = [(20, 9, 14), (33, 7, 12), (20, 5, 6), (64, 8, 10)]
     K, every, lam, tau, T = 5, 2, 3.0, 2.5, 0.5
     costs = [jittered(sh, 40 + i) for i, sh in enumerate(shapes)]
     rng = np.random.default_rng(9)
     g = [rng.normal(size=sh[1:]) for sh in shapes]
-    soft, gc, gl, gt = gpu_grad(costs, g, K, lam, tau, T, every, dev)
+    soft, gc, gl, gt = gpu_grad(costs, g, K, lam, tau, T, every, dev, layout)
     ol = ot = 0.0
     for i, c in enumerate(costs):
         s_o, gc_o, gl_o, gt_o = oracle.backward(c, K, lam, tau, T, g[i])
@@ -87,6 +92,28 @@ def test_adjoint_mixed_label_counts(dev):
         scale = np.abs(gc_o).max()
         close = np.abs(gc[i] - gc_o) <= 1e-3 * scale + 1e-5
         assert close.mean() >= 0.999, (i, close.mean())
+    assert abs(gl - ol) <= DIR_TOL * max(1.0, abs(ol)), (gl, ol)
+    assert abs(gt - ot) <= DIR_TOL * max(1.0, abs(ot)), (gt, ot)
+
+
+@pytest.mark.parametrize("lam,tau", [(0.0, 2.5), (1.5, 40.0), (4.0, 0.6)])
+def test_pixel_major_adjoint_smoothness_edges(dev, lam, tau):
+    """No smoothness (any label can win, the scatter scans every label), a
+    truncation wider than the label range, and tau below one label."""
+    shape, K, every, T = (48, 10, 13), 5, 2, 0.5
+    costs = [jittered(shape, 70 + i) for i in range(2)]
+    rng = np.random.default_rng(3)
+    g = [rng.normal(size=shape[1:]) for _ in costs]
+    soft, gc, gl, gt = gpu_grad(costs, g, K, lam, tau, T, every, dev)
+    ol = ot = 0.0
+    for i, c in enumerate(costs):
+        s_o, gc_o, gl_o, gt_o = oracle.backward(c, K, lam, tau, T, g[i])
+        ol += gl_o
+        ot += gt_o
+        assert np.abs(soft[i] - s_o).max() <= 1e-3
+        scale = max(np.abs(gc_o).max(), 1e-12)
+        close = np.abs(gc[i] - gc_o) <= 1e-3 * scale + 1e-5
+        assert close.mean() >= 0.999, close.mean()
     assert abs(gl - ol) <= DIR_TOL * max(1.0, abs(ol)), (gl, ol)
     assert abs(gt - ot) <= DIR_TOL * max(1.0, abs(ot)), (gt, ot)
 
