@@ -727,6 +727,9 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
             bp[i] = BwdProblem{&pl, ws, ws + pl.lv[0].msg_off, mbar, grad_cost + cost_off, nullptr};
             bq[i] = BwdPmProblem{&pl, ws, ws + pl.lv[0].msg_off, mbar, (float *)(ws + go[i]), nullptr};
             if ((st = launch_split_cost(probs[i].cost, pl, ws, stream)) != BP_OK) break;
+            // Zero state: its out-of-grid slots are never written afterwards, and
+            // replays below write only the slots the reverse steps read.
+            if ((st = launch_init_messages(pl, ws, stream)) != BP_OK) break;
             const uint8_t *last = ck[i] + (size_t)(nst - 1) * sb;
             if (lm)
                 st = launch_bwd_readout(pl, last, mbar, grad_soft + soft_off, bp[i].grad_cost, params->temperature, ws,
@@ -753,9 +756,18 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
                 // M_t is a saved state: the reverse step reads it in place.
                 mt = saved;
             } else {
-                if (!saved) st = launch_init_messages(pl, ws, stream);
-                else st = launch_copy(saved, state, sb, stream);
-                for (int r = t0; r < t && st == BP_OK; ++r)
+                // Half-sweep r reads the slots of colour r & 1 and writes those of
+                // the other colour, and the reverse step at t reads only the slots
+                // of colour t & 1: the first replay reads the saved state in place
+                // and writes into the state buffer, no copy needed.
+                int r = t0;
+                if (!saved) {
+                    st = launch_init_messages(pl, ws, stream);
+                } else {
+                    st = launch_iteration_from(pl, r, saved, params->lambda, params->tau, pl.variant, ws, stream);
+                    ++r;
+                }
+                for (; r < t && st == BP_OK; ++r)
                     st = launch_iteration(pl, 0, r, 0, params->lambda, params->tau, nullptr, pl.variant, ws, stream);
             }
             bp[i].state = bq[i].state = mt;

@@ -395,6 +395,21 @@ bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lamb
     return dispatch_iter_lm(a, v.fmt, iteration_lanes(p.L, variant), disp != nullptr, s);
 }
 
+bp_status launch_iteration_from(const Plan &p, int t, const uint8_t *src, float lambda, float tau, int variant,
+                                uint8_t *ws, hipStream_t s)
+{
+    const Level &v = p.lv[0];
+    IterArgs a = make_iter_args(p, 0, t, 0, lambda, tau, nullptr, ws);
+    a.src = src;
+    if (v.layout == PIXEL_MAJOR) {
+        int S, R;
+        bool xchg;
+        pm_split_variant(p.L, variant, &S, &R, &xchg);
+        return dispatch_iter_pm(a, v.fmt, S, R, false, xchg, s);
+    }
+    return dispatch_iter_lm(a, v.fmt, iteration_lanes(p.L, variant), false, s);
+}
+
 // ------------------------------------------------------------------------
 // a6: readout, message export
 // ------------------------------------------------------------------------

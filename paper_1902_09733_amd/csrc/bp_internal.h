@@ -95,6 +95,11 @@ bp_status launch_parent_copy(const Plan &p, int l, uint8_t *ws, hipStream_t s);
 // If disp != NULL the senders' argmin labels are written (finest level).
 bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lambda, float tau,
                            int32_t *disp, int variant, uint8_t *ws, hipStream_t s);
+// Half-sweep t of the finest level reading its incoming messages from `src`
+// (a saved state in the level's layout) and writing the receivers' slots
+// into the level's own message buffer.
+bp_status launch_iteration_from(const Plan &p, int t, const uint8_t *src, float lambda, float tau, int variant,
+                                uint8_t *ws, hipStream_t s);
 
 // a6: readout of the pixels of `colour_mask` (bit c = colour c) at level 0.
 bp_status launch_readout(const Plan &p, int colour_mask, int32_t *disp, float *soft, float temperature,
