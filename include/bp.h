@@ -89,8 +89,10 @@ typedef struct {
     float tau;                 /* truncation in labels > 0 */
     int32_t msg_dtype;         /* bp_msg_dtype */
     float temperature;         /* soft-argmin temperature T > 0 (used when soft_disparity != NULL) */
-    int32_t checkpoint_every;  /* 0 = none; k > 0 saves the message state every k half-sweeps
-                                  of the finest level into the checkpoint buffer (adjoint) */
+    int32_t checkpoint_every;  /* 0 = none; k > 0 saves, every k half-sweeps of the finest
+                                  level, the part of the message state the adjoint reads
+                                  (and the whole final state) into the checkpoint buffer,
+                                  whose contents only bp_backward interprets */
     int32_t variant;           /* 0 = library choice; otherwise a half-sweep kernel variant in
                                   1..bp_variant_count() (testing and tuning).  Label-major
                                   levels: lanes per pixel 1/2/4 by label count.  Pixel-major

@@ -209,9 +209,15 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
                 r.ms = 0.0f;
             }
             if (ckpt && (t + 1) % p.checkpoint_every == 0 && t + 1 < K) {
-                const size_t sb = pl.lv[0].msg_bytes;
-                if ((st = launch_copy(ws + pl.lv[0].msg_off, ckpt + (size_t)((t + 1) / p.checkpoint_every - 1) * sb, sb,
-                                      s)) != BP_OK)
+                // The adjoint reads a saved state M_{t+1} only through half-sweep
+                // t + 1's senders (the reverse step at t + 1, or the replay from
+                // it), i.e. the four slots of colour (t + 1) & 1, which are one
+                // contiguous half of the state (out-of-grid slots included).
+                const Level &v0 = pl.lv[0];
+                const size_t sb = v0.msg_bytes, half = (size_t)4 * v0.blk * fmt_bytes(v0.fmt);
+                const size_t at = (size_t)((t + 1) & 1) * half;
+                if ((st = launch_copy(ws + v0.msg_off + at, ckpt + (size_t)((t + 1) / p.checkpoint_every - 1) * sb + at,
+                                      half, s)) != BP_OK)
                     return st;
             }
         }
