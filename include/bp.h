@@ -364,7 +364,11 @@ bp_status bp_upsample_points(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo,
  * linear; the derivative follows the branch the forward pass took (forward
  * pass keeps h(f) on ties, backward pass keeps the current value, truncation
  * only when strictly smaller), and lambda/tau are shared scalars whose
- * gradients sum over the problems (reduced in a fixed order).
+ * gradients sum over the problems (reduced in a fixed order).  The forward
+ * call stores its states pixel-major (the default) or label-major
+ * (params->pm_from == levels); bp_backward uses the matching adjoint
+ * kernels, so both calls must get the same params.  Results are
+ * deterministic: repeated calls give identical bits.
  *   grad_soft   device float32, the problems' [H][W] arrays concatenated
  *   grad_cost   device float32, the problems' [L][H][W] arrays concatenated, overwritten
  *   grad_lambda, grad_tau  device float32[1] each, overwritten
