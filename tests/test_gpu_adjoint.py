@@ -188,3 +188,18 @@ def test_autograd_batch_matches_finite_differences(dev):
     V = np.random.default_rng(100).normal(size=C.shape)
     fd4 = sum(ell(i, C[i] + 1e-4 * V[i]) - ell(i, C[i] - 1e-4 * V[i]) for i in range(8)) / 2e-4
     print(f"batch fd(1e-4) {fd4:.6f} (kink-polluted reference)", flush=True)
+
+
+@pytest.mark.parametrize("layout", ["pm", "lm"])
+def test_adjoint_is_deterministic(dev, layout):
+    """Two backward calls on the same inputs give identical bits (fixed
+    summation orders everywhere, no atomics on floating-point values)."""
+    shape, K, every = (64, 24, 37), 6, 2
+    costs = [jittered(shape, 90 + i) for i in range(3)]
+    rng = np.random.default_rng(4)
+    g = [rng.normal(size=shape[1:]) for _ in costs]
+    a = gpu_grad(costs, g, K, 3.0, 2.5, 0.5, every, dev, layout)
+    b = gpu_grad(costs, g, K, 3.0, 2.5, 0.5, every, dev, layout)
+    for x, y in zip(a[1], b[1]):
+        np.testing.assert_array_equal(x, y)
+    assert a[2] == b[2] and a[3] == b[3]
