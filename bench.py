@@ -192,9 +192,11 @@ def main():
         "all_levels_GBps": round(all_bytes / (all_ms * 1e-3) / 1e9, 1),
     }
 
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, updates, args.cpu_seconds)
+        # The same oracle on one core: one repetition (about 10 s).
+        cpu1 = cpu_baseline(wl, updates, 0.0, threads=1)
 
     out = {
         "metric": METRIC,
@@ -225,27 +227,30 @@ def main():
         "bp_run_graph_updates_per_s": round(updates / (bp_graph_ms * 1e-3), 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_1core": cpu1,
     }
     print(json.dumps(out))
 
 
-def cpu_baseline(wl, updates, budget_s):
-    """The FP64 oracle (as it stands) on the host cores: cost + 5-level BP of
-    the same pair, repeated for about `budget_s` seconds."""
+def cpu_baseline(wl, updates, budget_s, threads=0):
+    """The FP64 oracle (as it stands) on the host cores (all of them, or
+    `threads`): cost + 5-level BP of the same pair, repeated for about
+    `budget_s` seconds (at least once)."""
     import oracle
     S, L = wl["downsample"], wl["num_labels"]
+    n = threads or oracle.max_threads()
     l4 = oracle.downsample(wl["left"], S)
     r4 = oracle.downsample(wl["right"], S)
     reps, t0 = 0, time.perf_counter()
     while True:
         c = oracle.cost_volume(l4, r4, L, wl["data_trunc"])
-        oracle.run(c, wl["levels"], wl["iters"], wl["lam"], wl["tau"])
+        oracle.run(c, wl["levels"], wl["iters"], wl["lam"], wl["tau"], nthreads=n)
         reps += 1
         el = time.perf_counter() - t0
         if el >= budget_s or reps >= 50:
             break
     return {
-        "value": round(reps * updates / el, 1), "unit": "updates/s", "cores": oracle.max_threads(),
+        "value": round(reps * updates / el, 1), "unit": "updates/s", "cores": n,
         "kind": "oracle",
         "sample": f"{reps} x (downsampled-pair cost volume + 5-level BP, {updates/1e6:.2f} M updates) of the "
                   f"benchmarked pair, {el:.1f} s",
