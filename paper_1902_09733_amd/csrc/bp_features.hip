@@ -73,31 +73,66 @@ __global__ void __launch_bounds__(256) k_harris_response(const uint8_t *__restri
 }
 
 // One block per cell: the largest response above the threshold among the
-// cell's 3 x 3 local maxima, first in row-major order on ties.
+// cell's 3 x 3 local maxima, first in row-major order on ties.  The cell is
+// taken in strips of rows whose responses, with a one-pixel border, are
+// staged in LDS by coalesced loads (outside the frame: INT64_MIN, never
+// larger); cells wider than the staging row fall back to global loads.
+constexpr int kSelTile = 4096;          // int64 responses staged per strip
+
+__device__ __forceinline__ void take_best(int64_t v, int64_t idx, int64_t &bv, int64_t &bi)
+{
+    if (bi < 0 || v > bv || (v == bv && idx < bi)) {
+        bv = v;
+        bi = idx;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_harris_select(const int64_t *__restrict__ r25, int w, int h, int g,
                                                       int64_t thr, bp_corner *__restrict__ out)
 {
+    __shared__ int64_t s_t[kSelTile];
     __shared__ int64_t s_v[256];
     __shared__ int64_t s_i[256];
     const int ci = blockIdx.x / g, cj = blockIdx.x - ci * g;
     const int x0 = (int)((int64_t)cj * w / g), x1 = (int)((int64_t)(cj + 1) * w / g);
     const int y0 = (int)((int64_t)ci * h / g), y1 = (int)((int64_t)(ci + 1) * h / g);
-    const int cw = x1 - x0, n = cw * (y1 - y0);
+    const int cw = x1 - x0, ch = y1 - y0;
     int64_t bv = 0, bi = -1;       // best value and row-major index of its pixel
-    for (int k = threadIdx.x; k < n; k += 256) {
-        const int y = y0 + k / cw, x = x0 + k % cw;
-        const int64_t v = r25[(int64_t)y * w + x];
-        if (v <= thr) continue;
-        bool peak = true;
-        for (int j = -1; j <= 1; ++j)
-            for (int i = -1; i <= 1; ++i) {
-                const int nx = x + i, ny = y + j;
-                if ((i || j) && nx >= 0 && ny >= 0 && nx < w && ny < h && r25[(int64_t)ny * w + nx] > v) peak = false;
+    const int tw = cw + 2;
+    const int sr = kSelTile / tw - 2; // rows per strip
+    if (sr >= 1) {
+        for (int ys = y0; ys < y1; ys += sr) {
+            const int ye = ys + sr < y1 ? ys + sr : y1, th = ye - ys + 2;
+            for (int k = threadIdx.x; k < th * tw; k += 256) {
+                const int ty = k / tw, tx = k - ty * tw;
+                const int y = ys - 1 + ty, x = x0 - 1 + tx;
+                s_t[k] = (x >= 0 && y >= 0 && x < w && y < h) ? r25[(int64_t)y * w + x] : INT64_MIN;
             }
-        const int64_t idx = (int64_t)y * w + x;
-        if (peak && (bi < 0 || v > bv || (v == bv && idx < bi))) {
-            bv = v;
-            bi = idx;
+            __syncthreads();
+            for (int k = threadIdx.x; k < (ye - ys) * cw; k += 256) {
+                const int py = k / cw, px = k - py * cw;
+                const int t = (py + 1) * tw + px + 1;
+                const int64_t v = s_t[t];
+                if (v <= thr) continue;
+                const bool peak = s_t[t - tw - 1] <= v && s_t[t - tw] <= v && s_t[t - tw + 1] <= v && s_t[t - 1] <= v &&
+                                  s_t[t + 1] <= v && s_t[t + tw - 1] <= v && s_t[t + tw] <= v && s_t[t + tw + 1] <= v;
+                if (peak) take_best(v, (int64_t)(ys + py) * w + (x0 + px), bv, bi);
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int k = threadIdx.x; k < cw * ch; k += 256) {
+            const int y = y0 + k / cw, x = x0 + k % cw;
+            const int64_t v = r25[(int64_t)y * w + x];
+            if (v <= thr) continue;
+            bool peak = true;
+            for (int j = -1; j <= 1; ++j)
+                for (int i = -1; i <= 1; ++i) {
+                    const int nx = x + i, ny = y + j;
+                    if ((i || j) && nx >= 0 && ny >= 0 && nx < w && ny < h && r25[(int64_t)ny * w + nx] > v)
+                        peak = false;
+                }
+            if (peak) take_best(v, (int64_t)y * w + x, bv, bi);
         }
     }
     s_v[threadIdx.x] = bv;
