@@ -199,14 +199,15 @@ __global__ void __launch_bounds__(256) k_zssd(const uint8_t *__restrict__ a, con
         const int dy = s / S - sr, dx = s % S - sr;
         const int qx = c.x + dx, qy = c.y + dy;
         if (qx < pr || qy < pr || qx + pr >= w || qy + pr >= h) continue;
-        int64_t sd = 0, sb = 0;
+        // 32-bit sums: at most 31^2 pixels, so sum (a - b)^2 <= 961 * 255^2 < 2^26.
+        int32_t sd = 0, sb = 0;
         for (int j = 0; j < P; ++j)
             for (int k = 0; k < P; ++k) {
-                const int64_t va = s_a[j][k], vb = s_b[dy + sr + j][dx + sr + k];
+                const int32_t va = s_a[j][k], vb = s_b[dy + sr + j][dx + sr + k];
                 sd += (va - vb) * (va - vb);
                 sb += vb;
             }
-        const int64_t cost = np * sd - (sa - sb) * (sa - sb);
+        const int64_t cost = np * (int64_t)sd - (sa - (int64_t)sb) * (sa - (int64_t)sb);
         if (bk < 0 || cost < best) {       // s increases per thread: the first shift wins ties
             best = cost;
             bk = s;
