@@ -578,11 +578,57 @@ __global__ void __launch_bounds__(256) k_export(const uint8_t *__restrict__ msg,
     out[(((int64_t)k * L + f) * d.h + y) * d.w + x] = v;
 }
 
+// Pixel-major level 0: through an LDS tile of 32 consecutive pixels of one
+// row (their slot-k rows read as contiguous runs, labels written as 128-byte
+// runs of x; rows padded by one word).  grid (ceil(w / 32), h, 4).
+template <typename S, int LP>
+__global__ void __launch_bounds__(256) k_export_pm(const uint8_t *__restrict__ msg, uint32_t msg_bytes, LevelDesc d,
+                                                  int L, float *__restrict__ out)
+{
+    __shared__ float tile[32][LP + 1];
+    const int x0 = blockIdx.x * 32, y = blockIdx.y, k = blockIdx.z;
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(msg, msg_bytes);
+    for (int e = threadIdx.x; e < 32 * LP; e += 256) {
+        const int p = e / LP, f = e - p * LP;
+        const int x = x0 + p;
+        if (x >= d.w) continue;
+        const bool ok = (k == 0) ? x > 0 : (k == 1) ? x < d.w - 1 : (k == 2) ? y > 0 : y < d.h - 1;
+        float v = 0.0f;
+        if (ok) {
+            const int64_t idx = msg_idx((x + y) & 1, k, f, y * d.wh + (x >> 1), d.blk, d.ls, d.ps);
+            v = S::ld(r, (uint32_t)(idx * S::bytes), 0);
+        }
+        tile[p][f] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 32 * L; e += 256) {
+        const int f = e / 32, p = e - f * 32;
+        const int x = x0 + p;
+        if (x < d.w) out[(((int64_t)k * L + f) * d.h + y) * d.w + x] = tile[p][f];
+    }
+}
+
 bp_status launch_export(const Plan &p, float *out, uint8_t *ws, hipStream_t s)
 {
     const Level &v = p.lv[0];
     return with_store(v.fmt, [&](auto st) {
         using S = decltype(st);
+        if (v.layout == PIXEL_MAJOR) {
+            const dim3 grid(cdiv(v.w, 32), v.h, 4);
+            const uint8_t *m = ws + v.msg_off;
+            const uint32_t mb = (uint32_t)v.msg_bytes;
+            switch (v.lp) {
+            case 16: k_export_pm<S, 16><<<grid, 256, 0, s>>>(m, mb, desc(v), p.L, out); break;
+            case 32: k_export_pm<S, 32><<<grid, 256, 0, s>>>(m, mb, desc(v), p.L, out); break;
+            case 64: k_export_pm<S, 64><<<grid, 256, 0, s>>>(m, mb, desc(v), p.L, out); break;
+            case 96: k_export_pm<S, 96><<<grid, 256, 0, s>>>(m, mb, desc(v), p.L, out); break;
+            case 128: k_export_pm<S, 128><<<grid, 256, 0, s>>>(m, mb, desc(v), p.L, out); break;
+            case 192: k_export_pm<S, 192><<<grid, 256, 0, s>>>(m, mb, desc(v), p.L, out); break;
+            case 256: k_export_pm<S, 256><<<grid, 256, 0, s>>>(m, mb, desc(v), p.L, out); break;
+            default: return BP_ERR_UNSUPPORTED;
+            }
+            return launch_status();
+        }
         k_export<S><<<dim3(cdiv(v.w, 256), v.h, 4 * p.L), 256, 0, s>>>(ws + v.msg_off, (uint32_t)v.msg_bytes, desc(v),
                                                                         p.L, out);
         return launch_status();
