@@ -173,6 +173,26 @@ __device__ __forceinline__ void bwd_step_pm(const BwdPmArgs &a, uint32_t block)
     const float lamR = lam * (float)R;
     const uint32_t base = jj * a.lp + (uint32_t)f0;
 
+    // The receiver slot's adjoint, loaded with the rows below (offset 0 and
+    // zeros for a sender without that neighbour).  The slot is not cleared:
+    // every in-grid slot of the receivers' colour is overwritten by the next
+    // reverse step's sender side before anything reads it again.
+    const bool hq = has[k];
+    uint32_t roff = 0;
+    if (hq) {
+        int nx = x, ny = y;
+        if (k == 0) nx = x - 1;
+        else if (k == 1) nx = x + 1;
+        else if (k == 2) ny = y - 1;
+        else ny = y + 1;
+        const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
+        roff = (((uint32_t)(a.colour ^ 1) * 4u + (uint32_t)(k ^ 1)) * a.blk + dj * a.lp + (uint32_t)f0) * 4u;
+    }
+    float mbv[R];
+    ld_row<StoreF32, R>(rb, roff, mbv);
+#pragma unroll
+    for (int r = 0; r < R; ++r) mbv[r] = hq ? mbv[r] : 0.0f;
+
     // h of this lane's labels, summed as in the forward kernel.
     float h[R];
     {
@@ -254,28 +274,7 @@ __device__ __forceinline__ void bwd_step_pm(const BwdPmArgs &a, uint32_t block)
     }
     const float cap = hmin + a.lt;
 
-    // Phase 1: read the receiver slot's adjoint, post (winner, mb).  The slot
-    // is not cleared: every in-grid slot of the receivers' colour is
-    // overwritten by the next reverse step's sender side before anything
-    // reads it again.
-    const bool hq = has[k];
-    uint32_t roff = 0;
-    if (hq) {
-        int nx = x, ny = y;
-        if (k == 0) nx = x - 1;
-        else if (k == 1) nx = x + 1;
-        else if (k == 2) ny = y - 1;
-        else ny = y + 1;
-        const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
-        roff = (((uint32_t)(a.colour ^ 1) * 4u + (uint32_t)(k ^ 1)) * a.blk + dj * a.lp + (uint32_t)f0) * 4u;
-    }
-    float mbv[R];
-    if (hq) {
-        ld_row<StoreF32, R>(rb, roff, mbv);
-    } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r) mbv[r] = 0.0f;
-    }
+    // Phase 1: post (winner, mb) of the receiver slot's adjoint.
     float lsum = 0.0f, tsum = 0.0f, nsum = 0.0f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
