@@ -192,6 +192,11 @@ __device__ __forceinline__ void bwd_step_pm(const BwdPmArgs &a, uint32_t block)
     ld_row<StoreF32, R>(rb, roff, mbv);
 #pragma unroll
     for (int r = 0; r < R; ++r) mbv[r] = hq ? mbv[r] : 0.0f;
+    // The cost adjoint this pixel accumulates (message-0 lanes), also early.
+    const __amdgpu_buffer_rsrc_t rg = make_rsrc(a.gcost, a.cost_bytes);
+    const uint32_t goff = ((uint32_t)a.colour * a.blk + base) * 4u;
+    float gc[R];
+    if (live && k == 0) ld_row<StoreF32, R>(rg, goff, gc);
 
     // h of this lane's labels, summed as in the forward kernel.
     float h[R];
@@ -324,10 +329,6 @@ __device__ __forceinline__ void bwd_step_pm(const BwdPmArgs &a, uint32_t block)
 #pragma unroll
     for (int r = 0; r < R; ++r) tot[r] = xor_sum<2 * SEG>(xor_sum<SEG>(hb[r]));
     if (live && k == 0) {
-        const __amdgpu_buffer_rsrc_t rg = make_rsrc(a.gcost, a.cost_bytes);
-        const uint32_t goff = ((uint32_t)a.colour * a.blk + base) * 4u;
-        float gc[R];
-        ld_row<StoreF32, R>(rg, goff, gc);
 #pragma unroll
         for (int r = 0; r < R; ++r) gc[r] += tot[r];
         st_row<StoreF32, R>(rg, goff, gc);
