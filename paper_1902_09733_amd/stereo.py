@@ -311,6 +311,8 @@ def icp(src: torch.Tensor, dst: torch.Tensor, pose: torch.Tensor, iters: int = 3
     _need_gpu(src, dst, pose)
     if src.dtype != torch.float32 or dst.dtype != torch.float32 or pose.dtype != torch.float64:
         raise ValueError("points must be float32 [N][3] and the pose float64 [12]")
+    if src.dim() != 2 or src.shape[1] != 3 or dst.dim() != 2 or dst.shape[1] != 3 or pose.numel() != 12:
+        raise ValueError("points must be float32 [N][3] and the pose float64 [12]")
     n, m = src.shape[0], dst.shape[0]
     lib = _abi.lib()
     nbytes = lib.bp_icp_workspace_size(n, m)
