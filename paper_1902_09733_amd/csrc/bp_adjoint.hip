@@ -373,6 +373,21 @@ bp_status launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
     return launch_status();
 }
 
+// Zero fill with 16-byte words (sizes are multiples of 16).
+__global__ void __launch_bounds__(256) k_zero16(uint4 *__restrict__ dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+bp_status launch_zero(void *dst, size_t bytes, hipStream_t s)
+{
+    const int64_t n = (int64_t)(bytes / 16);
+    if (n == 0) return BP_OK;
+    k_zero16<<<(unsigned)((n + 255) / 256), 256, 0, s>>>((uint4 *)dst, n);
+    return launch_status();
+}
+
 int bwd_step_blocks(const Plan &p) { return (p.lv[0].h * p.lv[0].wh + 15) / 16; }
 
 bp_status launch_bwd_readout(const Plan &p, const uint8_t *msg, float *mbar, const float *grad_soft,

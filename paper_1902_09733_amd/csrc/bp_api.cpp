@@ -768,7 +768,11 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
                 // and writes into the state buffer, no copy needed.
                 int r = t0;
                 if (!saved) {
-                    st = launch_init_messages(pl, ws, stream);
+                    // M_0 is zero; half-sweep 0 (or the reverse step at t = 0)
+                    // reads only the colour-0 half, and the out-of-grid slots of
+                    // the other half were zeroed at the start.
+                    const Level &v0 = pl.lv[0];
+                    st = launch_zero(state, (size_t)4 * v0.blk * fmt_bytes(v0.fmt), stream);
                 } else {
                     st = launch_iteration_from(pl, r, saved, params->lambda, params->tau, pl.variant, ws, stream);
                     ++r;

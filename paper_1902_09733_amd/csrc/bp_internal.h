@@ -149,6 +149,7 @@ bp_status dispatch_iter_lm(const IterArgs &a, int fmt, int G, bool ro, hipStream
 // a8: adjoint kernels (bp_adjoint.hip).  `msg` is a finest-level message
 // state (label-major float32), `mbar` its adjoint, `grad_cost` planar.
 bp_status launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+bp_status launch_zero(void *dst, size_t bytes, hipStream_t s);
 int bwd_step_blocks(const Plan &p);
 bp_status launch_bwd_readout(const Plan &p, const uint8_t *msg, float *mbar, const float *grad_soft,
                              float *grad_cost, float temperature, uint8_t *ws, hipStream_t s);
