@@ -174,8 +174,7 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
     int done = 1;
     if ((st = q.cost ? launch_split_cost(q.cost, pl, ws, s) : launch_pair_cost(*q.pair, pl, ws, s, &done)) != BP_OK)
         return st;
-    for (int l = done; l < n; ++l)
-        if ((st = launch_pyramid_level(pl, l, ws, s)) != BP_OK) return st;
+    if ((st = launch_pyramid(pl, done, ws, s)) != BP_OK) return st;
     // The finest level's last half-sweep also reads out its senders' labels.
     const bool fuse_ro = q.disparity && !q.soft_disparity && K >= 1;
     for (int l = n - 1; l >= 0; --l) {
@@ -281,8 +280,7 @@ bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans,
         if ((st = probs[i].cost ? launch_split_cost(probs[i].cost, plans[i], ws, s)
                                 : launch_pair_cost(*probs[i].pair, plans[i], ws, s, &done)) != BP_OK)
             return st;
-        for (int l = done; l < n; ++l)
-            if ((st = launch_pyramid_level(plans[i], l, ws, s)) != BP_OK) return st;
+        if ((st = launch_pyramid(plans[i], done, ws, s)) != BP_OK) return st;
     }
     // Problems grouped by lane split (classes of one launch each).
     int cls_S[32], cls_R[32], ncls = 0;

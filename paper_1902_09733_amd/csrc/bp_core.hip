@@ -203,6 +203,102 @@ bp_status launch_split_cost(const float *planar, const Plan &p, uint8_t *ws, hip
     return launch_status();
 }
 
+// Up to three pixel-major pyramid levels in one launch: the thread of label f
+// of pixel (x, y) of the last level sums its subtree level by level (the
+// children of every node added in the order of k_pyr_pm, so every stored
+// value is bit-identical to level-by-level launches) and stores every node.
+// grid (ceil(w_top * L / 256), h_top).
+struct PyrChain {
+    const float *src;
+    LevelDesc sd;
+    float *out[3];
+    LevelDesc od[3];
+};
+
+// The 4^K source values under node (x, y) of chain level K, loaded before any
+// store so that every load is in flight at once; children outside their
+// level's grid are skipped (their slots are never read).
+template <int K>
+__device__ __forceinline__ void pyr_leaves(const PyrChain &a, int x, int y, int f, float *v)
+{
+    if constexpr (K == 0) {
+        v[0] = a.src[cost_idx((x + y) & 1, f, y * a.sd.wh + (x >> 1), a.sd.blk, a.sd.ls, a.sd.ps)];
+    } else {
+        const LevelDesc &cd = K == 1 ? a.sd : a.od[K - 2];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 2; ++ii) {
+                const int fx = 2 * x + ii, fy = 2 * y + jj;
+                if (fx < cd.w && fy < cd.h) pyr_leaves<K - 1>(a, fx, fy, f, v + (2 * jj + ii) * (1 << (2 * (K - 1))));
+            }
+    }
+}
+
+// Sum of node (x, y) of chain level K from its loaded leaves, storing every
+// node of the subtree.
+template <int K>
+__device__ __forceinline__ float pyr_reduce(const PyrChain &a, int x, int y, int f, const float *v)
+{
+    if constexpr (K == 0) {
+        return v[0];
+    } else {
+        const LevelDesc &cd = K == 1 ? a.sd : a.od[K - 2];
+        float acc = 0.0f;
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 2; ++ii) {
+                const int fx = 2 * x + ii, fy = 2 * y + jj;
+                if (fx < cd.w && fy < cd.h) acc += pyr_reduce<K - 1>(a, fx, fy, f, v + (2 * jj + ii) * (1 << (2 * (K - 1))));
+            }
+        const LevelDesc &d = a.od[K - 1];
+        a.out[K - 1][cost_idx((x + y) & 1, f, y * d.wh + (x >> 1), d.blk, d.ls, d.ps)] = acc;
+        return acc;
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_pyr_pm_chain(const PyrChain a, int L)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (i >= a.od[D - 1].w * L) return;
+    const int x = i / L, f = i - x * L;
+    float v[1 << (2 * D)];
+    pyr_leaves<D>(a, x, y, f, v);
+    pyr_reduce<D>(a, x, y, f, v);
+}
+
+bp_status launch_pyramid(const Plan &p, int first, uint8_t *ws, hipStream_t s)
+{
+    for (int l = first; l < p.levels;) {
+        int D = 0;
+        while (D < 3 && l + D < p.levels && p.lv[l + D].layout == PIXEL_MAJOR && p.lv[l - 1].layout == PIXEL_MAJOR) ++D;
+        if (D < 2) {
+            const bp_status st = launch_pyramid_level(p, l, ws, s);
+            if (st != BP_OK) return st;
+            ++l;
+            continue;
+        }
+        PyrChain a;
+        a.src = (const float *)(ws + p.lv[l - 1].cost_off);
+        a.sd = desc(p.lv[l - 1]);
+        for (int k = 0; k < 3; ++k) {
+            const Level &v = p.lv[k < D ? l + k : l];
+            a.out[k] = (float *)(ws + v.cost_off);
+            a.od[k] = desc(v);
+        }
+        const Level &top = p.lv[l + D - 1];
+        const dim3 grid(cdiv((int64_t)top.w * p.L, 256), top.h);
+        if (D == 3) k_pyr_pm_chain<3><<<grid, 256, 0, s>>>(a, p.L);
+        else k_pyr_pm_chain<2><<<grid, 256, 0, s>>>(a, p.L);
+        const bp_status st = launch_status();
+        if (st != BP_OK) return st;
+        l += D;
+    }
+    return BP_OK;
+}
+
 bp_status launch_pyramid_level(const Plan &p, int l, uint8_t *ws, hipStream_t s)
 {
     const Level &f = p.lv[l - 1], &c = p.lv[l];

@@ -84,6 +84,9 @@ bp_status launch_split_cost(const float *planar, const Plan &p, uint8_t *ws, hip
 // too when both levels are pixel-major (*levels_done = 2, else 1).
 bp_status launch_pair_cost(const bp_pair &pr, const Plan &p, uint8_t *ws, hipStream_t s, int *levels_done);
 bp_status launch_pyramid_level(const Plan &p, int l, uint8_t *ws, hipStream_t s);
+// Levels first .. levels - 1 of the pyramid (up to three pixel-major levels
+// per launch).
+bp_status launch_pyramid(const Plan &p, int first, uint8_t *ws, hipStream_t s);
 
 // a4: zero every level's out-of-grid slots and the coarsest level's
 // messages; explicit parent copy.
