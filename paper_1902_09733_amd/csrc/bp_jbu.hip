@@ -2,17 +2,22 @@
 // optional fused triangulation of every output pixel (Eq. 3).
 //
 // A 256-thread block owns 16 x 16 full-resolution pixels.  The low-resolution
-// taps every pixel of the block can reach (disparity and the guide sample
-// I_q at scale*q + scale/2, packed RGB, with |I_q|^2) are staged once in LDS.
-// The weight of a tap is one exp2 of a sum of exponents: the spatial part is
-// separable and depends only on the pixel's sub-pixel phase, so it is a
-// per-thread table of 2R+1 values per axis; the range part is |I_p - I_q|^2
-// scaled by log2(e) / (2 sigma_r^2), with the squared distance formed exactly
-// in integers as |I_p|^2 + |I_q|^2 - 2 I_p.I_q (one 4 x u8 dot product per
-// tap).  Weights are evaluated relative to the smallest exponent of the window
-// (a common factor that cancels in K_p), so no pixel can lose all its weights
-// to underflow.  ALU/transcendental bound: about (2R+1)^2 exp2 and a dozen
-// other vector operations per output pixel and tap.
+// taps every pixel of the block can reach are staged once in LDS, one 16-byte
+// record each: the guide sample I_q at scale*q + scale/2 as FP16 channel pairs
+// (exact for 8-bit values), -|I_q|^2 and the tap's disparity as floats.  The
+// weight of a tap is exp2 of a non-positive exponent, spatial + range: the
+// spatial part is separable and depends only on the pixel's sub-pixel phase,
+// so the x part is a per-thread table of 2R+1 values and the y part a factor
+// applied once per window row to that row's sums; the range part is
+// -|I_p - I_q|^2 scaled by log2(e) / (2 sigma_r^2).  The squared distance is
+// formed exactly by FP16 dot products accumulating in FP32 (every term is an
+// integer below 2^24): 2 I_p.I_q - |I_q|^2 - 256 floor(|I_p|^2 / 256), the
+// remaining low byte of |I_p|^2 entering through the x table.  Weights are
+// taken relative to exponent 0; a pixel whose weights sum below 2^-60 (a guide
+// colour far from every tap in its window) is evaluated again relative to its
+// largest exponent, so no pixel loses its weights to underflow.
+// ALU/transcendental bound: per output pixel and tap one or two dot products,
+// one exp2 and three other vector operations.
 #include <hip/hip_runtime.h>
 
 #include "bp_internal.h"
@@ -38,15 +43,25 @@ struct PointArgs {
     float baseline, f_du, dv_du, u0, v0;
 };
 
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t h2_bits(float a, float b)
+{
+    const h2_t v = {(_Float16)a, (_Float16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ h2_t bits_h2(uint32_t u) { return __builtin_bit_cast(h2_t, u); }
+
 template <int R, int C, bool PTS>
 __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, int wl, int hl,
                                             const uint8_t *__restrict__ guide, int wh, int hh, int64_t stride,
                                             int s, float ksp, float krg, float *__restrict__ out, PointArgs pa)
 {
-    __shared__ float t_d[kMaxTap * kMaxTap];
-    // Per tap: packed guide colour and |I_q|^2 (+inf outside the grid, which
-    // gives the tap zero weight).
-    __shared__ uint2 t_g[kMaxTap * kMaxTap];
+    // Per tap: FP16 (I_R, I_G), (I_B, 256) (grey: (I, 256), unused),
+    // -|I_q|^2 and the disparity.  Outside the grid -|I_q|^2 is -inf, which
+    // gives the tap zero weight.
+    __shared__ uint4 t_q[kMaxTap * kMaxTap];
     constexpr int NT = 2 * R + 1;
     const int bx0 = blockIdx.x * kTile, by0 = blockIdx.y * kTile;
     const int qx0 = bx0 / s - R, qy0 = by0 / s - R;
@@ -55,64 +70,108 @@ __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, i
     for (int i = threadIdx.x; i < tw * th; i += 256) {
         const int ty = i / tw, tx = i - ty * tw;
         const int qx = qx0 + tx, qy = qy0 + ty;
-        float d = 0.0f;
-        uint32_t g = 0u;
-        float n = __builtin_huge_valf();
+        uint4 r = make_uint4(0u, 0u, __float_as_uint(-__builtin_huge_valf()), 0u);
         if (qx >= 0 && qx < wl && qy >= 0 && qy < hl) {
-            d = (float)disp[(int64_t)qy * wl + qx];
-            g = guide_px<C>(guide, stride, s * qx + s / 2, s * qy + s / 2);
-            n = (float)__builtin_amdgcn_udot4(g, g, 0u, false);
+            const uint32_t g = guide_px<C>(guide, stride, s * qx + s / 2, s * qy + s / 2);
+            const int n = (int)__builtin_amdgcn_udot4(g, g, 0u, false);
+            if constexpr (C == 3) {
+                r.x = h2_bits((float)(g & 255u), (float)((g >> 8) & 255u));
+                r.y = h2_bits((float)(g >> 16), 256.0f);
+            } else {
+                r.x = h2_bits((float)g, 256.0f);
+            }
+            r.z = __float_as_uint(-(float)n);
+            r.w = __float_as_uint((float)disp[(int64_t)qy * wl + qx]);
         }
-        t_d[ty * kMaxTap + tx] = d;
-        t_g[ty * kMaxTap + tx] = make_uint2(g, __float_as_uint(n));
+        t_q[ty * kMaxTap + tx] = r;
     }
     __syncthreads();
     const int px = bx0 + (int)(threadIdx.x % kTile), py = by0 + (int)(threadIdx.x / kTile);
     if (px >= wh || py >= hh) return;
     const uint32_t ip = guide_px<C>(guide, stride, px, py);
     const int np = (int)__builtin_amdgcn_udot4(ip, ip, 0u, false);
+    // Pixel side of the dot products: 2 I_p (exact in FP16 up to 510) and
+    // -floor(|I_p|^2 / 256) (at most 762) against the tap's 256.
+    h2_t pa2, pb2;
+    if constexpr (C == 3) {
+        pa2 = bits_h2(h2_bits(2.0f * (float)(ip & 255u), 2.0f * (float)((ip >> 8) & 255u)));
+        pb2 = bits_h2(h2_bits(2.0f * (float)(ip >> 16), -(float)(np >> 8)));
+    } else {
+        pa2 = bits_h2(h2_bits(2.0f * (float)ip, -(float)(np >> 8)));
+        pb2 = pa2;
+    }
+    const float np_lo = krg * (float)(np & 255);
     const int cx = px / s, cy = py / s;
     const int ox = cx - R - qx0, oy = cy - R - qy0;   // tile coordinates of the window corner
     // Separable spatial exponents: s * (p_lo - q) = phase + 0.5 - s/2 - s*dq.
-    float ex[NT], ey[NT];
+    const float fx = (float)(px - s * cx) + 0.5f - 0.5f * (float)s;
+    const float fy = (float)(py - s * cy) + 0.5f - 0.5f * (float)s;
+    // Range part of a tap's exponent before scaling, from its record:
+    // 2 I_p.I_q - |I_q|^2 - 256 floor(|I_p|^2 / 256), an exact integer (-inf
+    // outside the grid).
+    auto range = [&](const uint4 &q) {
+        float r = __builtin_amdgcn_fdot2(pa2, bits_h2(q.x), __uint_as_float(q.z), false);
+        if constexpr (C == 3) r = __builtin_amdgcn_fdot2(pb2, bits_h2(q.y), r, false);
+        return r;
+    };
+    // x term of the exponent: spatial x exponent less krg * the low byte of |I_p|^2.
+    float ex[NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
-        const float tx = (float)(px - s * cx) + 0.5f - 0.5f * (float)s - (float)(s * (i - R));
-        const float ty = (float)(py - s * cy) + 0.5f - 0.5f * (float)s - (float)(s * (i - R));
-        ex[i] = tx * tx * ksp;
-        ey[i] = ty * ty * ksp;
+        const float tx = fx - (float)(s * (i - R));
+        ex[i] = -(tx * tx * ksp) - np_lo;
     }
-    constexpr bool KEEP = NT * NT <= 81;
-    float e[KEEP ? NT * NT : 1];
-    // Exponent of tap (dx, dy); |I_p - I_q|^2 = (|I_p|^2 - 2 I_p.I_q) + |I_q|^2
-    // is an integer below 2^24, so every step is exact.
-    auto expo = [&](int dx, int dy) {
-        const uint2 g = t_g[(oy + dy) * kMaxTap + ox + dx];
-        const int dot = (int)__builtin_amdgcn_udot4(ip, g.x, 0u, false);
-        const float r2 = (float)(np - 2 * dot) + __uint_as_float(g.y);
-        return fmaf(r2, krg, ex[dx] + ey[dy]);
-    };
-    float emin = __builtin_huge_valf();
-#pragma unroll
-    for (int dy = 0; dy < NT; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < NT; ++dx) {
-            const float v = expo(dx, dy);
-            if constexpr (KEEP) e[dy * NT + dx] = v;
-            emin = fminf(emin, v);
-        }
     float num = 0.0f, den = 0.0f;
 #pragma unroll
-    for (int dy = 0; dy < NT; ++dy)
+    for (int dy = 0; dy < NT; ++dy) {
+        const float ty = fy - (float)(s * (dy - R));
+        const float wy = __builtin_amdgcn_exp2f(-(ty * ty * ksp));
+        float rn = 0.0f, rd = 0.0f;
 #pragma unroll
         for (int dx = 0; dx < NT; ++dx) {
-            float v;
-            if constexpr (KEEP) v = e[dy * NT + dx];
-            else v = expo(dx, dy);
-            const float w = __builtin_amdgcn_exp2f(emin - v);
-            num = fmaf(w, t_d[(oy + dy) * kMaxTap + ox + dx], num);
-            den += w;
+            const uint4 q = t_q[(oy + dy) * kMaxTap + ox + dx];
+            const float w = __builtin_amdgcn_exp2f(fmaf(range(q), krg, ex[dx]));
+            rn = fmaf(w, __uint_as_float(q.w), rn);
+            rd += w;
         }
+        num = fmaf(wy, rn, num);
+        den = fmaf(wy, rd, den);
+    }
+    if (!(den >= 0x1p-60f)) {
+        // Every weight is tiny: the same sums relative to the tap of largest
+        // exponent (finite, since the pixel's own cell is in the grid), with
+        // the range difference to it taken exactly before scaling so that
+        // exponents far below zero keep their precision.
+        float emax = -__builtin_huge_valf(), rm = 0.0f, sm = 0.0f;
+#pragma unroll 1
+        for (int dy = 0; dy < NT; ++dy) {
+            const float ty = fy - (float)(s * (dy - R)), sy = -(ty * ty * ksp);
+#pragma unroll 1
+            for (int dx = 0; dx < NT; ++dx) {
+                const float tx = fx - (float)(s * (dx - R)), sp = sy - tx * tx * ksp;
+                const float r = range(t_q[(oy + dy) * kMaxTap + ox + dx]), e = fmaf(r, krg, sp);
+                if (e > emax) {
+                    emax = e;
+                    rm = r;
+                    sm = sp;
+                }
+            }
+        }
+        num = 0.0f;
+        den = 0.0f;
+#pragma unroll 1
+        for (int dy = 0; dy < NT; ++dy) {
+            const float ty = fy - (float)(s * (dy - R)), sy = -(ty * ty * ksp);
+#pragma unroll 1
+            for (int dx = 0; dx < NT; ++dx) {
+                const float tx = fx - (float)(s * (dx - R)), sp = sy - tx * tx * ksp;
+                const uint4 q = t_q[(oy + dy) * kMaxTap + ox + dx];
+                const float w = __builtin_amdgcn_exp2f(fmaf(range(q) - rm, krg, sp - sm));
+                num = fmaf(w, __uint_as_float(q.w), num);
+                den += w;
+            }
+        }
+    }
     const float dp = num / den;
     if (out) out[(int64_t)py * wh + px] = dp;
     if constexpr (PTS) {

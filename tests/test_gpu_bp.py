@@ -228,6 +228,27 @@ def test_upsample_parity(dev, s, R, ch):
     assert err <= 2e-3, err
 
 
+@pytest.mark.parametrize("s,R,ch,sigma_r", [(4, 4, 3, 12.0), (3, 2, 1, 12.0), (2, 3, 3, 1.0)])
+def test_upsample_far_colours(dev, s, R, ch, sigma_r):
+    """Pixels whose guide colour is far from every tap in their window: every
+    weight underflows relative to exponent 0 and the kernel re-evaluates them
+    relative to their largest exponent; the sample pixels themselves take the
+    ordinary path in the same launch."""
+    bp = bp_mod()
+    wl, hl = 29, 19
+    rng = np.random.default_rng(100 + s * 10 + R)
+    disp = rng.integers(0, 64, size=(hl, wl)).astype(np.int32)
+    shape = (hl * s, wl * s) + ((3,) if ch == 3 else ())
+    guide = rng.integers(200, 256, size=shape, dtype=np.uint8)
+    guide[s // 2::s, s // 2::s] = rng.integers(0, 8, size=guide[s // 2::s, s // 2::s].shape, dtype=np.uint8)
+    g = bp.upsample(torch.from_numpy(disp).to(dev), torch.from_numpy(guide).to(dev), 8.0, sigma_r, R)
+    o = oracle.upsample(disp, guide, 8.0, sigma_r, R)
+    gn = g.cpu().numpy().astype(np.float64)
+    assert np.isfinite(gn).all()
+    err = np.abs(gn - o).max()
+    assert err <= 2e-3, err
+
+
 # ---------------------------------------------------------------- full-size pair, bench configuration
 
 @pytest.fixture(scope="module")
