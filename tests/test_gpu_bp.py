@@ -215,7 +215,7 @@ def test_16bit_messages_real(dev, fmt, mode):
 
 # ---------------------------------------------------------------- a7
 
-@pytest.mark.parametrize("s,R,ch", [(4, 4, 3), (2, 3, 1), (1, 2, 3), (3, 5, 3)])
+@pytest.mark.parametrize("s,R,ch", [(4, 4, 3), (2, 3, 1), (1, 2, 3), (3, 5, 3), (5, 8, 3), (17, 1, 3), (20, 0, 1)])
 def test_upsample_parity(dev, s, R, ch):
     bp = bp_mod()
     wl, hl = 37, 23
