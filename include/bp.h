@@ -321,7 +321,8 @@ bp_status bp_run_profiled(const bp_problem *probs, int32_t count, const bp_param
  * ceil(2 sigma_s / scale).  Output float32 [h_hi][w_hi] in low-resolution
  * label units (multiply by scale for full-resolution disparity).
  * Errors: BP_ERR_INVALID_ARGUMENT for NULL pointers, non-integer or unequal
- * scales, channels not 1/3, sigmas <= 0; BP_ERR_UNSUPPORTED for radius_lo > 8.
+ * scales, channels not 1/3, sigmas <= 0; BP_ERR_UNSUPPORTED for radius_lo > 8
+ * or w_hi / h_hi of 2^20 or more.
  */
 bp_status bp_upsample(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo, const uint8_t *guide_hi,
                       int32_t w_hi, int32_t h_hi, int32_t channels, int64_t guide_row_stride,

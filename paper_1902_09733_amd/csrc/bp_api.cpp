@@ -586,7 +586,7 @@ static bp_status upsample_args(const int32_t *disp_lo, int32_t w_lo, int32_t h_l
         return BP_ERR_INVALID_ARGUMENT;
     const int s = w_hi / w_lo;
     *R = radius_lo < 0 ? (int)std::ceil(2.0 * sigma_s / s) : radius_lo;
-    if (*R > 8) return BP_ERR_UNSUPPORTED;
+    if (*R > 8 || w_hi >= (1 << 20) || h_hi >= (1 << 20)) return BP_ERR_UNSUPPORTED;
     return BP_OK;
 }
 

@@ -53,22 +53,32 @@ __device__ __forceinline__ uint32_t h2_bits(float a, float b)
 
 __device__ __forceinline__ h2_t bits_h2(uint32_t u) { return __builtin_bit_cast(h2_t, u); }
 
+// floor(a / b) for 0 <= a < 2^20 and b >= 1 from a reciprocal rb of b within
+// one ulp: (a + 0.5) / b lies at least 0.5 / b, four ulps of the quotient,
+// from an integer, beyond the error of the product.
+__device__ __forceinline__ int div_small(int a, float rb) { return (int)(((float)a + 0.5f) * rb); }
+
 template <int R, int C, bool PTS>
 __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, int wl, int hl,
                                             const uint8_t *__restrict__ guide, int wh, int hh, int64_t stride,
-                                            int s, float ksp, float krg, float *__restrict__ out, PointArgs pa)
+                                            int s, float rs, float ksp, float krg, float *__restrict__ out,
+                                            PointArgs pa)
 {
     // Per tap: FP16 (I_R, I_G), (I_B, 256) (grey: (I, 256), unused),
     // -|I_q|^2 and the disparity.  Outside the grid -|I_q|^2 is -inf, which
     // gives the tap zero weight.
     __shared__ uint4 t_q[kMaxTap * kMaxTap];
     constexpr int NT = 2 * R + 1;
+    // Separable spatial terms of the block's 16 columns and 16 rows, per
+    // window column / row: the x exponent, and exp2 of the y exponent.
+    __shared__ float t_sx[kTile * NT], t_wy[kTile * NT];
     const int bx0 = blockIdx.x * kTile, by0 = blockIdx.y * kTile;
     const int qx0 = bx0 / s - R, qy0 = by0 / s - R;
     const int tw = (bx0 + kTile - 1) / s - bx0 / s + 1 + 2 * R;
     const int th = (by0 + kTile - 1) / s - by0 / s + 1 + 2 * R;
+    const float rtw = __builtin_amdgcn_rcpf((float)tw);
     for (int i = threadIdx.x; i < tw * th; i += 256) {
-        const int ty = i / tw, tx = i - ty * tw;
+        const int ty = div_small(i, rtw), tx = i - ty * tw;
         const int qx = qx0 + tx, qy = qy0 + ty;
         uint4 r = make_uint4(0u, 0u, __float_as_uint(-__builtin_huge_valf()), 0u);
         if (qx >= 0 && qx < wl && qy >= 0 && qy < hl) {
@@ -85,8 +95,18 @@ __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, i
         }
         t_q[ty * kMaxTap + tx] = r;
     }
+    // s * (p_lo - q) = phase + 0.5 - s/2 - s*dq for window offset dq = i - R.
+    for (int i = threadIdx.x; i < 2 * kTile * NT; i += 256) {
+        const int y = i >= kTile * NT, e = i - y * (kTile * NT), c = e / NT, k = e - c * NT;
+        const int p = (y ? by0 : bx0) + c;
+        const float t = (float)(p - s * div_small(p, rs)) + 0.5f - 0.5f * (float)s - (float)(s * (k - R));
+        const float v = -(t * t * ksp);
+        if (y) t_wy[e] = __builtin_amdgcn_exp2f(v);
+        else t_sx[e] = v;
+    }
     __syncthreads();
-    const int px = bx0 + (int)(threadIdx.x % kTile), py = by0 + (int)(threadIdx.x / kTile);
+    const int col = (int)(threadIdx.x % kTile), rowi = (int)(threadIdx.x / kTile);
+    const int px = bx0 + col, py = by0 + rowi;
     if (px >= wh || py >= hh) return;
     const uint32_t ip = guide_px<C>(guide, stride, px, py);
     const int np = (int)__builtin_amdgcn_udot4(ip, ip, 0u, false);
@@ -101,7 +121,7 @@ __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, i
         pb2 = pa2;
     }
     const float np_lo = krg * (float)(np & 255);
-    const int cx = px / s, cy = py / s;
+    const int cx = div_small(px, rs), cy = div_small(py, rs);
     const int ox = cx - R - qx0, oy = cy - R - qy0;   // tile coordinates of the window corner
     // Separable spatial exponents: s * (p_lo - q) = phase + 0.5 - s/2 - s*dq.
     const float fx = (float)(px - s * cx) + 0.5f - 0.5f * (float)s;
@@ -117,15 +137,11 @@ __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, i
     // x term of the exponent: spatial x exponent less krg * the low byte of |I_p|^2.
     float ex[NT];
 #pragma unroll
-    for (int i = 0; i < NT; ++i) {
-        const float tx = fx - (float)(s * (i - R));
-        ex[i] = -(tx * tx * ksp) - np_lo;
-    }
+    for (int i = 0; i < NT; ++i) ex[i] = t_sx[col * NT + i] - np_lo;
     float num = 0.0f, den = 0.0f;
 #pragma unroll
     for (int dy = 0; dy < NT; ++dy) {
-        const float ty = fy - (float)(s * (dy - R));
-        const float wy = __builtin_amdgcn_exp2f(-(ty * ty * ksp));
+        const float wy = t_wy[rowi * NT + dy];
         float rn = 0.0f, rd = 0.0f;
 #pragma unroll
         for (int dx = 0; dx < NT; ++dx) {
@@ -172,7 +188,8 @@ __global__ void __launch_bounds__(256) k_jbu(const int32_t *__restrict__ disp, i
             }
         }
     }
-    const float dp = num / den;
+    // den >= 2^-60 here (>= 1 after the second pass): a normal number.
+    const float dp = num * __builtin_amdgcn_rcpf(den);
     if (out) out[(int64_t)py * wh + px] = dp;
     if constexpr (PTS) {
         const float d = (float)s * dp;
@@ -198,6 +215,7 @@ bp_status launch_upsample(const int32_t *disp_lo, int wl, int hl, const uint8_t 
     const float log2e = 1.4426950408889634f;
     const float ksp = log2e / (2.0f * sigma_s * sigma_s);
     const float krg = log2e / (2.0f * sigma_r * sigma_r);
+    const float rs = 1.0f / (float)s;
     PointArgs pa{xyz, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     if (cam) {
         pa.baseline = cam->baseline;
@@ -211,11 +229,11 @@ bp_status launch_upsample(const int32_t *disp_lo, int wl, int hl, const uint8_t 
 #define BP_JBU_CASE(RV)                                                                                       \
     case RV:                                                                                                  \
         if (ch == 1) {                                                                                        \
-            if (pts) k_jbu<RV, 1, true><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, ksp, krg, out, pa); \
-            else k_jbu<RV, 1, false><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, ksp, krg, out, pa);    \
+            if (pts) k_jbu<RV, 1, true><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, rs, ksp, krg, out, pa); \
+            else k_jbu<RV, 1, false><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, rs, ksp, krg, out, pa);    \
         } else {                                                                                              \
-            if (pts) k_jbu<RV, 3, true><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, ksp, krg, out, pa); \
-            else k_jbu<RV, 3, false><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, ksp, krg, out, pa);    \
+            if (pts) k_jbu<RV, 3, true><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, rs, ksp, krg, out, pa); \
+            else k_jbu<RV, 3, false><<<grid, 256, 0, st>>>(disp_lo, wl, hl, guide, wh, hh, stride, s, rs, ksp, krg, out, pa);    \
         }                                                                                                     \
         break;
     switch (radius) {

@@ -132,6 +132,8 @@ def test_upsample_rejects(lib):
     assert f(v, 4, 4, v, 16, 16, 3, 48, 0.0, 12.0, -1, v, None) == _abi.BP_ERR_INVALID_ARGUMENT  # sigma_s
     assert f(v, 4, 4, v, 16, 16, 3, 48, 8.0, 12.0, 9, v, None) == _abi.BP_ERR_UNSUPPORTED
     assert f(v, 4, 4, v, 16, 16, 3, 47, 8.0, 12.0, -1, v, None) == _abi.BP_ERR_INVALID_ARGUMENT  # stride
+    big = 1 << 20
+    assert f(v, big // 4, 4, v, big, 16, 1, big, 8.0, 12.0, -1, v, None) == _abi.BP_ERR_UNSUPPORTED  # width
 
 
 def test_variant_counts(lib):
