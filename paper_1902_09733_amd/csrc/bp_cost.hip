@@ -129,10 +129,13 @@ bp_status launch_downsample(const uint8_t *in, int w, int h, int ch, int64_t str
 // selected by a 0/1 byte mask and summed with one 4 x u8 dot product.  Byte b
 // of a pixel block's row has channel b % C; the mask pattern repeats every C
 // words.  Same rounding as pixel_ds.
-template <int C>
+template <int C, int S>
 __device__ __forceinline__ uint32_t pixel_ds_words(const uint8_t *__restrict__ img, int64_t stride, int x, int y,
-                                                   int s)
+                                                   int s_rt)
 {
+    // S > 0: the scale fixed at compile time (the row chunk's words then load
+    // as one vector); S = 0: s_rt.
+    const int s = S > 0 ? S : s_rt;
     const int nw = s * C / 4;
     uint32_t acc[C];
 #pragma unroll
@@ -163,17 +166,19 @@ __device__ __forceinline__ uint32_t pixel_ds_words(const uint8_t *__restrict__ i
 }
 
 // Both images of the pair, downsampled and packed: out[z][y][x], z = 0 left.
-template <int C, bool WORDS>
+// grid (ceil(wo / 256), min(ho, 65535), 2); rows beyond gridDim.y loop.
+template <int C, bool WORDS, int S>
 __global__ void __launch_bounds__(256) k_pack_pair(const uint8_t *__restrict__ left, const uint8_t *__restrict__ right,
                                                   int64_t stride, int s, int wo, int ho, uint32_t *__restrict__ out)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t n = (int64_t)wo * ho;
-    if (i >= n) return;
-    const int x = (int)(i % wo), y = (int)(i / wo);
-    const uint8_t *img = blockIdx.y ? right : left;
-    if constexpr (WORDS) out[blockIdx.y * n + i] = pixel_ds_words<C>(img, stride, x, y, s);
-    else out[blockIdx.y * n + i] = pixel_ds<C>(img, stride, x, y, s);
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= wo) return;
+    const uint8_t *img = blockIdx.z ? right : left;
+    uint32_t *o = out + (int64_t)blockIdx.z * wo * ho;
+    for (int y = blockIdx.y; y < ho; y += gridDim.y) {
+        if constexpr (WORDS) o[(int64_t)y * wo + x] = pixel_ds_words<C, S>(img, stride, x, y, s);
+        else o[(int64_t)y * wo + x] = pixel_ds<C>(img, stride, x, y, s);
+    }
 }
 
 // One block owns row y, pixels [x0, x0 + xb) (x0 even): the packed left
@@ -308,19 +313,22 @@ bp_status launch_pair_cost(const bp_pair &pr, const Plan &p, uint8_t *ws, hipStr
     const Level &v = p.lv[0];
     const int w = v.w, h = v.h, L = p.L;
     uint32_t *packed = (uint32_t *)(ws + p.pair_off);
-    const unsigned g1 = (unsigned)(((int64_t)w * h + 255) / 256);
+    const dim3 g1((unsigned)((w + 255) / 256), (unsigned)(h < 65535 ? h : 65535), 2);
     // Word loads when every pixel block's row chunk is word-aligned.
     const bool words = pr.downsample % 4 == 0 && pr.row_stride_bytes % 4 == 0 && ((uintptr_t)pr.left % 4) == 0 &&
                        ((uintptr_t)pr.right % 4) == 0;
-#define BP_PACK(CV, WV) \
-    k_pack_pair<CV, WV><<<dim3(g1, 2), 256, 0, st>>>(pr.left, pr.right, pr.row_stride_bytes, pr.downsample, w, h, packed)
+#define BP_PACK_S(CV, WV, SV) \
+    k_pack_pair<CV, WV, SV><<<g1, 256, 0, st>>>(pr.left, pr.right, pr.row_stride_bytes, pr.downsample, w, h, packed)
+#define BP_PACK(CV, WV) BP_PACK_S(CV, WV, 0)
     if (pr.channels == 1) {
         if (words) BP_PACK(1, true);
         else BP_PACK(1, false);
     } else {
-        if (words) BP_PACK(3, true);
+        if (words && pr.downsample == 4) BP_PACK_S(3, true, 4);
+        else if (words) BP_PACK(3, true);
         else BP_PACK(3, false);
     }
+#undef BP_PACK_S
 #undef BP_PACK
     int lp2 = 1;
     while (lp2 < L) lp2 <<= 1;
