@@ -344,7 +344,16 @@ __global__ void __launch_bounds__(256) k_init_msgs(InitArgs a)
     const int per = 2 * d.h + 2 * d.w;
     if (i >= (int64_t)per * a.L) return;
     const int ii = (int)i;
-    const int f = ii / per, e = ii - f * per;
+    // Consecutive threads take consecutive labels where a pixel's labels are
+    // contiguous (pixel-major), else consecutive border pixels.
+    int f, e;
+    if (d.ls == 1) {
+        e = ii / a.L;
+        f = ii - e * a.L;
+    } else {
+        f = ii / per;
+        e = ii - f * per;
+    }
     int x, y, k;
     if (e < d.h) { x = 0; y = e; k = 0; }
     else if (e < 2 * d.h) { x = d.w - 1; y = e - d.h; k = 1; }
