@@ -169,8 +169,9 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
 {
     bp_status st;
     const int n = pl.levels, K = p.iters_per_level;
-    // Out-of-grid slots of every level and the coarsest level's messages start at zero.
-    if ((st = launch_init_messages(pl, ws, s)) != BP_OK) return st;
+    // Out-of-grid slots of every level and the coarsest level's messages start
+    // at zero (on the pair route, inside the pair packing's launch).
+    if (q.cost && (st = launch_init_messages(pl, ws, s)) != BP_OK) return st;
     int done = 1;
     if ((st = q.cost ? launch_split_cost(q.cost, pl, ws, s) : launch_pair_cost(*q.pair, pl, ws, s, &done)) != BP_OK)
         return st;
@@ -275,7 +276,7 @@ bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans,
     bp_status st;
     const int n = p.levels, K = p.iters_per_level;
     for (int i = 0; i < count; ++i) {
-        if ((st = launch_init_messages(plans[i], ws, s)) != BP_OK) return st;
+        if (probs[i].cost && (st = launch_init_messages(plans[i], ws, s)) != BP_OK) return st;
         int done = 1;
         if ((st = probs[i].cost ? launch_split_cost(probs[i].cost, plans[i], ws, s)
                                 : launch_pair_cost(*probs[i].pair, plans[i], ws, s, &done)) != BP_OK)

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bp_internal.h"
+#include "bp_levels.h"
 
 namespace bpk {
 
@@ -166,18 +167,39 @@ __device__ __forceinline__ uint32_t pixel_ds_words(const uint8_t *__restrict__ i
 }
 
 // Both images of the pair, downsampled and packed: out[z][y][x], z = 0 left.
-// grid (ceil(wo / 256), min(ho, 65535), 2); rows beyond gridDim.y loop.
+// Block (bx, by, z) of a (ceil(wo / 256), gy, 2) block grid packs pixels
+// [256 bx, 256 bx + 256) of rows by, by + gy, ...
 template <int C, bool WORDS, int S>
-__global__ void __launch_bounds__(256) k_pack_pair(const uint8_t *__restrict__ left, const uint8_t *__restrict__ right,
-                                                  int64_t stride, int s, int wo, int ho, uint32_t *__restrict__ out)
+__device__ __forceinline__ void pack_block(const uint8_t *__restrict__ left, const uint8_t *__restrict__ right,
+                                           int64_t stride, int s, int wo, int ho, uint32_t *__restrict__ out, int bx,
+                                           int by, int z, int gy)
 {
-    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int x = bx * 256 + threadIdx.x;
     if (x >= wo) return;
-    const uint8_t *img = blockIdx.z ? right : left;
-    uint32_t *o = out + (int64_t)blockIdx.z * wo * ho;
-    for (int y = blockIdx.y; y < ho; y += gridDim.y) {
+    const uint8_t *img = z ? right : left;
+    uint32_t *o = out + (int64_t)z * wo * ho;
+    for (int y = by; y < ho; y += gy) {
         if constexpr (WORDS) o[(int64_t)y * wo + x] = pixel_ds_words<C, S>(img, stride, x, y, s);
         else o[(int64_t)y * wo + x] = pixel_ds<C>(img, stride, x, y, s);
+    }
+}
+
+// The packing followed, in the same launch, by the message initialisation
+// (the two touch disjoint memory): a flat grid whose first gx * gy * 2 blocks
+// are the packing's (gx, gy, 2) grid and whose next ix * (levels + 1) blocks
+// are the initialisation's (ix, levels + 1) grid.
+template <int C, bool WORDS, int S>
+__global__ void __launch_bounds__(256) k_pack_pair(const uint8_t *__restrict__ left, const uint8_t *__restrict__ right,
+                                                  int64_t stride, int s, int wo, int ho, uint32_t *__restrict__ out,
+                                                  int gx, int gy, const InitArgs ia, int ix)
+{
+    const int b = blockIdx.x, np = gx * gy * 2;
+    if (b < np) {
+        const int z = b / (gx * gy), r = b - z * (gx * gy), by = r / gx;
+        pack_block<C, WORDS, S>(left, right, stride, s, wo, ho, out, r - by * gx, by, z, gy);
+    } else {
+        const int l = (b - np) / ix;
+        init_msgs_block(ia, b - np - l * ix, l);
     }
 }
 
@@ -310,15 +332,20 @@ __global__ void __launch_bounds__(256) k_cost_level01(const uint32_t *__restrict
 
 bp_status launch_pair_cost(const bp_pair &pr, const Plan &p, uint8_t *ws, hipStream_t st, int *levels_done)
 {
+    // The message initialisation runs in the packing's launch.
     const Level &v = p.lv[0];
     const int w = v.w, h = v.h, L = p.L;
     uint32_t *packed = (uint32_t *)(ws + p.pair_off);
-    const dim3 g1((unsigned)((w + 255) / 256), (unsigned)(h < 65535 ? h : 65535), 2);
+    const int gx = (w + 255) / 256, gy = h < 4096 ? h : 4096;
+    unsigned ix;
+    const InitArgs ia = init_args(p, ws, &ix);
+    const unsigned g1 = (unsigned)(gx * gy * 2) + ix * (unsigned)(p.levels + 1);
     // Word loads when every pixel block's row chunk is word-aligned.
     const bool words = pr.downsample % 4 == 0 && pr.row_stride_bytes % 4 == 0 && ((uintptr_t)pr.left % 4) == 0 &&
                        ((uintptr_t)pr.right % 4) == 0;
 #define BP_PACK_S(CV, WV, SV) \
-    k_pack_pair<CV, WV, SV><<<g1, 256, 0, st>>>(pr.left, pr.right, pr.row_stride_bytes, pr.downsample, w, h, packed)
+    k_pack_pair<CV, WV, SV><<<g1, 256, 0, st>>>(pr.left, pr.right, pr.row_stride_bytes, pr.downsample, w, h, packed, \
+                                                gx, gy, ia, (int)ix)
 #define BP_PACK(CV, WV) BP_PACK_S(CV, WV, 0)
     if (pr.channels == 1) {
         if (words) BP_PACK(1, true);

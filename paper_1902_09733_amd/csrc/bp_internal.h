@@ -79,9 +79,11 @@ bp_status launch_downsample(const uint8_t *in, int w, int h, int ch, int64_t str
 
 // a3: level-0 cost in the level's layout, and the sum pyramid.
 bp_status launch_split_cost(const float *planar, const Plan &p, uint8_t *ws, hipStream_t s);
-// Finest-level cost from a pair: packs the downsampled pair at p.pair_off,
-// then writes the data term in the level's layout, and level 1's pyramid sum
-// too when both levels are pixel-major (*levels_done = 2, else 1).
+// Finest-level cost from a pair: packs the downsampled pair at p.pair_off
+// (in the same launch as launch_init_messages' work, which callers therefore
+// skip on this route), then writes the data term in the level's layout, and
+// level 1's pyramid sum too when both levels are pixel-major
+// (*levels_done = 2, else 1).
 bp_status launch_pair_cost(const bp_pair &pr, const Plan &p, uint8_t *ws, hipStream_t s, int *levels_done);
 bp_status launch_pyramid_level(const Plan &p, int l, uint8_t *ws, hipStream_t s);
 // Levels first .. levels - 1 of the pyramid (up to three pixel-major levels
