@@ -7,8 +7,10 @@
 // (exact for 8-bit values), -|I_q|^2 and the tap's disparity as floats.  The
 // weight of a tap is exp2 of a non-positive exponent, spatial + range: the
 // spatial part is separable and depends only on the pixel's sub-pixel phase,
-// so the x part is a per-thread table of 2R+1 values and the y part a factor
-// applied once per window row to that row's sums; the range part is
+// so a per-block LDS table holds, for each of the block's 16 columns, the
+// 2R+1 x exponents (each thread copies its column's row into registers) and,
+// for each of its 16 rows, the 2R+1 exp2 factors of the y part, applied once
+// per window row to that row's sums; the range part is
 // -|I_p - I_q|^2 scaled by log2(e) / (2 sigma_r^2).  The squared distance is
 // formed exactly by FP16 dot products accumulating in FP32 (every term is an
 // integer below 2^24): 2 I_p.I_q - |I_q|^2 - 256 floor(|I_p|^2 / 256), the
