@@ -22,7 +22,6 @@ __all__ = [
     "value_noise",
     "slanted_planes",
     "aerial",
-    "downsample_box",
     "batch_specs",
     "jitter",
 ]
@@ -181,19 +180,6 @@ def aerial(width: int, height: int, num_labels: int, seed: int, channels: int = 
     left = np.clip(np.rint(left_f), 0, 255).astype(np.uint8)
     right = _warp_right(left.astype(np.float64), gt, rng, noise_sigma)
     return left, right, gt
-
-
-def downsample_box(img: np.ndarray, s: int) -> np.ndarray:
-    """Integer s x s box mean, rounding half up (input side of the path only).
-
-    Used to build ground truth at the matching resolution; the library's own
-    downsampling is part of the method and is implemented separately.
-    """
-    if s == 1:
-        return img.copy()
-    h, w = img.shape[:2]
-    v = img.astype(np.float64).reshape(h // s, s, w // s, s, *img.shape[2:])
-    return v.mean(axis=(1, 3))
 
 
 def jitter(shape, seed: int, high: float = 0.5) -> np.ndarray:

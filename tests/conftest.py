@@ -18,3 +18,13 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+# Alternate builds for the sanitizer runs (tests/test_sanitizers.py): the
+# parent test points these at instrumented copies of the two libraries.
+if os.environ.get("BP_TEST_ORACLE_LIB"):
+    import oracle as _oracle
+    _oracle._LIB_PATH = os.environ["BP_TEST_ORACLE_LIB"]
+if os.environ.get("BP_TEST_LIBRARY"):
+    from paper_1902_09733_amd import _abi as _abi_mod
+    _abi_mod.LIB_PATH = os.environ["BP_TEST_LIBRARY"]

@@ -65,3 +65,31 @@ def test_adjoint_zero_iterations_is_softmax_derivative(orc):
     ref = -g[None] / T * p * (np.arange(L)[:, None, None] - d[None])
     np.testing.assert_allclose(gc, ref, rtol=1e-12, atol=1e-15)
     assert gl == 0.0 and gt == 0.0
+
+
+@pytest.mark.parametrize("shape,K,lam,tau", [((6, 4, 5), 5, 3.0, 2.5), ((8, 5, 6), 6, 2.0, 2.0),
+                                             ((5, 1, 9), 4, 4.0, 1.5)])
+def test_adjoint_elementwise_autograd_with_ties(orc, shape, K, lam, tau):
+    """Integer costs make ties in the transform's comparisons common.  The
+    oracle's adjoint must equal, entry by entry, torch autograd through an
+    FP64 re-implementation of the forward pass that takes the same branch on
+    every tie (tests/_pins.py), for grad_cost, grad_lambda and grad_tau."""
+    torch = pytest.importorskip("torch")
+    import _pins
+    rng = np.random.default_rng(sum(shape) * 7 + K)
+    L, H, W = shape
+    cost = rng.integers(0, 12, size=shape).astype(float)
+    g = rng.normal(size=(H, W))
+    T = 0.5
+    soft, gc, gl, gt = orc.backward(cost, K, lam, tau, T, g)
+    c = torch.tensor(cost, dtype=torch.float64, requires_grad=True)
+    lt = torch.tensor(lam, dtype=torch.float64, requires_grad=True)
+    tt = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+    d = _pins.autograd_soft_bp(c, lt, tt, K, T)
+    np.testing.assert_allclose(d.detach().numpy(), soft, rtol=0, atol=1e-12)
+    (d * torch.tensor(g)).sum().backward()
+    np.testing.assert_allclose(gc, c.grad.numpy(), rtol=1e-10, atol=1e-12)
+    assert abs(gl - lt.grad.item()) <= 1e-10 * max(1.0, abs(gl))
+    assert abs(gt - tt.grad.item()) <= 1e-10 * max(1.0, abs(gt))
+    # The case exercises ties: pixels with two labels of equal cost.
+    assert (np.diff(np.sort(cost, axis=0), axis=0) == 0).any(axis=0).sum() > 0
