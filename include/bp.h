@@ -285,6 +285,37 @@ size_t bp_checkpoint_size(const bp_problem *probs, int32_t count, const bp_param
 bp_status bp_run(const bp_problem *probs, int32_t count, const bp_params *params, void *workspace,
                  size_t ws_bytes, void *checkpoints, size_t ckpt_bytes, hipStream_t stream);
 
+/* Size of the fixed device array bp_run_noalloc works in: 512 MiB, which
+ * holds bp_run's workspace for a 676 x 380 x 64-label five-level problem
+ * computed from a pair (420 MiB); bp_workspace_size() tells whether a call
+ * fits. */
+#define BP_NOALLOC_SCRATCH_BYTES ((size_t)512 << 20)
+
+/*
+ * bp_run without a caller workspace, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  Same problems, parameters, checkpoints, launch
+ * sequence, kernels and results as bp_run; the workspace is a fixed device
+ * array of BP_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, which the
+ * GPU holds from the first call on it until the process ends.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ *  - The array belongs to the current device; `stream` must be a stream of
+ *    that device (or NULL).  The first call on each device resolves the
+ *    array's device address (make it outside stream capture); later calls
+ *    reuse it.
+ *  - Every call on one GPU shares that GPU's array and leaves the last call's
+ *    contents in it; each call initialises everything it reads, so results
+ *    never depend on an earlier call.  Calls whose work overlaps on one GPU
+ *    (other streams or threads, before the earlier call's work has finished)
+ *    race on the array: serialise them, e.g. on one stream.
+ * Errors: as bp_run, with BP_ERR_WORKSPACE_TOO_SMALL when the problems need
+ * more than BP_NOALLOC_SCRATCH_BYTES (bp_workspace_size() > the array),
+ * BP_ERR_INVALID_ARGUMENT for a stream of another device, BP_ERR_HIP when
+ * the runtime cannot resolve the array's address.
+ */
+bp_status bp_run_noalloc(const bp_problem *probs, int32_t count, const bp_params *params, void *checkpoints,
+                         size_t ckpt_bytes, hipStream_t stream);
+
 /* One timed span of half-sweep launches (bp_run_profiled). */
 typedef struct {
     int32_t level;          /* pyramid level of the launches (0 = finest) */

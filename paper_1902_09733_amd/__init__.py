@@ -7,5 +7,5 @@ bilateral upsampling (Eq. 2), run by hand-written HIP kernels for gfx950
 behind the C ABI in include/bp.h.
 """
 from .stereo import (BPParams, Camera, Intrinsics, Pair, Workspace, backward, harris, icp, zssd_match, checkpoint_bytes, cost_volume, downsample,  # noqa: F401
-                     run, undistort, upsample, upsample_points, variant_count, workspace_bytes)
+                     run, run_noalloc, undistort, upsample, upsample_points, variant_count, workspace_bytes)
 from .autograd import BPSoftArgmin, soft_argmin_bp  # noqa: F401

@@ -17,6 +17,9 @@ BP_ERR_HIP = -4
 
 BP_MSG_F32, BP_MSG_F16, BP_MSG_BF16 = 0, 1, 2
 
+# Size of bp_run_noalloc's fixed per-GPU scratch array (BP_NOALLOC_SCRATCH_BYTES).
+BP_NOALLOC_SCRATCH_BYTES = 512 << 20
+
 
 class BpPair(ctypes.Structure):
     _fields_ = [
@@ -123,6 +126,8 @@ def lib():
     L.bp_checkpoint_size.restype = sz
     L.bp_run.argtypes = [P(BpProblem), i32, P(BpParams), vp, sz, vp, sz, vp]
     L.bp_run.restype = ctypes.c_int
+    L.bp_run_noalloc.argtypes = [P(BpProblem), i32, P(BpParams), vp, sz, vp]
+    L.bp_run_noalloc.restype = ctypes.c_int
     L.bp_run_profiled.argtypes = [P(BpProblem), i32, P(BpParams), vp, sz, vp, i32, P(BpLaunchRecord), i32, P(i32)]
     L.bp_run_profiled.restype = ctypes.c_int
     L.bp_upsample.argtypes = [vp, i32, i32, vp, i32, i32, i32, i64, f32, f32, i32, vp, vp]

@@ -373,6 +373,76 @@ bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans,
     return st;
 }
 
+// The fixed scratch array of bp_run_noalloc on the stream's device: the
+// current device, which a non-null stream must belong to.
+bp_status noalloc_workspace(hipStream_t stream, void **ws)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BP_ERR_HIP;
+    if (stream) {
+        int sdev = -1;
+        if (hipStreamGetDevice(stream, &sdev) != hipSuccess) return BP_ERR_HIP;
+        if (sdev != dev) return BP_ERR_INVALID_ARGUMENT;
+    }
+    *ws = noalloc_scratch(dev);
+    return *ws ? BP_OK : BP_ERR_HIP;
+}
+
+// bp_run on a workspace the caller has checked for alignment; a NULL
+// workspace selects bp_run_noalloc's fixed array (ws_bytes is then its size),
+// resolved only once the call has passed every other check.
+bp_status run_checked(const bp_problem *probs, int32_t count, const bp_params *params, void *workspace,
+                      size_t ws_bytes, void *checkpoints, size_t ckpt_bytes, hipStream_t stream)
+{
+    if (!probs || count < 1 || !valid_params(params)) return BP_ERR_INVALID_ARGUMENT;
+    for (int i = 0; i < count; ++i) {
+        if (!valid_problem(probs[i], *params)) return BP_ERR_INVALID_ARGUMENT;
+        if (!supported_labels(probs[i].num_labels)) return BP_ERR_UNSUPPORTED;
+    }
+    const bool ck = params->checkpoint_every > 0;
+    if (ck && !differentiable(*params)) return BP_ERR_UNSUPPORTED;
+    if (ck && (!checkpoints || ((uintptr_t)checkpoints % kAlign) != 0)) return BP_ERR_INVALID_ARGUMENT;
+    Plan *plans = new Plan[count];
+    size_t total = 0;
+    if (!plan_all(probs, count, params, plans, &total)) {
+        delete[] plans;
+        return BP_ERR_UNSUPPORTED;
+    }
+    size_t ck_total = 0;
+    if (ck)
+        for (int i = 0; i < count; ++i)
+            ck_total += checkpoint_bytes_of(plans[i], params->iters_per_level, params->checkpoint_every);
+    const bool batch = batched(plans, count, *params);
+    const size_t table_off = total;
+    if (batch) total += batch_table_bytes(count, params->levels);
+    if (ws_bytes < total || ckpt_bytes < ck_total) {
+        delete[] plans;
+        return BP_ERR_WORKSPACE_TOO_SMALL;
+    }
+    if (!workspace) {
+        const bp_status ws = noalloc_workspace(stream, &workspace);
+        if (ws != BP_OK) {
+            delete[] plans;
+            return ws;
+        }
+    }
+    (void)hipGetLastError();
+    if (batch) {
+        bp_status bs = run_batched(probs, count, plans, *params, (uint8_t *)workspace, table_off, stream);
+        delete[] plans;
+        return bs;
+    }
+    bp_status st = BP_OK;
+    size_t ck_off = 0;
+    for (int i = 0; i < count && st == BP_OK; ++i) {
+        uint8_t *cp = ck ? (uint8_t *)checkpoints + ck_off : nullptr;
+        st = run_one(probs[i], plans[i], *params, (uint8_t *)workspace, stream, nullptr, cp);
+        if (ck) ck_off += checkpoint_bytes_of(plans[i], params->iters_per_level, params->checkpoint_every);
+    }
+    delete[] plans;
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -445,47 +515,14 @@ size_t bp_checkpoint_size(const bp_problem *probs, int32_t count, const bp_param
 bp_status bp_run(const bp_problem *probs, int32_t count, const bp_params *params, void *workspace, size_t ws_bytes,
                  void *checkpoints, size_t ckpt_bytes, hipStream_t stream)
 {
-    if (!probs || count < 1 || !valid_params(params)) return BP_ERR_INVALID_ARGUMENT;
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return BP_ERR_INVALID_ARGUMENT;
-    for (int i = 0; i < count; ++i) {
-        if (!valid_problem(probs[i], *params)) return BP_ERR_INVALID_ARGUMENT;
-        if (!supported_labels(probs[i].num_labels)) return BP_ERR_UNSUPPORTED;
-    }
-    const bool ck = params->checkpoint_every > 0;
-    if (ck && !differentiable(*params)) return BP_ERR_UNSUPPORTED;
-    if (ck && (!checkpoints || ((uintptr_t)checkpoints % kAlign) != 0)) return BP_ERR_INVALID_ARGUMENT;
-    Plan *plans = new Plan[count];
-    size_t total = 0;
-    if (!plan_all(probs, count, params, plans, &total)) {
-        delete[] plans;
-        return BP_ERR_UNSUPPORTED;
-    }
-    size_t ck_total = 0;
-    if (ck)
-        for (int i = 0; i < count; ++i)
-            ck_total += checkpoint_bytes_of(plans[i], params->iters_per_level, params->checkpoint_every);
-    const bool batch = batched(plans, count, *params);
-    const size_t table_off = total;
-    if (batch) total += batch_table_bytes(count, params->levels);
-    if (ws_bytes < total || ckpt_bytes < ck_total) {
-        delete[] plans;
-        return BP_ERR_WORKSPACE_TOO_SMALL;
-    }
-    (void)hipGetLastError();
-    if (batch) {
-        bp_status bs = run_batched(probs, count, plans, *params, (uint8_t *)workspace, table_off, stream);
-        delete[] plans;
-        return bs;
-    }
-    bp_status st = BP_OK;
-    size_t ck_off = 0;
-    for (int i = 0; i < count && st == BP_OK; ++i) {
-        uint8_t *cp = ck ? (uint8_t *)checkpoints + ck_off : nullptr;
-        st = run_one(probs[i], plans[i], *params, (uint8_t *)workspace, stream, nullptr, cp);
-        if (ck) ck_off += checkpoint_bytes_of(plans[i], params->iters_per_level, params->checkpoint_every);
-    }
-    delete[] plans;
-    return st;
+    return run_checked(probs, count, params, workspace, ws_bytes, checkpoints, ckpt_bytes, stream);
+}
+
+bp_status bp_run_noalloc(const bp_problem *probs, int32_t count, const bp_params *params, void *checkpoints,
+                         size_t ckpt_bytes, hipStream_t stream)
+{
+    return run_checked(probs, count, params, nullptr, kNoallocScratchBytes, checkpoints, ckpt_bytes, stream);
 }
 
 bp_status bp_run_profiled(const bp_problem *probs, int32_t count, const bp_params *params, void *workspace,

@@ -68,6 +68,12 @@ int default_pm_from(int w, int h, int L, int levels, int msg_fmt);
 
 bp_status launch_status();
 
+// Fixed scratch of bp_run_noalloc (bp_noalloc.hip): its size, and its device
+// address on device `dev` (which must be current), resolved at the first call
+// per device; NULL if the runtime cannot resolve it.
+constexpr size_t kNoallocScratchBytes = BP_NOALLOC_SCRATCH_BYTES;
+void *noalloc_scratch(int dev);
+
 // ---- kernel launchers (each enqueues on `s`, returns BP_OK or BP_ERR_HIP) ----
 
 // a1 + a2: cost volume [L][h/ds][w/ds] from u8 images (optionally downsampled).

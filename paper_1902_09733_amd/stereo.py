@@ -170,6 +170,41 @@ def run(costs, params: BPParams, *, want_disp: bool = True, want_soft: bool = Fa
     [H][W]), ``soft`` (float32 [H][W]) and ``msgs`` (float32 [4][L][H][W]).
     ``outputs`` may pass preallocated dicts of the same form.
     """
+    single, costs, outputs, probs, p = _run_args(costs, params, want_disp, want_soft, want_msgs, outputs)
+    lib = _abi.lib()
+    nbytes = lib.bp_workspace_size(probs, len(costs), ctypes.byref(p))
+    if nbytes == 0:
+        raise ValueError("bp_workspace_size rejected the problem description")
+    ws = (workspace or _default_ws).get(nbytes, costs[0].device)
+    ck_ptr, ck_bytes = _ckpt(checkpoints)
+    st = lib.bp_run(probs, len(costs), ctypes.byref(p), _ptr(ws), nbytes, ck_ptr, ck_bytes, _stream(stream))
+    _abi.check("bp_run", st)
+    outs = [{k: v for k, v in o.items() if v is not None} for o in outputs]
+    return outs[0] if single else outs
+
+
+def run_noalloc(costs, params: BPParams, *, want_disp: bool = True, want_soft: bool = False,
+                want_msgs: bool = False, checkpoints: torch.Tensor | None = None, outputs=None, stream=None):
+    """``run`` through bp_run_noalloc: the library's fixed per-GPU scratch
+    array replaces the workspace, so the call allocates no device memory when
+    ``outputs`` (and ``checkpoints``, if any) are passed in."""
+    single, costs, outputs, probs, p = _run_args(costs, params, want_disp, want_soft, want_msgs, outputs)
+    ck_ptr, ck_bytes = _ckpt(checkpoints)
+    st = _abi.lib().bp_run_noalloc(probs, len(costs), ctypes.byref(p), ck_ptr, ck_bytes, _stream(stream))
+    _abi.check("bp_run_noalloc", st)
+    outs = [{k: v for k, v in o.items() if v is not None} for o in outputs]
+    return outs[0] if single else outs
+
+
+def _ckpt(checkpoints):
+    if checkpoints is None:
+        return None, 0
+    _need_gpu(checkpoints)
+    return _ptr(checkpoints), checkpoints.numel() * checkpoints.element_size()
+
+
+def _run_args(costs, params, want_disp, want_soft, want_msgs, outputs):
+    """Problem descriptors and output tensors of a run call."""
     single = isinstance(costs, (torch.Tensor, Pair))
     costs = [costs] if single else list(costs)
     for c in costs:
@@ -190,19 +225,7 @@ def run(costs, params: BPParams, *, want_disp: bool = True, want_soft: bool = Fa
             })
     probs = _problems(costs, [o.get("disp") for o in outputs], [o.get("soft") for o in outputs],
                       [o.get("msgs") for o in outputs])
-    p = params.c()
-    lib = _abi.lib()
-    nbytes = lib.bp_workspace_size(probs, len(costs), ctypes.byref(p))
-    if nbytes == 0:
-        raise ValueError("bp_workspace_size rejected the problem description")
-    ws = (workspace or _default_ws).get(nbytes, dev)
-    ck_ptr, ck_bytes = (None, 0)
-    if checkpoints is not None:
-        ck_ptr, ck_bytes = _ptr(checkpoints), checkpoints.numel() * checkpoints.element_size()
-    st = lib.bp_run(probs, len(costs), ctypes.byref(p), _ptr(ws), nbytes, ck_ptr, ck_bytes, _stream(stream))
-    _abi.check("bp_run", st)
-    outs = [{k: v for k, v in o.items() if v is not None} for o in outputs]
-    return outs[0] if single else outs
+    return single, costs, outputs, probs, params.c()
 
 
 def checkpoint_bytes(costs, params: BPParams) -> int:

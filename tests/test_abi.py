@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI: the library loads, exports every declared
 function, and rejects bad arguments before touching the GPU."""
 import ctypes
+import re
 
 import pytest
 
@@ -179,3 +180,26 @@ def test_icp_validation(lib):
                 dict(dmax=float("inf")), dict(ws=None), dict(ws=P(4096 + 8))):
         assert call(**bad) == _abi.BP_ERR_INVALID_ARGUMENT, bad
     assert call(nb=nb - 1) == _abi.BP_ERR_WORKSPACE_TOO_SMALL
+
+
+def test_noalloc_size_and_checks_before_any_device_call(lib):
+    """bp_run_noalloc rejects bad arguments and problems larger than its fixed
+    array on the host, before it touches a device (so these run without one)."""
+    src = open(_abi.HEADER).read()
+    m = re.search(r"#define BP_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == _abi.BP_NOALLOC_SCRATCH_BYTES
+    p = _params()
+    assert lib.bp_run_noalloc(_prob(), 0, ctypes.byref(p), None, 0, None) == _abi.BP_ERR_INVALID_ARGUMENT
+    assert lib.bp_run_noalloc(_prob(L=300), 1, ctypes.byref(p), None, 0, None) == _abi.BP_ERR_UNSUPPORTED
+    bad = _params(tau=0.0)
+    assert lib.bp_run_noalloc(_prob(), 1, ctypes.byref(bad), None, 0, None) == _abi.BP_ERR_INVALID_ARGUMENT
+    # 1352 x 760 x 128 labels, six levels: about 3.3 GB of workspace.
+    big = _prob(1352, 760, 128)
+    p6 = _params(levels=6)
+    assert lib.bp_workspace_size(big, 1, ctypes.byref(p6)) > _abi.BP_NOALLOC_SCRATCH_BYTES
+    assert lib.bp_run_noalloc(big, 1, ctypes.byref(p6), None, 0, None) == _abi.BP_ERR_WORKSPACE_TOO_SMALL
+    # The benchmarked 676 x 380 x 64 five-level problem from a pair fits.
+    pr = _pair(row_stride_bytes=2704 * 3)
+    q = _prob(676, 380, 64, cost=0)
+    q[0].pair = ctypes.pointer(pr)
+    assert 0 < lib.bp_workspace_size(q, 1, ctypes.byref(_params(levels=5))) <= _abi.BP_NOALLOC_SCRATCH_BYTES
