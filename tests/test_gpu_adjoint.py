@@ -66,6 +66,8 @@ def test_adjoint_matches_oracle_adjoint(dev, shape, K, every, layout):
         assert np.abs(soft[i] - s_o).max() <= 1e-3
         scale = np.abs(gc_o).max()
         close = np.abs(gc[i] - gc_o) <= 1e-3 * scale + 1e-5
+        print(f"problem {i}: {close.mean():.6f} of entries within 1e-3 of the largest "
+              f"({int((~close).sum())} outside)", flush=True)
         assert close.mean() >= 0.999, close.mean()
         V = np.random.default_rng(i).normal(size=shape)
         a, b = (gc[i] * V).sum(), (gc_o * V).sum()
@@ -91,6 +93,7 @@ def test_adjoint_mixed_label_counts(dev, layout):
         ot += gt_o
         scale = np.abs(gc_o).max()
         close = np.abs(gc[i] - gc_o) <= 1e-3 * scale + 1e-5
+        print(f"problem {i}: {close.mean():.6f} of entries within 1e-3 of the largest", flush=True)
         assert close.mean() >= 0.999, (i, close.mean())
     assert abs(gl - ol) <= DIR_TOL * max(1.0, abs(ol)), (gl, ol)
     assert abs(gt - ot) <= DIR_TOL * max(1.0, abs(ot)), (gt, ot)
@@ -113,6 +116,7 @@ def test_pixel_major_adjoint_smoothness_edges(dev, lam, tau):
         assert np.abs(soft[i] - s_o).max() <= 1e-3
         scale = max(np.abs(gc_o).max(), 1e-12)
         close = np.abs(gc[i] - gc_o) <= 1e-3 * scale + 1e-5
+        print(f"problem {i}: {close.mean():.6f} of entries within 1e-3 of the largest", flush=True)
         assert close.mean() >= 0.999, close.mean()
     assert abs(gl - ol) <= DIR_TOL * max(1.0, abs(ol)), (gl, ol)
     assert abs(gt - ot) <= DIR_TOL * max(1.0, abs(ot)), (gt, ot)
@@ -160,6 +164,8 @@ def test_autograd_batch_matches_finite_differences(dev):
     # GPU against the FP64 adjoint.
     scale = np.abs(ogC).max()
     close = np.abs(gC - ogC) <= 1e-3 * scale + 1e-5
+    print(f"batch: {close.mean():.7f} of {close.size} entries within 1e-3 of the largest "
+          f"({int((~close).sum())} outside)", flush=True)
     assert close.mean() >= 0.999, close.mean()
     for d in range(2):
         V = np.random.default_rng(100 + d).normal(size=C.shape)
@@ -203,3 +209,52 @@ def test_adjoint_is_deterministic(dev, layout):
     for x, y in zip(a[1], b[1]):
         np.testing.assert_array_equal(x, y)
     assert a[2] == b[2] and a[3] == b[3]
+
+
+def dyadic(shape, seed):
+    """Integer costs plus multiples of 1/64: with lambda and lambda*tau dyadic
+    too, every forward value of the FP32 half-sweeps is exact, and equal
+    values (ties of the min-plus comparisons) are frequent."""
+    rng = np.random.default_rng(seed)
+    return (rng.integers(0, 20, size=shape) + rng.integers(0, 64, size=shape) / 64.0).astype(np.float64)
+
+
+@pytest.mark.parametrize("shape,K,every", [((32, 12, 20), 6, 2), ((64, 17, 23), 8, 2), ((20, 9, 14), 5, 1),
+                                           ((128, 6, 9), 4, 2)])
+@pytest.mark.parametrize("lam,tau", [(3.25, 2.5), (1.5, 4.0), (2.0, 0.5)])
+@pytest.mark.parametrize("layout", ["pm", "lm"])
+def test_adjoint_exact_forward_elementwise(dev, shape, K, every, lam, tau, layout):
+    """Where the FP32 forward pass is exact (dyadic costs, lambda, lambda*tau),
+    the GPU follows the same branches as the FP64 oracle at every tie, so
+    every gradient entry must agree: the only differences left are the FP32
+    rounding of the soft-argmin weights and of the accumulated sums.  A
+    different tie rule anywhere (forward or backward pass, truncation,
+    normaliser, readout) routes a whole adjoint term to another label and
+    fails the bar.  Bar: |g_gpu - g_fp64| <= 1e-5 * (max |g_fp64| + |g_fp64|)
+    for every entry, no fraction allowance; lambda and tau (sums over the
+    whole problem) within 1e-4 relative; the soft disparity within 1e-6 L
+    labels."""
+    L, H, W = shape
+    rng = np.random.default_rng(L * 7 + K)
+    costs = [dyadic(shape, 300 + i + K) for i in range(2)]
+    g = [rng.normal(size=(H, W)).astype(np.float32).astype(np.float64) for _ in costs]
+    T = 0.5
+    soft, gc, gl, gt = gpu_grad(costs, g, K, lam, tau, T, every, dev, layout)
+    ol = ot = 0.0
+    for i, c in enumerate(costs):
+        s_o, gc_o, gl_o, gt_o = oracle.backward(c, K, lam, tau, T, g[i])
+        ol += gl_o
+        ot += gt_o
+        # soft-argmin in FP32: weights rounded once each, label sums up to L - 1
+        assert np.abs(soft[i] - s_o).max() <= 1e-6 * L, np.abs(soft[i] - s_o).max()
+        scale = np.abs(gc_o).max()
+        err = np.abs(gc[i] - gc_o)
+        bad = err > 1e-5 * (scale + np.abs(gc_o))
+        print(f"problem {i}: max |dg| / max |g| = {err.max() / scale:.3e}, "
+              f"entries outside the bar {int(bad.sum())} of {bad.size}", flush=True)
+        assert not bad.any(), np.argwhere(bad)[:10]
+    print(f"lambda gpu {gl:.8f} fp64 {ol:.8f}; tau gpu {gt:.8f} fp64 {ot:.8f}", flush=True)
+    # lambda and tau gradients sum every message adjoint times its branch
+    # coefficient over the whole problem: FP32 accumulation with cancellation
+    assert abs(gl - ol) <= 1e-4 * max(1.0, abs(ol)), (gl, ol)
+    assert abs(gt - ot) <= 1e-4 * max(1.0, abs(ot)), (gt, ot)
