@@ -21,6 +21,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libbp_oracle.so")
+# Compiler flags of the library (oracle/build.py), reported with CPU timings.
+BUILD_FLAGS = "gcc -std=c11 -O3 -march=x86-64-v3 -ffp-contract=off -fopenmp"
 _lib = None
 
 STORE_F64, STORE_F16, STORE_BF16, STORE_F32 = 0, 1, 2, 3
