@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--volume", action="store_true",
                     help="materialise the planar cost volume with bp_cost_volume inside the step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint", "points", "undistort",
+    ap.add_argument("--form", default="pair", choices=["pair", "batch", "precision", "adjoint", "points", "undistort", "ceiling",
                                                   "features", "icp", "counters"],
                     help="pair: the benchmarked single-pair path (default); batch, precision, adjoint "
                          "measure the other forms; points the JBU with fused triangulation; counters "
@@ -163,31 +163,44 @@ def main():
     recs = (_abi.BpLaunchRecord * 64)()
     nrec = ctypes.c_int32(0)
     stream_h = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    lv_ms, lv_bytes, lv_n = {}, {}, {}
+    lv_ms, lv_bytes, lv_units, lv_n = {}, {}, {}, {}
     for _ in range(6):
         st = lib.bp_run_profiled(probs, 1, ctypes.byref(cp), ctypes.c_void_p(wsb.data_ptr()), nbytes, stream_h, 1,
                                  recs, 64, ctypes.byref(nrec))
         _abi.check("bp_run_profiled", st)
         for i in range(nrec.value):
             r = recs[i]
-            # Algorithmic bytes: the active half of the pixels reads the cost
-            # (4 B) and 4 incoming messages and writes 4 outgoing ones.
+            # Algorithmic bytes of the level's launches as the library reports
+            # them: a single half-sweep's active half reads its cost and four
+            # incoming rows and writes four outgoing ones (18 B per pixel and
+            # label in FP32); a fused pair reads both colours' costs and
+            # colour 0's rows and writes colour 0's rows (10 B per pixel,
+            # label and half-sweep), colour 1's rows also at the level's end.
             lv_ms.setdefault(r.level, []).append(r.ms / r.launches)
-            lv_bytes[r.level] = r.units / r.launches * (4.0 + 8.0 * r.msg_bytes) / 2.0
+            lv_bytes[r.level] = r.bytes / r.launches
+            lv_units[r.level] = r.units / r.launches
             lv_n[r.level] = r.launches
     per_level = {l: float(np.median(v[1:])) for l, v in lv_ms.items()}     # first run is a warm-up
     l0_ms = per_level[0]
     achieved = lv_bytes[0] / (l0_ms * 1e-3) / 1e9
     all_ms = sum(per_level[l] * lv_n[l] for l in per_level)
     all_bytes = sum(lv_bytes[l] * lv_n[l] for l in per_level)
+    fused = lv_units[0] > w * h * L
+    # The same updates at the single-half-sweep schedule's 18 B (FP32): what a
+    # one-half-sweep kernel would have to stream to match this time.
+    equiv = lv_units[0] * (4.0 + 8.0 * (4 if args.msg_dtype == "f32" else 2)) / 2.0 / (l0_ms * 1e-3) / 1e9
 
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": stored_traffic() if args.msg_dtype == "f32" else None,
-        "kernel": f"k_iter_pm level-0 checkerboard half-sweep ({w}x{h}x{L}, {args.msg_dtype} messages)",
+        "kernel": (f"k_iter_pm2 level-0 fused pair of checkerboard half-sweeps ({w}x{h}x{L}, {args.msg_dtype} "
+                   "messages)") if fused else
+                  f"k_iter_pm level-0 checkerboard half-sweep ({w}x{h}x{L}, {args.msg_dtype} messages)",
         "avg_launch_us": round(l0_ms * 1e3, 2), "launches_per_step": lv_n[0],
-        "bytes_per_launch": lv_bytes[0], "bytes_per_update": lv_bytes[0] / (w * h * L),
+        "half_sweeps_per_launch": round(lv_units[0] / (w * h * L)),
+        "bytes_per_launch": lv_bytes[0], "bytes_per_update": lv_bytes[0] / lv_units[0],
+        "single_half_sweep_equivalent_GBps": round(equiv, 1),
         "per_level_avg_launch_us": {str(l): round(per_level[l] * 1e3, 2) for l in sorted(per_level)},
         "all_levels_GBps": round(all_bytes / (all_ms * 1e-3) / 1e9, 1),
     }
@@ -234,26 +247,45 @@ def main():
 
 def cpu_baseline(wl, updates, budget_s, threads=0):
     """The FP64 oracle (as it stands) on the host cores (all of them, or
-    `threads`): cost + 5-level BP of the same pair, repeated for about
-    `budget_s` seconds (at least once)."""
+    `threads`): the benchmarked step's three stages on the same pair --
+    downsample + cost volume, 5-level BP, joint bilateral upsampling to the
+    full frame -- repeated for about `budget_s` seconds (at least once); the
+    median time of each stage over the repetitions, and updates/s over the
+    whole step as the GPU's value counts them."""
+    import statistics
+
     import oracle
     S, L = wl["downsample"], wl["num_labels"]
     n = threads or oracle.max_threads()
-    l4 = oracle.downsample(wl["left"], S)
-    r4 = oracle.downsample(wl["right"], S)
-    reps, t0 = 0, time.perf_counter()
+    times = {"cost": [], "bp": [], "jbu": []}
+    t_start = time.perf_counter()
     while True:
+        t0 = time.perf_counter()
+        l4 = oracle.downsample(wl["left"], S)
+        r4 = oracle.downsample(wl["right"], S)
         c = oracle.cost_volume(l4, r4, L, wl["data_trunc"])
-        oracle.run(c, wl["levels"], wl["iters"], wl["lam"], wl["tau"], nthreads=n)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 50:
+        t1 = time.perf_counter()
+        o = oracle.run(c, wl["levels"], wl["iters"], wl["lam"], wl["tau"], nthreads=n)
+        t2 = time.perf_counter()
+        oracle.upsample(o["disp"], wl["left"], wl["sigma_s"], wl["sigma_r"], nthreads=n)
+        t3 = time.perf_counter()
+        times["cost"].append(t1 - t0)
+        times["bp"].append(t2 - t1)
+        times["jbu"].append(t3 - t2)
+        if time.perf_counter() - t_start >= budget_s or len(times["bp"]) >= 50:
             break
+    med = {k: statistics.median(v) for k, v in times.items()}
+    step = sum(med.values())
+    reps = len(times["bp"])
     return {
-        "value": round(reps * updates / el, 1), "unit": "updates/s", "cores": n,
+        "value": round(updates / step, 1), "unit": "updates/s", "cores": n,
         "kind": "oracle",
-        "sample": f"{reps} x (downsampled-pair cost volume + 5-level BP, {updates/1e6:.2f} M updates) of the "
-                  f"benchmarked pair, {el:.1f} s",
+        "sample": f"{reps} x the benchmarked pair's step (downsample + cost volume, 5-level BP of "
+                  f"{updates/1e6:.2f} M updates, JBU to {wl['width']}x{wl['height']}), median per stage",
+        "stage_s": {k: round(v, 4) for k, v in med.items()},
+        "pairs_per_s": round(1.0 / step, 3),
+        "bp_updates_per_s": round(updates / med["bp"], 1),
+        "build": oracle.BUILD_FLAGS,
     }
 
 
@@ -599,7 +631,9 @@ def form_icp(args):
 
 def form_counters(args):
     """The pair path three times without a graph (every dispatch visible to a
-    counter pass), then three plain device-to-device copies of 256 MiB."""
+    counter pass) with the library's kernel choice, three times with one
+    half-sweep per launch (variant 1, the same per-message arithmetic), then
+    three plain device-to-device copies of 256 MiB."""
     import torch
 
     import paper_1902_09733_amd as bp
@@ -613,20 +647,71 @@ def form_counters(args):
     pair = bp.Pair(left, right, L, wl["data_trunc"], downsample=S)
     for _ in range(3):
         bp.run(pair, params)
+    single = bp.BPParams(levels=wl["levels"], iters=wl["iters"], lam=wl["lam"], tau=wl["tau"], variant=1)
+    for _ in range(3):
+        bp.run(pair, single)
     src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev).fill_(1)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    return {"form": "counters", "copy_bytes": COPY_BYTES, "pair_runs": 3, "copies": 3,
+    return {"form": "counters", "copy_bytes": COPY_BYTES, "pair_runs": 3, "single_half_sweep_runs": 3, "copies": 3,
             "sources_sha256": sources_digest()}
+
+
+def form_ceiling(args):
+    """Practical bandwidth ceiling for the level-0 launches' read/write mixes:
+    bp_stream_probe moves the same bytes in 16-byte accesses (no BP work),
+    timed with HIP events on its stream, median of 20.  Mixes at the
+    benchmarked 676x380x64 level 0: a single half-sweep (reads 164.4 MB,
+    writes 131.5 MB), a fused pair (reads both costs and colour 0's rows,
+    197.3 MB, writes colour 0's rows, 131.5 MB), and a plain 1:1 copy."""
+    import ctypes
+
+    import torch
+
+    from paper_1902_09733_amd import _abi
+    lib = _abi.lib()
+    nl = 676 * 380 * 64
+    mixes = {
+        "single_half_sweep": (nl * (4 + 16) // 2, nl * 16 // 2),
+        "fused_pair": (nl * (4 + 8), nl * 8),
+        "copy_256MiB": (256 << 20, 256 << 20),
+    }
+    dev = torch.device("cuda:0")
+    big = max(max(r, w) for r, w in mixes.values())
+    src = torch.ones(big // 4 + 64, dtype=torch.float32, device=dev)
+    dst = torch.empty(big // 4 + 64, dtype=torch.float32, device=dev)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    out = {"form": "ceiling", "peak_GBps": HBM_PEAK_GBS}
+    for name, (rb, wb) in mixes.items():
+        rb, wb = rb // 16 * 16, wb // 16 * 16
+
+        def once():
+            _abi.check("bp_stream_probe", lib.bp_stream_probe(ctypes.c_void_p(src.data_ptr()), rb,
+                                                              ctypes.c_void_p(dst.data_ptr()), wb, st))
+        for _ in range(3):
+            once()
+        times = []
+        for _ in range(20):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            once()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        out[name] = {"read_bytes": rb, "write_bytes": wb, "us": round(ms * 1e3, 2),
+                     "GBps": round((rb + wb) / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_peak": round((rb + wb) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def run_form(form, args):
     return {"batch": form_batch, "precision": form_precision, "adjoint": form_adjoint, "points": form_points,
             "undistort": form_undistort, "features": form_features, "icp": form_icp,
-            "counters": form_counters}[form](args)
+            "counters": form_counters, "ceiling": form_ceiling}[form](args)
 
 
 if __name__ == "__main__":

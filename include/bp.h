@@ -93,7 +93,12 @@ typedef struct {
                                   level, the part of the message state the adjoint reads
                                   (and the whole final state) into the checkpoint buffer,
                                   whose contents only bp_backward interprets */
-    int32_t variant;           /* 0 = library choice; otherwise a half-sweep kernel variant in
+    int32_t variant;           /* 0 = library choice: on a single problem (or problems that do
+                                  not run batched), pixel-major levels with K >= 2 run two
+                                  half-sweeps per launch (tiles whose colour-1 messages stay
+                                  on chip between the two; a second buffer of half a level's
+                                  messages in the workspace), without checkpoints; otherwise
+                                  one half-sweep per launch.  Else a half-sweep kernel variant in
                                   1..bp_variant_count() (testing and tuning).  Label-major
                                   levels: lanes per pixel 1/2/4 by label count.  Pixel-major
                                   levels: 1 default lane split, 2 half the lanes with twice
@@ -285,11 +290,11 @@ size_t bp_checkpoint_size(const bp_problem *probs, int32_t count, const bp_param
 bp_status bp_run(const bp_problem *probs, int32_t count, const bp_params *params, void *workspace,
                  size_t ws_bytes, void *checkpoints, size_t ckpt_bytes, hipStream_t stream);
 
-/* Size of the fixed device array bp_run_noalloc works in: 512 MiB, which
+/* Size of the fixed device array bp_run_noalloc works in: 640 MiB, which
  * holds bp_run's workspace for a 676 x 380 x 64-label five-level problem
- * computed from a pair (420 MiB); bp_workspace_size() tells whether a call
+ * computed from a pair (546 MiB); bp_workspace_size() tells whether a call
  * fits. */
-#define BP_NOALLOC_SCRATCH_BYTES ((size_t)512 << 20)
+#define BP_NOALLOC_SCRATCH_BYTES ((size_t)640 << 20)
 
 /*
  * bp_run without a caller workspace, for callers that cannot allocate device
@@ -323,8 +328,14 @@ typedef struct {
     int32_t launches;       /* launches covered: 1, or the level's K with per_level */
     int32_t readout_fused;  /* number of covered launches that also wrote the senders' labels */
     int32_t msg_bytes;      /* bytes per stored message value at this level (4 or 2) */
-    double units;           /* pixel-label updates covered: launches * W_l * H_l * L */
+    double units;           /* pixel-label updates covered: half-sweeps * W_l * H_l * L */
     float ms;               /* time between HIP events recorded on `stream` around the span */
+    double bytes;           /* algorithmic memory traffic of the covered launches, per pixel and
+                               label of the level (mb = msg_bytes): a single half-sweep
+                               (4 + 8 mb) / 2 (the active half reads its cost and four incoming
+                               rows and writes four outgoing ones); a fused pair 4 + 4 mb (both
+                               colours' costs, colour 0's rows read and written), plus 2 mb
+                               for the pair that ends a level (colour 1's rows stored) */
 } bp_launch_record;
 
 /*
@@ -435,6 +446,18 @@ bp_status bp_load_tune_table(const char *path);
 /* Number of kernel variants bp_params.variant may select (1..count); 0 for an
  * unsupported label count. */
 int32_t bp_variant_count(int32_t num_labels);
+
+/*
+ * Measurement aid, not part of the method: streams `read_bytes` from `src`
+ * and writes `write_bytes` to `dst` in 16-byte accesses (chunk c of dst
+ * receives a value derived from chunk c of src), so that the mix of a BP
+ * launch's reads and writes can be timed alone and its sustained bandwidth
+ * taken as the practical ceiling for that mix.  dst's first 16 bytes may
+ * also be written when read_bytes > write_bytes.
+ * Errors: BP_ERR_INVALID_ARGUMENT for NULL or misaligned pointers, sizes not
+ * multiples of 16, or write_bytes < 16.
+ */
+bp_status bp_stream_probe(const void *src, size_t read_bytes, void *dst, size_t write_bytes, hipStream_t stream);
 
 /* Static text for a status code. */
 const char *bp_status_string(bp_status status);

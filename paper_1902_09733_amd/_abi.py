@@ -18,7 +18,7 @@ BP_ERR_HIP = -4
 BP_MSG_F32, BP_MSG_F16, BP_MSG_BF16 = 0, 1, 2
 
 # Size of bp_run_noalloc's fixed per-GPU scratch array (BP_NOALLOC_SCRATCH_BYTES).
-BP_NOALLOC_SCRATCH_BYTES = 512 << 20
+BP_NOALLOC_SCRATCH_BYTES = 640 << 20
 
 
 class BpPair(ctypes.Structure):
@@ -92,6 +92,7 @@ class BpLaunchRecord(ctypes.Structure):
         ("msg_bytes", ctypes.c_int32),
         ("units", ctypes.c_double),
         ("ms", ctypes.c_float),
+        ("bytes", ctypes.c_double),
     ]
 
 
@@ -148,6 +149,8 @@ def lib():
     L.bp_backward.restype = ctypes.c_int
     L.bp_backward_workspace_size.argtypes = [P(BpProblem), i32, P(BpParams)]
     L.bp_backward_workspace_size.restype = sz
+    L.bp_stream_probe.argtypes = [vp, sz, vp, sz, vp]
+    L.bp_stream_probe.restype = ctypes.c_int
     L.bp_load_tune_table.argtypes = [ctypes.c_char_p]
     L.bp_load_tune_table.restype = ctypes.c_int
     L.bp_variant_count.argtypes = [i32]

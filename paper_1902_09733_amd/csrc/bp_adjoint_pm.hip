@@ -145,6 +145,9 @@ __device__ __forceinline__ void pair_suffix_excl(float v, int vi, int s, float &
 template <int SEG, int R>
 __device__ __forceinline__ void bwd_step_pm(const BwdPmArgs &a, uint32_t block)
 {
+    // The forward arithmetic is repeated exactly as the half-sweep kernels
+    // do it: products rounded before they are added (bp_pm_core.h).
+#pragma clang fp contract(off)
     constexpr int GP = 4 * SEG;           // lanes per pixel
     constexpr int LP = SEG * R;           // labels stored per pixel
     __shared__ float2 s_post[256 * R];    // posted (mb, winner bits), one row of LP per (pixel, message)

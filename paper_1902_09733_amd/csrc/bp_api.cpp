@@ -115,8 +115,20 @@ bool tuned_choice(int w, int h, int L, int fmt, int levels, int *pm_from, int *v
 // (pm_from = levels), otherwise on pixel-major ones.
 static bool adjoint_label_major(const bp_params &p) { return p.pm_from == p.levels; }
 
-// Problem plans laid out back to back in the workspace.
-bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *plans, size_t *total)
+// Whether level l of a plan runs its half-sweeps as fused pairs.
+bool level_pairs(const Plan &pl, int l, int K)
+{
+    int S, R;
+    pm_split(pl.L, &S, &R);
+    return pl.pairs && pl.lv[l].layout == PIXEL_MAJOR && K >= 2 && pair_supported(S, R);
+}
+
+// Problem plans laid out back to back in the workspace.  With allow_pairs,
+// problems that leave the kernel choice to the library run pixel-major levels
+// as fused pairs of half-sweeps, which need a second buffer of colour 0's
+// incoming rows (the size of the finest such level's block).
+bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *plans, size_t *total,
+              bool allow_pairs = false)
 {
     size_t off = 0;
     for (int i = 0; i < count; ++i) {
@@ -137,6 +149,20 @@ bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
         plans[i].variant = p->variant != 0 ? p->variant : tv != 0 ? tv : default_variant(q.num_labels, p->msg_dtype);
         // The pixel-major adjoint repeats the sums of the plain-load split.
         if (p->checkpoint_every > 0 && pm_from == 0) plans[i].variant = 1;
+        plans[i].pairs = allow_pairs && p->variant == 0 && tv == 0 && p->checkpoint_every == 0;
+        plans[i].y_off = 0;
+        if (plans[i].pairs) {
+            size_t yb = 0;
+            for (int l = 0; l < plans[i].levels; ++l)
+                if (level_pairs(plans[i], l, p->iters_per_level)) {
+                    const Level &v = plans[i].lv[l];
+                    const size_t b = align_up((size_t)4 * v.blk * fmt_bytes(v.fmt));
+                    if (b > yb) yb = b;
+                }
+            plans[i].pairs = yb > 0;
+            plans[i].y_off = off + plans[i].bytes;
+            plans[i].bytes += yb;
+        }
         off += plans[i].bytes;
     }
     *total = align_up(off);
@@ -162,6 +188,20 @@ struct Recorder {
     int cap, n;
     bool per_level;
 };
+
+// Algorithmic memory traffic of one half-sweep and of one fused pair at
+// level l (bp_launch_record.bytes).
+double sweep_bytes(const Plan &pl, int l)
+{
+    const double nl = (double)pl.lv[l].w * pl.lv[l].h * pl.L;
+    return nl * (4.0 + 8.0 * fmt_bytes(pl.lv[l].fmt)) / 2.0;
+}
+
+double pair_bytes(const Plan &pl, int l, bool ends)
+{
+    const double nl = (double)pl.lv[l].w * pl.lv[l].h * pl.L, mb = fmt_bytes(pl.lv[l].fmt);
+    return nl * (4.0 + 4.0 * mb + (ends ? 2.0 * mb : 0.0));
+}
 
 // Runs the whole hierarchical BP of one problem.
 bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8_t *ws, hipStream_t s,
@@ -191,11 +231,66 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
         }
         const bool lrec = prof && prof->per_level && prof->n < prof->cap && K > 0;
         if (lrec && hipEventRecord(prof->ev[prof->n][0], s) != hipSuccess) return BP_ERR_HIP;
-        for (int t = 0; t < K; ++t) {
+        int launches = 0;
+        double lbytes = 0.0;   // algorithmic bytes of the level's launches
+        int t0 = 0;   // first half-sweep left to the one-half-sweep kernels
+        // Single half-sweeps of a level that runs fused pairs sum h in slot
+        // order like the pairs do (variant 1).
+        const bool lpairs = level_pairs(pl, l, K);
+        const int variant = lpairs ? 1 : pl.variant;
+        if (lpairs) {
+            // Fused pairs over half-sweeps [t0, K - (K & 1)).  Phase 1 of the
+            // first pair reads the parent's state, zeros (coarsest level) or the
+            // level's own state after a materialised parent copy; pairs
+            // alternate between the level's colour-0 block and the second
+            // buffer so that the last one writes the level's own block.  When
+            // the first pair would have to read and write the own block, two
+            // single half-sweeps go first.
+            const size_t own = pl.lv[l].msg_off, other = pl.y_off;
+            int np = K / 2;
+            const bool own_src = l < n - 1 && !first_src;
+            if (own_src && (np & 1)) {
+                for (; t0 < 2; ++t0, ++launches) {
+                    if ((st = launch_iteration(pl, l, t0, 0, p.lambda, p.tau, nullptr, variant, ws, s)) != BP_OK)
+                        return st;
+                    lbytes += sweep_bytes(pl, l);
+                }
+                --np;
+            }
+            size_t src_off = own;
+            for (int pi = 0; pi < np; ++pi, t0 += 2, ++launches) {
+                const size_t dst_off = ((np - 1 - pi) & 1) ? other : own;
+                int kind = PAIR_SRC_OWN;
+                if (t0 == 0) kind = l == n - 1 ? PAIR_SRC_ZERO : (first_src ? PAIR_SRC_PARENT : PAIR_SRC_OWN);
+                const bool ends = pi == np - 1 && (K & 1) == 0;
+                int32_t *ro = (l == 0 && ends && fuse_ro) ? q.disparity : nullptr;
+                const bool rec = prof && !prof->per_level && prof->n < prof->cap;
+                if (rec && hipEventRecord(prof->ev[prof->n][0], s) != hipSuccess) return BP_ERR_HIP;
+                if ((st = launch_iteration_pair(pl, l, kind, src_off, dst_off, ends, p.lambda, p.tau, ro, ws, s)) !=
+                    BP_OK)
+                    return st;
+                if (rec) {
+                    if (hipEventRecord(prof->ev[prof->n][1], s) != hipSuccess) return BP_ERR_HIP;
+                    bp_launch_record &r = prof->rec[prof->n++];
+                    r.level = l;
+                    r.half_sweep = t0;
+                    r.launches = 1;
+                    r.readout_fused = ro != nullptr;
+                    r.msg_bytes = fmt_bytes(pl.lv[l].fmt);
+                    r.units = 2.0 * pl.lv[l].w * pl.lv[l].h * pl.L;
+                    r.ms = 0.0f;
+                    r.bytes = pair_bytes(pl, l, ends);
+                }
+                lbytes += pair_bytes(pl, l, ends);
+                src_off = dst_off;
+            }
+        }
+        for (int t = t0; t < K; ++t) {
+            ++launches;
             int32_t *ro = (l == 0 && t == K - 1 && fuse_ro) ? q.disparity : nullptr;
             const bool rec = prof && !prof->per_level && prof->n < prof->cap;
             if (rec && hipEventRecord(prof->ev[prof->n][0], s) != hipSuccess) return BP_ERR_HIP;
-            if ((st = launch_iteration(pl, l, t, t == 0 ? first_src : 0, p.lambda, p.tau, ro, pl.variant, ws, s)) != BP_OK)
+            if ((st = launch_iteration(pl, l, t, t == 0 ? first_src : 0, p.lambda, p.tau, ro, variant, ws, s)) != BP_OK)
                 return st;
             if (rec) {
                 if (hipEventRecord(prof->ev[prof->n][1], s) != hipSuccess) return BP_ERR_HIP;
@@ -207,7 +302,9 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
                 r.msg_bytes = fmt_bytes(pl.lv[l].fmt);
                 r.units = (double)pl.lv[l].w * pl.lv[l].h * pl.L;
                 r.ms = 0.0f;
+                r.bytes = sweep_bytes(pl, l);
             }
+            lbytes += sweep_bytes(pl, l);
             if (ckpt && (t + 1) % p.checkpoint_every == 0 && t + 1 < K) {
                 // The adjoint reads a saved state M_{t+1} only through half-sweep
                 // t + 1's senders (the reverse step at t + 1, or the replay from
@@ -226,11 +323,12 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
             bp_launch_record &r = prof->rec[prof->n++];
             r.level = l;
             r.half_sweep = 0;
-            r.launches = K;
+            r.launches = launches;
             r.readout_fused = (l == 0 && fuse_ro) ? 1 : 0;
             r.msg_bytes = fmt_bytes(pl.lv[l].fmt);
             r.units = (double)K * pl.lv[l].w * pl.lv[l].h * pl.L;
             r.ms = 0.0f;
+            r.bytes = lbytes;
         }
     }
     if (ckpt) {
@@ -268,6 +366,16 @@ bool batched(const Plan *plans, int32_t count, const bp_params &p)
 size_t batch_table_bytes(int32_t count, int levels)
 {
     return align_up(((size_t)levels * 3 + 1) * count * sizeof(BatchEntry));
+}
+
+// Plans of a bp_run call: the batched form when it applies, otherwise each
+// problem on its own with fused pairs of half-sweeps where they apply.
+bool plan_run(const bp_problem *probs, int32_t count, const bp_params *p, Plan *plans, size_t *total, bool *batch)
+{
+    if (!plan_all(probs, count, p, plans, total)) return false;
+    *batch = batched(plans, count, *p);
+    if (*batch) return true;
+    return plan_all(probs, count, p, plans, total, true);
 }
 
 bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans, const bp_params &p, uint8_t *ws,
@@ -331,7 +439,7 @@ bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans,
                     BatchEntry &be = host[e++];
                     be.a = make_iter_args(pl, l, t, src_mode, p.lambda, p.tau, ro, ws);
                     be.block0 = b0;
-                    b0 += pm_blocks(be.a.ncomp, cls_S[c]);
+                    b0 += pm_sweep_blocks(be.a.ncomp, cls_S[c], cls_X[c]);
                     ++num[slot];
                 }
                 blocks[slot] = b0;
@@ -404,7 +512,8 @@ bp_status run_checked(const bp_problem *probs, int32_t count, const bp_params *p
     if (ck && (!checkpoints || ((uintptr_t)checkpoints % kAlign) != 0)) return BP_ERR_INVALID_ARGUMENT;
     Plan *plans = new Plan[count];
     size_t total = 0;
-    if (!plan_all(probs, count, params, plans, &total)) {
+    bool batch = false;
+    if (!plan_run(probs, count, params, plans, &total, &batch)) {
         delete[] plans;
         return BP_ERR_UNSUPPORTED;
     }
@@ -412,7 +521,6 @@ bp_status run_checked(const bp_problem *probs, int32_t count, const bp_params *p
     if (ck)
         for (int i = 0; i < count; ++i)
             ck_total += checkpoint_bytes_of(plans[i], params->iters_per_level, params->checkpoint_every);
-    const bool batch = batched(plans, count, *params);
     const size_t table_off = total;
     if (batch) total += batch_table_bytes(count, params->levels);
     if (ws_bytes < total || ckpt_bytes < ck_total) {
@@ -442,6 +550,7 @@ bp_status run_checked(const bp_problem *probs, int32_t count, const bp_params *p
     delete[] plans;
     return st;
 }
+
 
 }  // namespace
 
@@ -492,8 +601,9 @@ size_t bp_workspace_size(const bp_problem *probs, int32_t count, const bp_params
             return 0;
     Plan *plans = new Plan[count];
     size_t total = 0;
-    bool ok = plan_all(probs, count, params, plans, &total);
-    if (ok && batched(plans, count, *params)) total += batch_table_bytes(count, params->levels);
+    bool batch = false;
+    const bool ok = plan_run(probs, count, params, plans, &total, &batch);
+    if (ok && batch) total += batch_table_bytes(count, params->levels);
     delete[] plans;
     return ok ? total : 0;
 }
@@ -537,7 +647,8 @@ bp_status bp_run_profiled(const bp_problem *probs, int32_t count, const bp_param
     if (params->checkpoint_every > 0) return BP_ERR_UNSUPPORTED;
     Plan plan;
     size_t total = 0;
-    if (!plan_all(probs, 1, params, &plan, &total)) return BP_ERR_UNSUPPORTED;
+    bool batch = false;
+    if (!plan_run(probs, 1, params, &plan, &total, &batch)) return BP_ERR_UNSUPPORTED;
     if (ws_bytes < total) return BP_ERR_WORKSPACE_TOO_SMALL;
     (void)hipGetLastError();
     Recorder prof{records, new hipEvent_t[capacity > 0 ? capacity : 1][2], capacity, 0, per_level == 1};
@@ -557,6 +668,16 @@ bp_status bp_run_profiled(const bp_problem *probs, int32_t count, const bp_param
     delete[] prof.ev;
     *n_records = prof.n;
     return st;
+}
+
+bp_status bp_stream_probe(const void *src, size_t read_bytes, void *dst, size_t write_bytes, hipStream_t stream)
+{
+    if ((read_bytes && !src) || (write_bytes && !dst)) return BP_ERR_INVALID_ARGUMENT;
+    if ((uintptr_t)src % 16 || (uintptr_t)dst % 16 || read_bytes % 16 || write_bytes % 16)
+        return BP_ERR_INVALID_ARGUMENT;
+    if (write_bytes < 16) return BP_ERR_INVALID_ARGUMENT;
+    (void)hipGetLastError();
+    return launch_stream(src, read_bytes, dst, write_bytes, stream);
 }
 
 bp_status bp_harris(const uint8_t *img, int32_t width, int32_t height, int64_t stride, int32_t grid, int64_t threshold,

@@ -429,6 +429,53 @@ bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lamb
     return dispatch_iter_lm(a, v.fmt, iteration_lanes(p.L, variant), disp != nullptr, s);
 }
 
+bp_status launch_iteration_pair(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
+                                float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s)
+{
+    const Level &v = p.lv[l];
+    PairArgs a;
+    a.cost = (const float *)(ws + v.cost_off);
+    a.cost_bytes = (uint32_t)v.cost_bytes;
+    a.msg = ws + v.msg_off;
+    a.msg_bytes = (uint32_t)v.msg_bytes;
+    const uint32_t half = (uint32_t)((size_t)4 * v.blk * fmt_bytes(v.fmt));
+    if (src_kind == PAIR_SRC_PARENT) {
+        const Level &pa = p.lv[l + 1];
+        a.src = ws + pa.msg_off;
+        a.src_bytes = (uint32_t)pa.msg_bytes;
+        a.sblk = (uint32_t)pa.blk;
+        a.sps = (uint32_t)pa.ps;
+        a.src_wh = pa.wh;
+    } else {
+        a.src = ws + src_off;
+        a.src_bytes = half;
+        a.sblk = (uint32_t)v.blk;
+        a.sps = (uint32_t)v.ps;
+        a.src_wh = v.wh;
+    }
+    a.src_parent = src_kind == PAIR_SRC_PARENT;
+    a.src_zero = src_kind == PAIR_SRC_ZERO;
+    a.dst = ws + dst_off;
+    a.dst_bytes = half;
+    a.write_c1 = write_c1;
+    a.disp = disp;
+    a.w = v.w;
+    a.h = v.h;
+    a.wh = v.wh;
+    a.blk = (uint32_t)v.blk;
+    a.lp = (uint32_t)v.lp;
+    a.L = p.L;
+    a.lambda = lambda;
+    a.lt = lambda * tau;
+    pair_tile(v.lp, v.w, v.h, &a.tx, &a.ty);
+    a.tiles_x = (v.w + a.tx - 1) / a.tx;
+    a.ntiles = a.tiles_x * ((v.h + a.ty - 1) / a.ty);
+    a.per_xcd = (a.ntiles + 7) / 8;
+    int S, R;
+    pm_split(p.L, &S, &R);
+    return dispatch_iter_pm2(a, v.fmt, S, R, disp != nullptr, s);
+}
+
 bp_status launch_iteration_from(const Plan &p, int t, const uint8_t *src, float lambda, float tau, int variant,
                                 uint8_t *ws, hipStream_t s)
 {

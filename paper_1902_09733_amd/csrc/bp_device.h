@@ -216,27 +216,76 @@ __device__ __forceinline__ float seg_from_upper(float v, float ident, int s)
     return r;
 }
 
-// Inclusive prefix minimum over lanes 0..s of the segment.
-template <int SEG>
-__device__ __forceinline__ float seg_prefix_min(float v, int s)
+// Minimum scans of a whole 16-lane row written as DPP minimum instructions
+// (the compiler emits a copy, a DPP move and a minimum per step).  A lane
+// whose source lane lies outside the row is not written by a DPP operation
+// without bound_ctrl, so it keeps its own value, which is what an inclusive
+// minimum scan needs there.  Every DPP read of a register written by the
+// previous VALU instruction needs two wait states, which the compiler cannot
+// see inside the asm: each step is preceded by s_nop 1, and the block ends
+// with one for a DPP read that may follow it.  The values are never NaN.
+__device__ __forceinline__ float row_prefix_min16(float v)
 {
-    const float inf = __builtin_huge_valf();
-    v = fminf(v, seg_from_lower<SEG, 1>(v, inf, s));
-    if constexpr (SEG > 2) v = fminf(v, seg_from_lower<SEG, 2>(v, inf, s));
-    if constexpr (SEG > 4) v = fminf(v, seg_from_lower<SEG, 4>(v, inf, s));
-    if constexpr (SEG > 8) v = fminf(v, seg_from_lower<SEG, 8>(v, inf, s));
+    asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\ts_nop 1"
+                 : "+v"(v));
     return v;
 }
 
-// Inclusive suffix minimum over lanes s..SEG-1 of the segment.
+__device__ __forceinline__ float row_suffix_min16(float v)
+{
+    asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shl:2 row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shl:4 row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shl:8 row_mask:0xf bank_mask:0xf\n\ts_nop 1"
+                 : "+v"(v));
+    return v;
+}
+
+// Minimum over aligned groups of SEG lanes (2, 4, 8 or 16), every lane ending
+// with the group's minimum: the butterfly of seg_allreduce as DPP minimum
+// instructions (all source lanes are inside the row).
+template <int SEG>
+__device__ __forceinline__ float seg_allmin(float v)
+{
+    static_assert(SEG == 2 || SEG == 4 || SEG == 8 || SEG == 16, "unsupported segment");
+    asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf" : "+v"(v));
+    if constexpr (SEG > 2)
+        asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf" : "+v"(v));
+    if constexpr (SEG > 4)
+        asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xf" : "+v"(v));
+    if constexpr (SEG > 8)
+        asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_mirror row_mask:0xf bank_mask:0xf" : "+v"(v));
+    asm volatile("s_nop 1" ::);
+    return v;
+}
+
+// Inclusive prefix minimum over lanes 0..s of the segment.  A lane with no
+// lane N below it in its segment takes its own value (min is idempotent), so
+// the exchanges need no identity register.
+template <int SEG>
+__device__ __forceinline__ float seg_prefix_min(float v, int s)
+{
+    if constexpr (SEG == 16) return row_prefix_min16(v);
+    v = fminf(v, seg_from_lower<SEG, 1>(v, v, s));
+    if constexpr (SEG > 2) v = fminf(v, seg_from_lower<SEG, 2>(v, v, s));
+    if constexpr (SEG > 4) v = fminf(v, seg_from_lower<SEG, 4>(v, v, s));
+    if constexpr (SEG > 8) v = fminf(v, seg_from_lower<SEG, 8>(v, v, s));
+    return v;
+}
+
+// Inclusive suffix minimum over lanes s..SEG-1 of the segment (own value
+// where lane s + N is outside the segment, as above).
 template <int SEG>
 __device__ __forceinline__ float seg_suffix_min(float v, int s)
 {
-    const float inf = __builtin_huge_valf();
-    v = fminf(v, seg_from_upper<SEG, 1>(v, inf, s));
-    if constexpr (SEG > 2) v = fminf(v, seg_from_upper<SEG, 2>(v, inf, s));
-    if constexpr (SEG > 4) v = fminf(v, seg_from_upper<SEG, 4>(v, inf, s));
-    if constexpr (SEG > 8) v = fminf(v, seg_from_upper<SEG, 8>(v, inf, s));
+    if constexpr (SEG == 16) return row_suffix_min16(v);
+    v = fminf(v, seg_from_upper<SEG, 1>(v, v, s));
+    if constexpr (SEG > 2) v = fminf(v, seg_from_upper<SEG, 2>(v, v, s));
+    if constexpr (SEG > 4) v = fminf(v, seg_from_upper<SEG, 4>(v, v, s));
+    if constexpr (SEG > 8) v = fminf(v, seg_from_upper<SEG, 8>(v, v, s));
     return v;
 }
 

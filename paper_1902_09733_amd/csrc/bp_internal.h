@@ -51,6 +51,9 @@ struct Plan {
     int variant;          // half-sweep kernel variant (0 = default)
     Level lv[kMaxLevels];
     size_t pair_off;      // byte offset of the packed downsampled pair (cost from a pair)
+    bool pairs;           // pixel-major levels run fused pairs of half-sweeps (bp_iter_pm2.hip)
+    size_t y_off;         // second buffer of colour 0's incoming rows for the fused pairs
+                          // (the finest pixel-major level's size; 0 when !pairs)
     size_t bytes;         // total workspace bytes of this problem (aligned)
 };
 
@@ -106,6 +109,17 @@ bp_status launch_parent_copy(const Plan &p, int l, uint8_t *ws, hipStream_t s);
 // If disp != NULL the senders' argmin labels are written (finest level).
 bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lambda, float tau,
                            int32_t *disp, int variant, uint8_t *ws, hipStream_t s);
+// Half-sweeps t, t + 1 (t even) of pixel-major level l as one fused launch.
+// Phase 1 reads colour 0's incoming rows from the colour-0 block at byte
+// `src_off` of the workspace (PAIR_SRC_OWN), from the parent level's final
+// state (PAIR_SRC_PARENT, t = 0) or as zeros (PAIR_SRC_ZERO, the coarsest
+// level at t = 0); phase 2 writes colour 0's incoming rows into the colour-0
+// block at `dst_off` (never the block read).  write_c1 also stores colour 1's
+// incoming rows into the level's state; disp receives phase 2's senders'
+// labels (finest level).
+enum { PAIR_SRC_OWN = 0, PAIR_SRC_PARENT = 1, PAIR_SRC_ZERO = 2 };
+bp_status launch_iteration_pair(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
+                                float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s);
 // Half-sweep t of the finest level reading its incoming messages from `src`
 // (a saved state in the level's layout) and writing the receivers' slots
 // into the level's own message buffer.
@@ -116,6 +130,9 @@ bp_status launch_iteration_from(const Plan &p, int t, const uint8_t *src, float 
 bp_status launch_readout(const Plan &p, int colour_mask, int32_t *disp, float *soft, float temperature,
                          uint8_t *ws, hipStream_t s);
 bp_status launch_export(const Plan &p, float *out, uint8_t *ws, hipStream_t s);
+
+// Measurement aid: stream read_bytes from src and write_bytes to dst.
+bp_status launch_stream(const void *src, size_t read_bytes, void *dst, size_t write_bytes, hipStream_t s);
 
 // a7: joint bilateral upsampling.
 bp_status launch_harris(const uint8_t *img, int w, int h, int64_t stride, int g, int64_t thr, int64_t *r25,
@@ -204,6 +221,37 @@ bp_status launch_bwd_finish(const float *partial, int n, float *grad_lambda, flo
                             hipStream_t s);
 bp_status dispatch_iter_pm(const IterArgs &a, int fmt, int S, int R, bool ro, bool xchg, hipStream_t s);
 
+// Two half-sweeps (t, t + 1, t even) of a pixel-major level in one launch
+// (bp_iter_pm2.hip).  Phase 1 sends from colour 0, whose incoming rows are
+// read from `src` (a colour-0 block [slot][plane][lp] of the level, or the
+// parent level's whole state when src_parent, or all zero when src_zero);
+// phase 2 sends from colour 1 into `dst`, a colour-0 block of the level.
+struct PairArgs {
+    const float *cost;     // this level's cost
+    uint32_t cost_bytes;
+    uint8_t *msg;          // this level's messages (colour 1's block written when write_c1)
+    uint32_t msg_bytes;
+    const uint8_t *src;
+    uint32_t src_bytes;
+    uint8_t *dst;
+    uint32_t dst_bytes;
+    int32_t *disp;         // argmin labels of phase 2's senders, or NULL
+    int w, h, wh;
+    uint32_t blk, lp;      // this level's strides (pixel-major: ls = 1, ps = lp)
+    uint32_t sblk, sps;    // strides of `src`
+    int src_wh;
+    int src_parent, src_zero, write_c1;
+    int L;
+    float lambda, lt;
+    int tx, ty;            // tile (tx even)
+    int tiles_x, ntiles, per_xcd;
+};
+void pair_tile(int lp, int w, int h, int *tx, int *ty);
+size_t pair_lds_bytes(int tx, int ty, int lp);
+bp_status dispatch_iter_pm2(const PairArgs &a, int fmt, int S, int R, bool ro, hipStream_t s);
+// Whether the fused pair supports a level's lane split.
+bool pair_supported(int S, int R);
+
 // Pixel-major kernel variants (1 default split; 2 half the lanes per message,
 // twice the labels per lane; 3 and 4 the same with each lane group reading
 // only its own incoming row and exchanging sums by lane shuffles).
@@ -225,6 +273,7 @@ struct EntryChunk {
     int n;
 };
 int pm_blocks(int ncomp, int S);
+int pm_sweep_blocks(int ncomp, int S, bool xchg);
 bp_status launch_write_entries(BatchEntry *dst, const BatchEntry *src, int n, hipStream_t s);
 IterArgs make_iter_args(const Plan &p, int l, int t, int src_mode, float lambda, float tau, int32_t *disp,
                         uint8_t *ws);

@@ -2,11 +2,17 @@
 // pixel spread over lanes and the distance transform done as wave-level
 // min-plus scans.
 //
-// A sender pixel owns 4*SEG lanes: SEG lanes per outgoing message k (0 left,
-// 1 right, 2 up, 3 down), lane s holding labels [s*R, s*R + R).  Each lane
-// reads its labels of the cost and of the four incoming slots as 16-byte
-// vectors (a pixel's labels are contiguous in this layout), and forms
+// Lane s of a sender pixel's SEG lanes holds labels [s*R, s*R + R) of its
+// cost and of its four incoming slots (16-byte vectors: a pixel's labels are
+// contiguous in this layout) and computes, for each outgoing message k (0
+// left, 1 right, 2 up, 3 down),
 //   h(f) = cost(f) + sum of the incoming messages except slot k   (order 0..3)
+// and its transform (variants 1 and 2; variants 3 to 5 give each message its
+// own SEG lanes instead, see pm_sweep).  Measured on MI355X, the per-message
+// lane split spent 208 VALU instructions per pixel (one wave per pixel at 64
+// labels), most of them index arithmetic and h sums repeated by each of the
+// four lane groups, and left the finest half-sweep bound by instruction issue;
+// the lane holding all four messages spends about 82.
 // The two passes of the transform are split into a lane-local pass over R
 // labels and a scan across the SEG lanes of the message:
 //   forward   A(f) = min_{g<=f} h(g) + lambda (f - g):
@@ -26,9 +32,76 @@
 
 #include "bp_device.h"
 #include "bp_internal.h"
+#include "bp_pm_core.h"
 
 namespace bpk {
 
+// Variants 1 and 2: a sender pixel owns SEG lanes, lane s holding labels
+// [s R, s R + R) of the cost and of all four incoming rows (five 16-byte
+// row loads per lane, no load repeated), and computes the four outgoing
+// messages of those labels in turn (h in slot order, then the transform).
+// Per pixel this is a quarter of the lanes of the four-group split below,
+// so the index arithmetic and the h sums are shared by the four messages.
+template <int SEG, int R, typename S, bool EXACT, bool RO>
+__device__ __forceinline__ void pm_sweep4(const IterArgs &a, uint32_t block)
+{
+    const uint32_t gid = block * 256u + threadIdx.x;
+    const int j = (int)(gid / SEG);
+    const int s = (int)(gid % SEG);       // label segment
+    if (j >= a.ncomp) return;
+    const int y = j / a.wh;
+    const int x = 2 * (j - y * a.wh) + ((y + a.colour) & 1);
+    if (x >= a.w) return;
+
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost, a.cost_bytes);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, a.src_bytes);
+    const __amdgpu_buffer_rsrc_t rm = make_rsrc(a.msg, a.msg_bytes);
+    const int f0 = s * R;
+    int sj = j, sc = a.colour;
+    if (a.src_parent) {
+        const int sx = x >> 1, sy = y >> 1;
+        sc = (sx + sy) & 1;
+        sj = sy * a.src_wh + (sx >> 1);
+    }
+    const uint32_t base = (uint32_t)sj * a.sps + (uint32_t)f0;
+    float c[R], m[4][R];
+    ld_row<StoreF32, R>(rc, ((uint32_t)a.colour * a.blk + (uint32_t)j * a.lp + (uint32_t)f0) * 4u, c);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+        ld_row<S, R>(rs, (((uint32_t)sc * 4u + (uint32_t)kk) * a.sblk + base) * S::bytes, m[kk]);
+
+    if constexpr (RO) {
+        float bel[R];
+        pm_belief<R>(c, m, bel);
+        const int bi = pm_argmin<SEG, R, EXACT>(bel, f0, a.L);
+        if (s == 0 && a.disp) a.disp[(int64_t)y * a.w + x] = bi;
+    }
+    // All four h rows up front with shared partial sums while they fit the
+    // registers comfortably; one at a time for long label rows.
+    constexpr bool H4 = R <= 8;
+    float h4[H4 ? 4 : 1][R];
+    if constexpr (H4) pm_h4<R>(c, m, h4);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float h[R], out[R];
+        if constexpr (H4) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) h[r] = h4[k][r];
+        } else {
+            pm_h<R>(c, m, k, h);
+        }
+        pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, out);
+        int nx, ny;
+        if (pm_receiver(k, x, y, a.w, a.h, nx, ny)) {
+            const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
+            st_row<S, R>(rm, (((uint32_t)(a.colour ^ 1) * 4u + (uint32_t)(k ^ 1)) * a.blk + dj * a.lp +
+                              (uint32_t)f0) * S::bytes,
+                         out);
+        }
+    }
+}
+
+// Variants 3 to 5: a sender pixel owns 4 SEG lanes, SEG per outgoing message.
 template <int SEG, int R, typename S, bool EXACT, bool RO, bool XCHG>
 __device__ __forceinline__ void pm_sweep(const IterArgs &a, uint32_t block)
 {
@@ -102,58 +175,12 @@ __device__ __forceinline__ void pm_sweep(const IterArgs &a, uint32_t block)
     }
 
     if constexpr (RO) {
-        // Lowest-index argmin of the belief.
-        float bv = inf;
-        int bi = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            float b = bel[r];
-            if (!EXACT && f0 + r >= a.L) b = inf;
-            if (b < bv) {
-                bv = b;
-                bi = f0 + r;
-            }
-        }
-        seg_argmin<SEG>(bv, bi);
+        const int bi = pm_argmin<SEG, R, EXACT>(bel, f0, a.L);
         if (k == 0 && s == 0 && a.disp) a.disp[(int64_t)y * a.w + x] = bi;
     }
 
-    float hmin = inf;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (!EXACT && f0 + r >= a.L) h[r] = inf;
-        hmin = fminf(hmin, h[r]);
-    }
-    hmin = seg_allreduce<SEG>(hmin, [](float p, float q) { return fminf(p, q); });
-
-    // Forward pass.
-    float A[R];
-    A[0] = h[0];
-#pragma unroll
-    for (int r = 1; r < R; ++r) A[r] = fminf(h[r], A[r - 1] + lam);
-    {
-        const float u = A[R - 1] - lamR * (float)s;
-        const float P = seg_prefix_min<SEG>(seg_from_lower<SEG, 1>(u, inf, s), s);
-        const float carry = P + lamR * (float)(s - 1);
-#pragma unroll
-        for (int r = 0; r < R; ++r) A[r] = fminf(A[r], carry + lam * (float)(r + 1));
-    }
-    // Backward pass.
-    float B[R];
-    B[R - 1] = A[R - 1];
-#pragma unroll
-    for (int r = R - 2; r >= 0; --r) B[r] = fminf(A[r], B[r + 1] + lam);
-    {
-        const float v = B[0] + lamR * (float)s;
-        const float Q = seg_suffix_min<SEG>(seg_from_upper<SEG, 1>(v, inf, s), s);
-        const float carry = Q - lamR * (float)(s + 1);
-#pragma unroll
-        for (int r = 0; r < R; ++r) B[r] = fminf(B[r], carry + lam * (float)(R - r));
-    }
-    const float cap = hmin + a.lt;
     float out[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) out[r] = fminf(B[r], cap) - hmin;
+    pm_transform<SEG, R, EXACT>(h, s, f0, a.L, lam, a.lt, out);
 
     // Receiver of message k and its slot k^1.
     int nx = x, ny = y;
@@ -173,7 +200,8 @@ __device__ __forceinline__ void pm_sweep(const IterArgs &a, uint32_t block)
 template <int SEG, int R, typename S, bool EXACT, bool RO, bool XCHG>
 __global__ void __launch_bounds__(256) k_iter_pm(const IterArgs a)
 {
-    pm_sweep<SEG, R, S, EXACT, RO, XCHG>(a, blockIdx.x);
+    if constexpr (XCHG) pm_sweep<SEG, R, S, EXACT, RO, true>(a, blockIdx.x);
+    else pm_sweep4<SEG, R, S, EXACT, RO>(a, blockIdx.x);
 }
 
 // Batched half-sweep: the problems of one launch share the lane split; block
@@ -188,7 +216,8 @@ __global__ void __launch_bounds__(256) k_iter_pm_batch(const BatchEntry *__restr
         else hi = mid - 1;
     }
     const IterArgs a = tab[lo].a;
-    pm_sweep<SEG, R, S, false, RO, XCHG>(a, blockIdx.x - (uint32_t)tab[lo].block0);
+    if constexpr (XCHG) pm_sweep<SEG, R, S, false, RO, true>(a, blockIdx.x - (uint32_t)tab[lo].block0);
+    else pm_sweep4<SEG, R, S, false, RO>(a, blockIdx.x - (uint32_t)tab[lo].block0);
 }
 
 // Table of batch entries written from kernel arguments (capture-safe: no
@@ -258,6 +287,10 @@ bp_status launch_iteration_batch(const BatchEntry *tab, int n, int blocks, int f
 
 int pm_blocks(int ncomp, int SEGV) { return (int)(((int64_t)ncomp * 4 * SEGV + 255) / 256); }
 
+// Blocks of a forward half-sweep: SEG lanes per pixel (variants 1, 2) or 4 SEG
+// (shuffled-sum variants).
+int pm_sweep_blocks(int ncomp, int SEGV, bool xchg) { return (int)(((int64_t)ncomp * (xchg ? 4 : 1) * SEGV + 255) / 256); }
+
 void pm_split(int L, int *S, int *R)
 {
     if (L <= 16) { *S = 4; *R = 4; }
@@ -325,7 +358,7 @@ static void launch_pm_x(const IterArgs &a, bool ro, unsigned grid, hipStream_t s
 template <int SEG, int R, typename S>
 static bp_status launch_pm(const IterArgs &a, bool ro, bool xchg, hipStream_t st)
 {
-    const unsigned grid = (unsigned)(((int64_t)a.ncomp * 4 * SEG + 255) / 256);
+    const unsigned grid = (unsigned)pm_sweep_blocks(a.ncomp, SEG, xchg);
     if (xchg) launch_pm_x<SEG, R, S, true>(a, ro, grid, st);
     else launch_pm_x<SEG, R, S, false>(a, ro, grid, st);
     return launch_status();
@@ -336,7 +369,7 @@ template <int SEG, int R, typename S>
 static bp_status launch_pm_xonly(const IterArgs &a, bool ro, bool xchg, hipStream_t st)
 {
     if (!xchg) return BP_ERR_UNSUPPORTED;
-    launch_pm_x<SEG, R, S, true>(a, ro, (unsigned)(((int64_t)a.ncomp * 4 * SEG + 255) / 256), st);
+    launch_pm_x<SEG, R, S, true>(a, ro, (unsigned)pm_sweep_blocks(a.ncomp, SEG, true), st);
     return launch_status();
 }
 

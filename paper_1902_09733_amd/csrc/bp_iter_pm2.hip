@@ -1,0 +1,257 @@
+// a5, pixel-major levels: two consecutive checkerboard half-sweeps (t, t + 1,
+// t even) fused into one launch by tiling the level.
+//
+// Half-sweep t sends from the colour-0 pixels (x + y even) into the incoming
+// slots of the colour-1 pixels, and half-sweep t + 1 reads exactly those slots
+// and nothing else written at t; afterwards they are dead until half-sweep
+// t + 2 overwrites them.  A block owns a TX x TY tile (TX even, tile origin
+// even) and runs
+//   phase 1: every colour-0 pixel of the tile and of a one-pixel ring around
+//            it (the ring pixels belong to neighbouring tiles, which compute
+//            them too) reads its cost and four incoming rows and computes
+//            its four outgoing messages; those whose receiver is a colour-1
+//            pixel of the tile go to LDS (rounded to the storage format),
+//            the rest are dropped;
+//   phase 2: every colour-1 pixel of the tile reads its cost from memory and
+//            its four incoming rows from LDS and sends its four messages to
+//            its colour-0 neighbours (inside the tile or on the ring).
+// So colour 1's incoming rows never travel to memory, which removes their
+// write and re-read: per pixel pair and two half-sweeps the traffic is two
+// costs, one colour-0 incoming state read and one written (plus the ring's
+// reads), against two costs, both states read and both written.
+//
+// Phase 1 of one tile reads colour-0 rows of ring pixels that phase 2 of the
+// neighbouring tile writes in the same launch, so colour 0's incoming slots
+// are double-buffered: phase 1 reads `src` (the level's own state or a
+// second buffer of the same layout, or the parent level's final state for
+// t = 0) and phase 2 writes `dst`, the other one.  The host alternates them so
+// that the level's last pair writes the level's own state.  When the pair
+// ends the level (or precedes a last single half-sweep), phase 1 also stores
+// colour 1's incoming rows into the level's state, which the next level's
+// parent copy and the readout read.
+//
+// Per message the arithmetic is the one-half-sweep kernel's variant 1
+// (bp_pm_core.h: h summed in slot order, the same transform), so results
+// equal two launches of that kernel bit for bit.
+#include <hip/hip_runtime.h>
+
+#include "bp_device.h"
+#include "bp_internal.h"
+#include "bp_pm_core.h"
+
+namespace bpk {
+
+// A pixel owns SEG lanes, lane s holding labels [s R, s R + R) of its cost and
+// incoming rows, and computes its four outgoing messages in turn (as the
+// one-half-sweep kernel's variant 1).  U pixels per lane group are loaded
+// before any is computed, to keep more rows in flight per wave.
+template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U>
+__global__ void __launch_bounds__(NT) k_iter_pm2(const PairArgs a)
+{
+    extern __shared__ float lds[];       // [tile colour-1 pixel][slot][lp]
+    constexpr int PPB = NT / SEG;        // lane groups (pixels at a time) per block
+    // Tile of this block: blocks b, b + 8, ... run on one XCD of the eight and
+    // take a contiguous run of tiles, so a tile's ring comes from its own L2.
+    const int b = (int)blockIdx.x;
+    const int tile = (b & 7) * a.per_xcd + (b >> 3);
+    if (tile >= a.ntiles) return;
+    const int TX = a.tx, TY = a.ty, HX = TX >> 1;
+    const int tx0 = (tile % a.tiles_x) * TX, ty0 = (tile / a.tiles_x) * TY;
+    const int g = (int)threadIdx.x / SEG, s = (int)threadIdx.x % SEG, f0 = s * R;
+    const uint32_t lp = a.lp;
+
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost, a.cost_bytes);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, a.src_bytes);
+    const __amdgpu_buffer_rsrc_t rm = make_rsrc(a.msg, a.msg_bytes);
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(a.dst, a.dst_bytes);
+
+    // Phase 1: colour-0 pixels of [tx0 - 1, tx0 + TX] x [ty0 - 1, ty0 + TY]
+    // without the corners, HX + 1 per row.
+    const int n1 = (TY + 2) * (HX + 1);
+    for (int i0 = g; i0 < n1; i0 += PPB * U) {
+        int xs[U], ys[U];
+        bool live[U];
+        float c[U][R], m[U][4][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * PPB;
+            const int r = i / (HX + 1), cc = i - r * (HX + 1);
+            const int y = ty0 - 1 + r;
+            const int x = tx0 - 1 + 2 * cc + ((tx0 - 1 + y) & 1);
+            xs[u] = x;
+            ys[u] = y;
+            live[u] = i < n1 && x >= 0 && x < a.w && y >= 0 && y < a.h &&
+                      !((r == 0 || r == TY + 1) && (x < tx0 || x >= tx0 + TX));
+            if (!live[u]) continue;
+            const int j = y * a.wh + (x >> 1);
+            int sj = j, sc = 0;
+            if (a.src_parent) {
+                const int sx = x >> 1, sy = y >> 1;
+                sc = (sx + sy) & 1;
+                sj = sy * a.src_wh + (sx >> 1);
+            }
+            ld_row<StoreF32, R>(rc, ((uint32_t)j * lp + (uint32_t)f0) * 4u, c[u]);
+            const uint32_t base = (uint32_t)sj * a.sps + (uint32_t)f0;
+            // Slots from outside the grid are zero; they are not read, since
+            // the second buffer never holds them.
+            const bool has[4] = {x > 0, x < a.w - 1, y > 0, y < a.h - 1};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                if (!a.src_zero && has[kk]) {
+                    ld_row<S, R>(rs, (((uint32_t)sc * 4u + (uint32_t)kk) * a.sblk + base) * S::bytes, m[u][kk]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < R; ++q) m[u][kk][q] = 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!live[u]) continue;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int nx, ny;
+                const bool ok = pm_receiver(k, xs[u], ys[u], a.w, a.h, nx, ny);
+                // Only receivers inside the tile (colour 1 by construction);
+                // the same for every lane of the pixel.
+                if (!(ok && nx >= tx0 && nx < tx0 + TX && ny >= ty0 && ny < ty0 + TY)) continue;
+                float h[R], out[R];
+                pm_h<R>(c[u], m[u], k, h);
+                pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, out);
+                const int slot = (ny - ty0) * HX + ((nx - tx0) >> 1);
+                float *row = lds + ((uint32_t)slot * 4u + (uint32_t)(k ^ 1)) * lp + f0;
+                if constexpr (S::bytes == 4) {
+#pragma unroll
+                    for (int q = 0; q < R; ++q) row[q] = out[q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < R; ++q) row[q] = S::decode(S::encode(out[q]));
+                }
+                if (a.write_c1) {
+                    const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
+                    st_row<S, R>(rm, ((4u + (uint32_t)(k ^ 1)) * a.blk + dj * lp + (uint32_t)f0) * S::bytes, out);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // Phase 2: the tile's colour-1 pixels, HX per row.
+    const int n2 = TY * HX;
+    for (int i0 = g; i0 < n2; i0 += PPB * U) {
+        int xs[U], ys[U];
+        bool live[U];
+        float c[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * PPB;
+            const int r = i / HX, cc = i - r * HX;
+            const int y = ty0 + r;
+            const int x = tx0 + 2 * cc + ((tx0 + y + 1) & 1);
+            xs[u] = x;
+            ys[u] = y;
+            live[u] = i < n2 && x < a.w && y < a.h;
+            if (!live[u]) continue;
+            const int j = y * a.wh + (x >> 1);
+            ld_row<StoreF32, R>(rc, ((a.blk + (uint32_t)j * lp) + (uint32_t)f0) * 4u, c[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!live[u]) continue;
+            const int i = i0 + u * PPB, x = xs[u], y = ys[u];
+            // Slots from outside the grid hold zero (never written above).
+            const bool has[4] = {x > 0, x < a.w - 1, y > 0, y < a.h - 1};
+            const float *row = lds + (uint32_t)i * 4u * lp + f0;
+            float m[4][R];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) m[kk][q] = has[kk] ? row[kk * lp + q] : 0.0f;
+            }
+            if constexpr (RO) {
+                float bel[R];
+                pm_belief<R>(c[u], m, bel);
+                const int bi = pm_argmin<SEG, R, EXACT>(bel, f0, a.L);
+                if (s == 0 && a.disp) a.disp[(int64_t)y * a.w + x] = bi;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int nx, ny;
+                if (!pm_receiver(k, x, y, a.w, a.h, nx, ny)) continue;
+                float h[R], out[R];
+                pm_h<R>(c[u], m, k, h);
+                pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, out);
+                const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
+                st_row<S, R>(rd, ((uint32_t)(k ^ 1) * a.blk + dj * lp + (uint32_t)f0) * S::bytes, out);
+            }
+        }
+    }
+}
+
+// Tile of a fused pair at a w x h level: the largest of a few shapes whose
+// colour-1 rows fit 64 KiB of LDS (TX x TY / 2 pixels x 4 rows x lp floats),
+// halved (rows first) while the level has fewer than 512 tiles, so that small
+// levels still spread over every compute unit (down to 4 x 4).
+void pair_tile(int lp, int w, int h, int *tx, int *ty)
+{
+    const int px = 65536 / (16 * lp);   // colour-1 pixels that fit
+    if (px >= 256) { *tx = 32; *ty = 16; }
+    else if (px >= 128) { *tx = 16; *ty = 16; }
+    else if (px >= 64) { *tx = 16; *ty = 8; }
+    else if (px >= 32) { *tx = 8; *ty = 8; }
+    else { *tx = 8; *ty = 4; }
+    auto tiles = [&](int a, int b) { return (int64_t)((w + a - 1) / a) * ((h + b - 1) / b); };
+    while (tiles(*tx, *ty) < 512 && (*tx > 4 || *ty > 4)) {
+        if (*ty >= *tx && *ty > 4) *ty /= 2;
+        else *tx /= 2;
+    }
+}
+
+size_t pair_lds_bytes(int tx, int ty, int lp) { return (size_t)tx * ty / 2 * 4 * lp * sizeof(float); }
+
+template <int SEG, int R, typename S, bool EXACT, bool RO>
+static bp_status launch_pm2(const PairArgs &a, size_t lds, hipStream_t st)
+{
+    constexpr int NT = 512;
+    constexpr int U = 1;
+    const unsigned grid = (unsigned)(8 * a.per_xcd);
+    k_iter_pm2<SEG, R, S, EXACT, RO, NT, U><<<grid, NT, lds, st>>>(a);
+    return launch_status();
+}
+
+template <int SEG, int R, typename S>
+static bp_status launch_pm2_ro(const PairArgs &a, size_t lds, bool ro, hipStream_t st)
+{
+    const bool exact = a.L == SEG * R;
+    if (exact) return ro ? launch_pm2<SEG, R, S, true, true>(a, lds, st) : launch_pm2<SEG, R, S, true, false>(a, lds, st);
+    return ro ? launch_pm2<SEG, R, S, false, true>(a, lds, st) : launch_pm2<SEG, R, S, false, false>(a, lds, st);
+}
+
+template <typename S>
+static bp_status dispatch_pm2(const PairArgs &a, size_t lds, int SEGV, int R, bool ro, hipStream_t st)
+{
+#define BP_PM2(SV, RV) \
+    if (SEGV == SV && R == RV) return launch_pm2_ro<SV, RV, S>(a, lds, ro, st);
+    BP_PM2(4, 4) BP_PM2(8, 4) BP_PM2(16, 4) BP_PM2(16, 6) BP_PM2(16, 8) BP_PM2(16, 12) BP_PM2(16, 16)
+#undef BP_PM2
+    return BP_ERR_UNSUPPORTED;
+}
+
+bool pair_supported(int SEGV, int R)
+{
+    return (SEGV == 4 && R == 4) || (SEGV == 8 && R == 4) ||
+           (SEGV == 16 && (R == 4 || R == 6 || R == 8 || R == 12 || R == 16));
+}
+
+bp_status dispatch_iter_pm2(const PairArgs &a, int fmt, int SEGV, int R, bool ro, hipStream_t st)
+{
+    const size_t lds = pair_lds_bytes(a.tx, a.ty, (int)a.lp);
+    if (lds > 65536 || (a.tx & 1) || a.tx <= 0 || a.ty <= 0) return BP_ERR_UNSUPPORTED;
+    switch (fmt) {
+    case FMT_F16: return dispatch_pm2<StoreF16>(a, lds, SEGV, R, ro, st);
+    case FMT_BF16: return dispatch_pm2<StoreBF16>(a, lds, SEGV, R, ro, st);
+    default: return dispatch_pm2<StoreF32>(a, lds, SEGV, R, ro, st);
+    }
+}
+
+}  // namespace bpk

@@ -1,0 +1,137 @@
+// The per-message arithmetic of a pixel-major half-sweep, shared by the
+// one-half-sweep kernels (bp_iter_pm.hip) and the fused pair of half-sweeps
+// (bp_iter_pm2.hip): the distance transform of h over a message's SEG lanes
+// (R labels per lane), truncation and normalisation, and the argmin of a
+// belief.  The identities behind the split scans are in bp_iter_pm.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bp_device.h"
+
+namespace bpk {
+
+// out(f) = min(min_g h(g) + lambda |f - g|, min h + lt) - min h for the
+// labels [s R, s R + R) of lane s of its segment; labels at or past L must
+// hold +inf in h unless EXACT (L == SEG * R).
+//
+// Every product is rounded before it is added (no multiply-add contraction):
+// the compiler would otherwise fuse or not depending on what it hoists out of
+// the calling kernel's loops, and two kernels running this transform on the
+// same data (one half-sweep per launch, or two) must agree bit for bit.
+template <int SEG, int R, bool EXACT>
+__device__ __forceinline__ void pm_transform(float (&h)[R], int s, int f0, int L, float lam, float lt, float (&out)[R])
+{
+#pragma clang fp contract(off)
+    const float inf = __builtin_huge_valf();
+    const float lamR = lam * (float)R;
+    float hmin = inf;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!EXACT && f0 + r >= L) h[r] = inf;
+        hmin = fminf(hmin, h[r]);
+    }
+    hmin = seg_allmin<SEG>(hmin);
+
+    // Forward pass.
+    float A[R];
+    A[0] = h[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r) A[r] = fminf(h[r], A[r - 1] + lam);
+    {
+        const float u = A[R - 1] - lamR * (float)s;
+        const float P = seg_prefix_min<SEG>(seg_from_lower<SEG, 1>(u, inf, s), s);
+        const float carry = P + lamR * (float)(s - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) A[r] = fminf(A[r], carry + lam * (float)(r + 1));
+    }
+    // Backward pass.
+    float B[R];
+    B[R - 1] = A[R - 1];
+#pragma unroll
+    for (int r = R - 2; r >= 0; --r) B[r] = fminf(A[r], B[r + 1] + lam);
+    {
+        const float v = B[0] + lamR * (float)s;
+        const float Q = seg_suffix_min<SEG>(seg_from_upper<SEG, 1>(v, inf, s), s);
+        const float carry = Q - lamR * (float)(s + 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) B[r] = fminf(B[r], carry + lam * (float)(R - r));
+    }
+    const float cap = hmin + lt;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r] = fminf(B[r], cap) - hmin;
+}
+
+// h for outgoing message k (to the neighbour on side k): the cost plus the
+// incoming rows of the other three slots, added in slot order.
+template <int R>
+__device__ __forceinline__ void pm_h(const float (&c)[R], const float (&m)[4][R], int k, float (&h)[R])
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (k == 0) h[r] = ((c[r] + m[1][r]) + m[2][r]) + m[3][r];
+        else if (k == 1) h[r] = ((c[r] + m[0][r]) + m[2][r]) + m[3][r];
+        else if (k == 2) h[r] = ((c[r] + m[0][r]) + m[1][r]) + m[3][r];
+        else h[r] = ((c[r] + m[0][r]) + m[1][r]) + m[2][r];
+    }
+}
+
+// The four h rows of pm_h at once, sharing the partial sums cost + m0 and
+// cost + m0 + m1 (the same additions in the same order).
+template <int R>
+__device__ __forceinline__ void pm_h4(const float (&c)[R], const float (&m)[4][R], float (&h)[4][R])
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float p0 = c[r] + m[0][r];
+        const float p01 = p0 + m[1][r];
+        h[0][r] = ((c[r] + m[1][r]) + m[2][r]) + m[3][r];
+        h[1][r] = (p0 + m[2][r]) + m[3][r];
+        h[2][r] = p01 + m[3][r];
+        h[3][r] = p01 + m[2][r];
+    }
+}
+
+// Belief cost + all four incoming rows, in slot order (readout).
+template <int R>
+__device__ __forceinline__ void pm_belief(const float (&c)[R], const float (&m)[4][R], float (&b)[R])
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) b[r] = (((c[r] + m[0][r]) + m[1][r]) + m[2][r]) + m[3][r];
+}
+
+// Receiver of message k from (x, y): its coordinates, and whether it is in
+// the grid (0 left, 1 right, 2 up, 3 down).
+__device__ __forceinline__ bool pm_receiver(int k, int x, int y, int w, int h, int &nx, int &ny)
+{
+    nx = x;
+    ny = y;
+    if (k == 0) { nx = x - 1; return x > 0; }
+    if (k == 1) { nx = x + 1; return x < w - 1; }
+    if (k == 2) { ny = y - 1; return y > 0; }
+    ny = y + 1;
+    return y < h - 1;
+}
+
+// Lowest label minimising the belief over the segment; labels at or past L
+// are ignored unless EXACT.
+template <int SEG, int R, bool EXACT>
+__device__ __forceinline__ int pm_argmin(const float (&bel)[R], int f0, int L)
+{
+    const float inf = __builtin_huge_valf();
+    float bv = inf;
+    int bi = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float b = bel[r];
+        if (!EXACT && f0 + r >= L) b = inf;
+        if (b < bv) {
+            bv = b;
+            bi = f0 + r;
+        }
+    }
+    seg_argmin<SEG>(bv, bi);
+    return bi;
+}
+
+}  // namespace bpk

@@ -1,0 +1,93 @@
+"""The fused pair of half-sweeps (two checkerboard half-sweeps per launch,
+colour-1 messages kept on chip between them) against one launch per
+half-sweep.
+
+The library runs pixel-major levels as fused pairs when the kernel choice is
+left to it (variant 0); variant 1 is the one-half-sweep kernel with the same
+per-message arithmetic (h summed in slot order).  On real-valued costs --
+where any change of operation order would show -- both must give the same
+labels and final finest-level messages bit for bit, over tile edges and
+ragged grids (1x1 up to several tiles), every lane split (2 to 256 labels),
+odd and even K (single half-sweeps before or after the pairs), one to five
+levels, and the three storage formats (16-bit levels under an FP32 coarsest
+level take the materialised parent copy).  On integer data the fused path
+also equals the FP64 oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_1902_09733_amd as bp
+    bp.stereo._abi.lib()
+    return torch.device("cuda:0")
+
+
+def both(bp, cost, levels, K, fmt, lam=7.3, tau=2.6):
+    outs = []
+    for variant in (0, 1):
+        p = bp.BPParams(levels=levels, iters=K, lam=lam, tau=tau, msg_dtype=fmt, variant=variant)
+        o = bp.run(cost, p, want_msgs=True)
+        torch.cuda.synchronize()
+        outs.append(o)
+    return outs
+
+
+CASES = [
+    # (L, H, W, levels, K, fmt)
+    (64, 380 // 4, 676 // 4, 3, 10, "f32"),
+    (64, 37, 53, 2, 7, "f32"),
+    (64, 1, 1, 1, 4, "f32"),
+    (64, 1, 2, 1, 3, "f32"),
+    (64, 2, 1, 2, 2, "f32"),
+    (64, 9, 17, 1, 5, "f32"),
+    (64, 8, 16, 1, 6, "f32"),
+    (2, 21, 34, 3, 8, "f32"),
+    (5, 13, 40, 2, 9, "f32"),
+    (16, 40, 33, 4, 6, "f32"),
+    (17, 24, 19, 3, 4, "f32"),
+    (32, 50, 70, 5, 10, "f32"),
+    (33, 25, 31, 2, 5, "f32"),
+    (65, 19, 23, 2, 4, "f32"),
+    (96, 17, 40, 3, 6, "f32"),
+    (128, 22, 35, 2, 8, "f32"),
+    (200, 9, 20, 2, 3, "f32"),
+    (256, 12, 17, 1, 2, "f32"),
+    (64, 33, 47, 3, 10, "f16"),
+    (64, 33, 47, 3, 9, "bf16"),
+    (64, 30, 40, 2, 6, "f16"),
+    (128, 20, 25, 4, 8, "f16"),
+    (32, 31, 29, 3, 7, "bf16"),
+]
+
+
+@pytest.mark.parametrize("L,H,W,levels,K,fmt", CASES)
+def test_pairs_equal_single_half_sweeps(dev, L, H, W, levels, K, fmt):
+    import paper_1902_09733_amd as bp
+    print(f"pairs vs single: L={L} {W}x{H} levels={levels} K={K} {fmt}", flush=True)
+    rng = np.random.default_rng(L * 1000 + H * 10 + W + K)
+    cost = torch.from_numpy(rng.uniform(0.0, 20.0, size=(L, H, W)).astype(np.float32)).to(dev)
+    a, b = both(bp, cost, levels, K, fmt)
+    assert torch.equal(a["disp"], b["disp"])
+    assert torch.equal(a["msgs"], b["msgs"])
+
+
+@pytest.mark.parametrize("L,H,W,levels,K", [(64, 47, 61, 3, 10), (32, 20, 29, 2, 7), (96, 13, 22, 2, 6)])
+def test_pairs_equal_oracle_integer(dev, L, H, W, levels, K):
+    import paper_1902_09733_amd as bp
+    print(f"pairs vs oracle: L={L} {W}x{H} levels={levels} K={K}", flush=True)
+    rng = np.random.default_rng(L + H + W)
+    c = rng.integers(0, 21, size=(L, H, W)).astype(np.float64)
+    o = oracle.run(c, levels, K, 10.0, 2.0, want_msgs=True)
+    g = bp.run(torch.from_numpy(c.astype(np.float32)).to(dev), bp.BPParams(levels=levels, iters=K), want_msgs=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(g["disp"].cpu().numpy(), o["disp"])
+    assert np.array_equal(g["msgs"].cpu().numpy().astype(np.float64), o["msgs"])
