@@ -193,7 +193,7 @@ def main():
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": stored_traffic() if args.msg_dtype == "f32" else None,
+        "traffic": stored_traffic("k_iter_pm2" if fused else "k_iter_pm") if args.msg_dtype == "f32" else None,
         "kernel": (f"k_iter_pm2 level-0 fused pair of checkerboard half-sweeps ({w}x{h}x{L}, {args.msg_dtype} "
                    "messages)") if fused else
                   f"k_iter_pm level-0 checkerboard half-sweep ({w}x{h}x{L}, {args.msg_dtype} messages)",
@@ -381,6 +381,48 @@ def form_batch(args):
         res[f"batched_{fmt}_bad_pixel_vs_plain_f32"] = bad / npx
     res["speedup_batched_f16_vs_plain_f32"] = round(res["batched_f16_pairs_per_s"] / res["plain_f32_pairs_per_s"], 3)
     res["speedup_batched_f32_vs_plain_f32"] = round(res["batched_f32_pairs_per_s"] / res["plain_f32_pairs_per_s"], 3)
+
+    # The autotuner over the batch's shapes: for each label count the
+    # smallest, median and largest pair, both storage formats; the table is
+    # loaded into the library and the batched form timed again with it.
+    import tempfile
+
+    from paper_1902_09733_amd import _abi, tune
+    by_L = {}
+    for p in pairs:
+        by_L.setdefault(p["num_labels"], []).append((p["width"] * p["height"], p["width"], p["height"]))
+    reps = []
+    for L in sorted(by_L):
+        sizes = sorted(by_L[L])
+        for q in sorted({0, len(sizes) // 2, len(sizes) - 1}):
+            reps.append((sizes[q][1], sizes[q][2], L))
+    lines, picks = ["# width height labels fmt levels pm_from variant us"], {}
+    for fmt in ("f32", "f16"):
+        ln, pk = tune.table_lines(reps, fmt, wl["levels"], wl["iters"], dev)
+        lines += ln[1:]
+        picks[fmt] = [list(x) for x in pk]
+    with tempfile.NamedTemporaryFile("w", suffix=".txt", delete=False) as fh:
+        fh.write("\n".join(lines) + "\n")
+        table = fh.name
+    lib = _abi.lib()
+    _abi.check("bp_load_tune_table", lib.bp_load_tune_table(table.encode()))
+    try:
+        for fmt in ("f32", "f16"):
+            outs = make_outs()
+            pp = bp.BPParams(levels=wl["levels"], iters=wl["iters"], lam=wl["lam"], tau=wl["tau"], msg_dtype=fmt)
+            ws = bp.Workspace()
+
+            def tuned():
+                bp.run(srcs, pp, workspace=ws, outputs=outs)
+            tuned()
+            torch.cuda.synchronize()
+            t = _time(_graph(tuned).replay, 5)
+            res[f"tuned_batched_{fmt}_pairs_per_s"] = round(48 / t, 2)
+    finally:
+        lib.bp_load_tune_table(None)
+        os.unlink(table)
+    res["tune_shapes"] = [list(r) for r in reps]
+    res["tune_picks"] = picks   # (W, H, L, levels, pm_from, variant (0 = fused pairs), us)
     return {"form": "batched", "workload": "batch48_mixed", "updates_per_batch": updates, **res}
 
 
@@ -455,31 +497,38 @@ def form_adjoint(args):
 
 
 COPY_BYTES = 256 << 20
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_iter_pm_aerial676x380_L64_f32.txt")
-TRAFFIC_SOURCES = ["paper_1902_09733_amd/csrc/bp_iter_pm.hip", "paper_1902_09733_amd/csrc/bp_device.h",
-                   "paper_1902_09733_amd/csrc/bp_internal.h"]
+# Counter-measured HBM traffic of the dominant level-0 kernel, per kernel:
+# the committed file and the sources whose digest it was taken with.
+TRAFFIC = {
+    "k_iter_pm2": ("traffic_k_iter_pm2_aerial676x380_L64_f32.txt",
+                   ["paper_1902_09733_amd/csrc/bp_iter_pm2.hip", "paper_1902_09733_amd/csrc/bp_pm_core.h",
+                    "paper_1902_09733_amd/csrc/bp_device.h", "paper_1902_09733_amd/csrc/bp_internal.h"]),
+    "k_iter_pm": ("traffic_k_iter_pm_aerial676x380_L64_f32.txt",
+                  ["paper_1902_09733_amd/csrc/bp_iter_pm.hip", "paper_1902_09733_amd/csrc/bp_pm_core.h",
+                   "paper_1902_09733_amd/csrc/bp_device.h", "paper_1902_09733_amd/csrc/bp_internal.h"]),
+}
 
 
-def sources_digest():
+def sources_digest(kernel="k_iter_pm2"):
     import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in TRAFFIC[kernel][1]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def stored_traffic():
-    """HBM bytes per level-0 half-sweep launch from the committed counter
+def stored_traffic(kernel="k_iter_pm2"):
+    """HBM bytes per level-0 launch of `kernel` from the committed counter
     passes (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading
     for a plain copy of known size), or None when the kernel sources changed
     since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(os.path.join(ROOT, "profiles", TRAFFIC[kernel][0])) as fh:
             kv = dict(line.split(None, 1) for line in fh if line.strip() and not line.startswith("#"))
     except OSError:
         return None
-    if kv.get("sources_sha256", "").strip() != sources_digest():
+    if kv.get("sources_sha256", "").strip() != sources_digest(kernel):
         return None
     return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
 
@@ -657,7 +706,7 @@ def form_counters(args):
         dst.copy_(src)
     torch.cuda.synchronize()
     return {"form": "counters", "copy_bytes": COPY_BYTES, "pair_runs": 3, "single_half_sweep_runs": 3, "copies": 3,
-            "sources_sha256": sources_digest()}
+            "sources_sha256": {k: sources_digest(k) for k in TRAFFIC}}
 
 
 def form_ceiling(args):

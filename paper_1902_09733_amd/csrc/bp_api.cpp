@@ -358,24 +358,153 @@ bool batched(const Plan *plans, int32_t count, const bp_params &p)
     return true;
 }
 
-// Table entries of the batched form: per level, three kinds of half-sweep
-// (t = 0, odd t, even t >= 2), per problem.
-// Launch entries of the batched form: (level, kind) x problems for the kinds
-// {t = 0, odd t, even t > 0}, plus the finest level's last half-sweep with its
-// fused readout.
-size_t batch_table_bytes(int32_t count, int levels)
+// The batched form runs fused pairs at every level when the library picks
+// the kernels, K is even (no single half-sweeps anywhere) and every level
+// whose parent copy cannot be fused into its first pair (16-bit levels under
+// the FP32 coarsest level) has an even number of pairs, so that the first
+// pair reads the level's own state and writes the second buffer.
+bool batch_pairs(const Plan *plans, int32_t count, const bp_params &p)
 {
+    const int K = p.iters_per_level;
+    if (p.variant != 0 || K < 2 || (K & 1) || p.checkpoint_every > 0) return false;
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i].pairs) return false;
+        for (int l = 0; l < plans[i].levels; ++l) {
+            if (!level_pairs(plans[i], l, K)) return false;
+            if (l < plans[i].levels - 1 && plans[i].lv[l].fmt != plans[i].lv[l + 1].fmt && ((K / 2) & 1)) return false;
+        }
+    }
+    return true;
+}
+
+// Launch entries of the batched form.  One-half-sweep launches: (level, kind)
+// x problems for the kinds {t = 0, odd t, even t > 0}, plus the finest level's
+// last half-sweep with its fused readout.  Fused pairs: (level, pair) x
+// problems.
+size_t batch_table_bytes(int32_t count, int levels, int K, bool pairs)
+{
+    if (pairs) return align_up((size_t)levels * (K / 2) * count * sizeof(PairEntry));
     return align_up(((size_t)levels * 3 + 1) * count * sizeof(BatchEntry));
 }
 
-// Plans of a bp_run call: the batched form when it applies, otherwise each
-// problem on its own with fused pairs of half-sweeps where they apply.
-bool plan_run(const bp_problem *probs, int32_t count, const bp_params *p, Plan *plans, size_t *total, bool *batch)
+// Plans of a bp_run call: the batched form when it applies (with fused pairs
+// when batch_pairs allows them), otherwise each problem on its own with fused
+// pairs of half-sweeps where they apply.  *table: bytes of the batched form's
+// launch table (0 when not batched).
+bool plan_run(const bp_problem *probs, int32_t count, const bp_params *p, Plan *plans, size_t *total, bool *batch,
+              size_t *table = nullptr)
 {
+    if (table) *table = 0;
     if (!plan_all(probs, count, p, plans, total)) return false;
     *batch = batched(plans, count, *p);
-    if (*batch) return true;
-    return plan_all(probs, count, p, plans, total, true);
+    if (!plan_all(probs, count, p, plans, total, true)) return false;
+    if (*batch) {
+        const bool pairs = batch_pairs(plans, count, *p);
+        if (!pairs && !plan_all(probs, count, p, plans, total)) return false;
+        if (table) *table = batch_table_bytes(count, p->levels, p->iters_per_level, pairs);
+    }
+    return true;
+}
+
+// Readout of the colours the last half-sweep did not cover, and the message
+// export, problem by problem.
+bp_status finish_batched(const bp_problem *probs, int32_t count, const Plan *plans, const bp_params &p,
+                         const bool *fuse, uint8_t *ws, hipStream_t s)
+{
+    bp_status st = BP_OK;
+    const int K = p.iters_per_level;
+    for (int i = 0; i < count && st == BP_OK; ++i) {
+        const bp_problem &q = probs[i];
+        if (q.disparity || q.soft_disparity) {
+            const int mask = fuse[i] ? (1 << (K & 1)) : 3;
+            st = launch_readout(plans[i], mask, q.disparity, q.soft_disparity, p.temperature, ws, s);
+        }
+        if (st == BP_OK && q.messages_out) st = launch_export(plans[i], q.messages_out, ws, s);
+    }
+    return st;
+}
+
+// The batched form with fused pairs (batch_pairs): per level, pair and lane
+// split one launch over all problems of that split.  Buffers alternate as in
+// run_one, so every level's last pair writes the level's own state.
+bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *plans, const bp_params &p,
+                            uint8_t *ws, size_t table_off, const bool *fuse, hipStream_t s)
+{
+    const int n = p.levels, K = p.iters_per_level, np = K / 2;
+    int cls_S[32], cls_R[32], ncls = 0;
+    int *cls_of = new int[count];
+    for (int i = 0; i < count; ++i) {
+        int S, R;
+        pm_split(plans[i].L, &S, &R);
+        int c = 0;
+        while (c < ncls && !(cls_S[c] == S && cls_R[c] == R)) ++c;
+        if (c == ncls) {
+            cls_S[c] = S;
+            cls_R[c] = R;
+            ++ncls;
+        }
+        cls_of[i] = c;
+    }
+    const size_t nslot = (size_t)n * np * ncls;
+    PairEntry *host = new PairEntry[(size_t)n * np * count];
+    PairEntry *dev = (PairEntry *)(ws + table_off);
+    int *start = new int[nslot], *num = new int[nslot], *blocks = new int[nslot];
+    size_t *lds = new size_t[nslot];
+    bool *ro = new bool[nslot];
+    int e = 0;
+    for (int l = 0; l < n; ++l)
+        for (int q = 0; q < np; ++q)
+            for (int c = 0; c < ncls; ++c) {
+                const size_t slot = ((size_t)l * np + q) * ncls + c;
+                start[slot] = e;
+                num[slot] = 0;
+                lds[slot] = 0;
+                ro[slot] = false;
+                int b0 = 0;
+                for (int i = 0; i < count; ++i) {
+                    if (cls_of[i] != c) continue;
+                    const Plan &pl = plans[i];
+                    const bool fusable = l == n - 1 || pl.lv[l].fmt == pl.lv[l + 1].fmt;
+                    const size_t own = pl.lv[l].msg_off, other = pl.y_off;
+                    const size_t dst = ((np - 1 - q) & 1) ? other : own;
+                    const size_t src = q == 0 ? own : (((np - q) & 1) ? other : own);
+                    const int kind = q > 0 ? PAIR_SRC_OWN
+                                           : (l == n - 1 ? PAIR_SRC_ZERO : (fusable ? PAIR_SRC_PARENT : PAIR_SRC_OWN));
+                    const bool ends = q == np - 1;
+                    int32_t *disp = (l == 0 && ends && fuse[i]) ? probs[i].disparity : nullptr;
+                    PairEntry &pe = host[e++];
+                    pe.a = make_pair_args(pl, l, kind, src, dst, ends, p.lambda, p.tau, disp, ws);
+                    pe.block0 = b0;
+                    b0 += pair_blocks(pe.a);
+                    const size_t lb = pair_lds_bytes(pe.a.tx, pe.a.ty, (int)pe.a.lp, fmt_bytes(pl.lv[l].fmt));
+                    if (lb > lds[slot]) lds[slot] = lb;
+                    if (disp) ro[slot] = true;
+                    ++num[slot];
+                }
+                blocks[slot] = b0;
+            }
+    bp_status st = launch_write_pair_entries(dev, host, e, s);
+    for (int l = n - 1; l >= 0 && st == BP_OK; --l) {
+        if (l < n - 1)
+            for (int i = 0; i < count && st == BP_OK; ++i)
+                if (plans[i].lv[l].fmt != plans[i].lv[l + 1].fmt) st = launch_parent_copy(plans[i], l, ws, s);
+        const int fmt = plans[0].lv[l].fmt;   // every problem has the same levels
+        for (int q = 0; q < np && st == BP_OK; ++q)
+            for (int c = 0; c < ncls && st == BP_OK; ++c) {
+                const size_t slot = ((size_t)l * np + q) * ncls + c;
+                if (num[slot] == 0) continue;
+                st = launch_iteration_pair_batch(dev + start[slot], num[slot], blocks[slot], lds[slot], fmt, cls_S[c],
+                                                 cls_R[c], ro[slot], s);
+            }
+    }
+    delete[] host;
+    delete[] start;
+    delete[] num;
+    delete[] blocks;
+    delete[] lds;
+    delete[] ro;
+    delete[] cls_of;
+    return st;
 }
 
 bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans, const bp_params &p, uint8_t *ws,
@@ -390,6 +519,14 @@ bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans,
                                 : launch_pair_cost(*probs[i].pair, plans[i], ws, s, &done)) != BP_OK)
             return st;
         if ((st = launch_pyramid(plans[i], done, ws, s)) != BP_OK) return st;
+    }
+    if (batch_pairs(plans, count, p)) {
+        bool *fz = new bool[count];
+        for (int i = 0; i < count; ++i) fz[i] = probs[i].disparity && !probs[i].soft_disparity && K >= 1;
+        st = run_batched_pairs(probs, count, plans, p, ws, table_off, fz, s);
+        if (st == BP_OK) st = finish_batched(probs, count, plans, p, fz, ws, s);
+        delete[] fz;
+        return st;
     }
     // Problems grouped by lane split (classes of one launch each).
     int cls_S[32], cls_R[32], ncls = 0;
@@ -464,14 +601,7 @@ bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans,
             }
         }
     }
-    for (int i = 0; i < count && st == BP_OK; ++i) {
-        const bp_problem &q = probs[i];
-        if (q.disparity || q.soft_disparity) {
-            const int mask = fuse[i] ? (1 << (K & 1)) : 3;
-            st = launch_readout(plans[i], mask, q.disparity, q.soft_disparity, p.temperature, ws, s);
-        }
-        if (st == BP_OK && q.messages_out) st = launch_export(plans[i], q.messages_out, ws, s);
-    }
+    if (st == BP_OK) st = finish_batched(probs, count, plans, p, fuse, ws, s);
     delete[] fuse;
     delete[] host;
     delete[] start;
@@ -511,9 +641,9 @@ bp_status run_checked(const bp_problem *probs, int32_t count, const bp_params *p
     if (ck && !differentiable(*params)) return BP_ERR_UNSUPPORTED;
     if (ck && (!checkpoints || ((uintptr_t)checkpoints % kAlign) != 0)) return BP_ERR_INVALID_ARGUMENT;
     Plan *plans = new Plan[count];
-    size_t total = 0;
+    size_t total = 0, table = 0;
     bool batch = false;
-    if (!plan_run(probs, count, params, plans, &total, &batch)) {
+    if (!plan_run(probs, count, params, plans, &total, &batch, &table)) {
         delete[] plans;
         return BP_ERR_UNSUPPORTED;
     }
@@ -522,7 +652,7 @@ bp_status run_checked(const bp_problem *probs, int32_t count, const bp_params *p
         for (int i = 0; i < count; ++i)
             ck_total += checkpoint_bytes_of(plans[i], params->iters_per_level, params->checkpoint_every);
     const size_t table_off = total;
-    if (batch) total += batch_table_bytes(count, params->levels);
+    total += table;
     if (ws_bytes < total || ckpt_bytes < ck_total) {
         delete[] plans;
         return BP_ERR_WORKSPACE_TOO_SMALL;
@@ -600,12 +730,11 @@ size_t bp_workspace_size(const bp_problem *probs, int32_t count, const bp_params
             (!probs[i].cost && !valid_pair(probs[i].pair, probs[i].width, probs[i].height)))
             return 0;
     Plan *plans = new Plan[count];
-    size_t total = 0;
+    size_t total = 0, table = 0;
     bool batch = false;
-    const bool ok = plan_run(probs, count, params, plans, &total, &batch);
-    if (ok && batch) total += batch_table_bytes(count, params->levels);
+    const bool ok = plan_run(probs, count, params, plans, &total, &batch, &table);
     delete[] plans;
-    return ok ? total : 0;
+    return ok ? total + table : 0;
 }
 
 size_t bp_checkpoint_size(const bp_problem *probs, int32_t count, const bp_params *params)

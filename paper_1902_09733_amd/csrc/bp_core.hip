@@ -429,8 +429,8 @@ bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lamb
     return dispatch_iter_lm(a, v.fmt, iteration_lanes(p.L, variant), disp != nullptr, s);
 }
 
-bp_status launch_iteration_pair(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
-                                float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s)
+PairArgs make_pair_args(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
+                        float lambda, float tau, int32_t *disp, uint8_t *ws)
 {
     const Level &v = p.lv[l];
     PairArgs a;
@@ -467,13 +467,20 @@ bp_status launch_iteration_pair(const Plan &p, int l, int src_kind, size_t src_o
     a.L = p.L;
     a.lambda = lambda;
     a.lt = lambda * tau;
-    pair_tile(v.lp, v.w, v.h, &a.tx, &a.ty);
+    pair_tile(v.lp, fmt_bytes(v.fmt), v.w, v.h, &a.tx, &a.ty);
     a.tiles_x = (v.w + a.tx - 1) / a.tx;
     a.ntiles = a.tiles_x * ((v.h + a.ty - 1) / a.ty);
     a.per_xcd = (a.ntiles + 7) / 8;
+    return a;
+}
+
+bp_status launch_iteration_pair(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
+                                float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s)
+{
+    const PairArgs a = make_pair_args(p, l, src_kind, src_off, dst_off, write_c1, lambda, tau, disp, ws);
     int S, R;
     pm_split(p.L, &S, &R);
-    return dispatch_iter_pm2(a, v.fmt, S, R, disp != nullptr, s);
+    return dispatch_iter_pm2(a, p.lv[l].fmt, S, R, disp != nullptr, s);
 }
 
 bp_status launch_iteration_from(const Plan &p, int t, const uint8_t *src, float lambda, float tau, int variant,

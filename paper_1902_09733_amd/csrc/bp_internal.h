@@ -120,6 +120,7 @@ bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lamb
 enum { PAIR_SRC_OWN = 0, PAIR_SRC_PARENT = 1, PAIR_SRC_ZERO = 2 };
 bp_status launch_iteration_pair(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
                                 float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s);
+
 // Half-sweep t of the finest level reading its incoming messages from `src`
 // (a saved state in the level's layout) and writing the receivers' slots
 // into the level's own message buffer.
@@ -246,11 +247,29 @@ struct PairArgs {
     int tx, ty;            // tile (tx even)
     int tiles_x, ntiles, per_xcd;
 };
-void pair_tile(int lp, int w, int h, int *tx, int *ty);
-size_t pair_lds_bytes(int tx, int ty, int lp);
+void pair_tile(int lp, int mb, int w, int h, int *tx, int *ty);
+size_t pair_lds_bytes(int tx, int ty, int lp, int mb);
 bp_status dispatch_iter_pm2(const PairArgs &a, int fmt, int S, int R, bool ro, hipStream_t s);
 // Whether the fused pair supports a level's lane split.
 bool pair_supported(int S, int R);
+PairArgs make_pair_args(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
+                        float lambda, float tau, int32_t *disp, uint8_t *ws);
+// Batched fused pairs: one launch over the problems of a lane split; entries
+// hold each problem's arguments and its first block (a multiple of 8).
+struct PairEntry {
+    PairArgs a;
+    int block0;
+    int pad[3];
+};
+constexpr int kPairChunk = 12;
+struct PairChunk {
+    PairEntry e[kPairChunk];
+    int n;
+};
+int pair_blocks(const PairArgs &a);
+bp_status launch_write_pair_entries(PairEntry *dst, const PairEntry *src, int n, hipStream_t s);
+bp_status launch_iteration_pair_batch(const PairEntry *tab, int n, int blocks, size_t lds, int fmt, int S, int R,
+                                      bool ro, hipStream_t s);
 
 // Pixel-major kernel variants (1 default split; 2 half the lanes per message,
 // twice the labels per lane; 3 and 4 the same with each lane group reading

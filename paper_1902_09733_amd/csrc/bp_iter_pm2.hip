@@ -46,13 +46,12 @@ namespace bpk {
 // one-half-sweep kernel's variant 1).  U pixels per lane group are loaded
 // before any is computed, to keep more rows in flight per wave.
 template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U>
-__global__ void __launch_bounds__(NT) k_iter_pm2(const PairArgs a)
+__device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
 {
-    extern __shared__ float lds[];       // [tile colour-1 pixel][slot][lp]
+    // lds: [tile colour-1 pixel][slot][lp] in the storage format
     constexpr int PPB = NT / SEG;        // lane groups (pixels at a time) per block
-    // Tile of this block: blocks b, b + 8, ... run on one XCD of the eight and
+    // Tile of block b: blocks b, b + 8, ... run on one XCD of the eight and
     // take a contiguous run of tiles, so a tile's ring comes from its own L2.
-    const int b = (int)blockIdx.x;
     const int tile = (b & 7) * a.per_xcd + (b >> 3);
     if (tile >= a.ntiles) return;
     const int TX = a.tx, TY = a.ty, HX = TX >> 1;
@@ -119,13 +118,14 @@ __global__ void __launch_bounds__(NT) k_iter_pm2(const PairArgs a)
                 pm_h<R>(c[u], m[u], k, h);
                 pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, out);
                 const int slot = (ny - ty0) * HX + ((nx - tx0) >> 1);
-                float *row = lds + ((uint32_t)slot * 4u + (uint32_t)(k ^ 1)) * lp + f0;
+                uint8_t *row = lds + (((uint32_t)slot * 4u + (uint32_t)(k ^ 1)) * lp + f0) * S::bytes;
                 if constexpr (S::bytes == 4) {
 #pragma unroll
-                    for (int q = 0; q < R; ++q) row[q] = out[q];
+                    for (int q = 0; q < R; ++q) ((float *)row)[q] = out[q];
                 } else {
 #pragma unroll
-                    for (int q = 0; q < R; ++q) row[q] = S::decode(S::encode(out[q]));
+                    for (int q = 0; q < R / 2; ++q)
+                        ((uint32_t *)row)[q] = (uint32_t)S::encode(out[2 * q]) | ((uint32_t)S::encode(out[2 * q + 1]) << 16);
                 }
                 if (a.write_c1) {
                     const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
@@ -161,12 +161,23 @@ __global__ void __launch_bounds__(NT) k_iter_pm2(const PairArgs a)
             const int i = i0 + u * PPB, x = xs[u], y = ys[u];
             // Slots from outside the grid hold zero (never written above).
             const bool has[4] = {x > 0, x < a.w - 1, y > 0, y < a.h - 1};
-            const float *row = lds + (uint32_t)i * 4u * lp + f0;
+            const uint8_t *row = lds + ((uint32_t)i * 4u * lp + f0) * S::bytes;
             float m[4][R];
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
+                if constexpr (S::bytes == 4) {
+                    const float *rk = (const float *)row + kk * lp;
 #pragma unroll
-                for (int q = 0; q < R; ++q) m[kk][q] = has[kk] ? row[kk * lp + q] : 0.0f;
+                    for (int q = 0; q < R; ++q) m[kk][q] = has[kk] ? rk[q] : 0.0f;
+                } else {
+                    const uint32_t *rk = (const uint32_t *)(row + (size_t)kk * lp * S::bytes);
+#pragma unroll
+                    for (int q = 0; q < R / 2; ++q) {
+                        const uint32_t w = has[kk] ? rk[q] : 0u;
+                        m[kk][2 * q] = S::decode((uint16_t)(w & 0xffffu));
+                        m[kk][2 * q + 1] = S::decode((uint16_t)(w >> 16));
+                    }
+                }
             }
             if constexpr (RO) {
                 float bel[R];
@@ -188,13 +199,60 @@ __global__ void __launch_bounds__(NT) k_iter_pm2(const PairArgs a)
     }
 }
 
-// Tile of a fused pair at a w x h level: the largest of a few shapes whose
-// colour-1 rows fit 64 KiB of LDS (TX x TY / 2 pixels x 4 rows x lp floats),
-// halved (rows first) while the level has fewer than 512 tiles, so that small
-// levels still spread over every compute unit (down to 4 x 4).
-void pair_tile(int lp, int w, int h, int *tx, int *ty)
+template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U>
+__global__ void __launch_bounds__(NT) k_iter_pm2(const PairArgs a)
 {
-    const int px = 65536 / (16 * lp);   // colour-1 pixels that fit
+    extern __shared__ uint8_t lds[];
+    pm2_tile<SEG, R, S, EXACT, RO, NT, U>(a, (int)blockIdx.x, lds);
+}
+
+// Batched fused pair: block b belongs to the last table entry whose first
+// block is <= b; every entry's first block is a multiple of 8, so the XCD
+// grouping of tiles holds within each problem.
+template <int SEG, int R, typename S, bool RO, int NT, int U>
+__global__ void __launch_bounds__(NT) k_iter_pm2_batch(const PairEntry *__restrict__ tab, int n)
+{
+    extern __shared__ uint8_t lds[];
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].block0 <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const PairArgs a = tab[lo].a;
+    pm2_tile<SEG, R, S, false, RO, NT, U>(a, (int)blockIdx.x - tab[lo].block0, lds);
+}
+
+// Table of batch entries written from kernel arguments (capture-safe).
+__global__ void k_write_pair_entries(PairEntry *__restrict__ dst, PairChunk c)
+{
+    const int i = threadIdx.x;
+    if (i < c.n) dst[i] = c.e[i];
+}
+
+bp_status launch_write_pair_entries(PairEntry *dst, const PairEntry *src, int n, hipStream_t st)
+{
+    for (int i = 0; i < n; i += kPairChunk) {
+        PairChunk c;
+        c.n = n - i < kPairChunk ? n - i : kPairChunk;
+        for (int k = 0; k < c.n; ++k) c.e[k] = src[i + k];
+        k_write_pair_entries<<<1, 64, 0, st>>>(dst + i, c);
+        const bp_status s = launch_status();
+        if (s != BP_OK) return s;
+    }
+    return BP_OK;
+}
+
+int pair_blocks(const PairArgs &a) { return 8 * a.per_xcd; }
+
+// Tile of a fused pair at a w x h level: the largest of a few shapes whose
+// colour-1 rows fit 64 KiB of LDS (TX x TY / 2 pixels x 4 rows x lp values of
+// mb bytes, the storage format), halved (rows first) while the level has
+// fewer than 512 tiles, so that small levels still spread over every compute
+// unit (down to 4 x 4).
+void pair_tile(int lp, int mb, int w, int h, int *tx, int *ty)
+{
+    const int px = 65536 / (4 * lp * mb);   // colour-1 pixels that fit
     if (px >= 256) { *tx = 32; *ty = 16; }
     else if (px >= 128) { *tx = 16; *ty = 16; }
     else if (px >= 64) { *tx = 16; *ty = 8; }
@@ -207,16 +265,42 @@ void pair_tile(int lp, int w, int h, int *tx, int *ty)
     }
 }
 
-size_t pair_lds_bytes(int tx, int ty, int lp) { return (size_t)tx * ty / 2 * 4 * lp * sizeof(float); }
+size_t pair_lds_bytes(int tx, int ty, int lp, int mb) { return (size_t)tx * ty / 2 * 4 * lp * mb; }
+
+constexpr int kPairThreads = 512;
 
 template <int SEG, int R, typename S, bool EXACT, bool RO>
 static bp_status launch_pm2(const PairArgs &a, size_t lds, hipStream_t st)
 {
-    constexpr int NT = 512;
-    constexpr int U = 1;
-    const unsigned grid = (unsigned)(8 * a.per_xcd);
-    k_iter_pm2<SEG, R, S, EXACT, RO, NT, U><<<grid, NT, lds, st>>>(a);
+    const unsigned grid = (unsigned)pair_blocks(a);
+    k_iter_pm2<SEG, R, S, EXACT, RO, kPairThreads, 1><<<grid, kPairThreads, lds, st>>>(a);
     return launch_status();
+}
+
+template <typename S>
+static bp_status dispatch_pm2_batch(const PairEntry *tab, int n, int blocks, size_t lds, int SEGV, int R, bool ro,
+                                    hipStream_t st)
+{
+#define BP_PM2B(SV, RV)                                                                                        \
+    if (SEGV == SV && R == RV) {                                                                               \
+        if (ro) k_iter_pm2_batch<SV, RV, S, true, kPairThreads, 1><<<blocks, kPairThreads, lds, st>>>(tab, n); \
+        else k_iter_pm2_batch<SV, RV, S, false, kPairThreads, 1><<<blocks, kPairThreads, lds, st>>>(tab, n);  \
+        return launch_status();                                                                                \
+    }
+    BP_PM2B(4, 4) BP_PM2B(8, 4) BP_PM2B(16, 4) BP_PM2B(16, 6) BP_PM2B(16, 8) BP_PM2B(16, 12) BP_PM2B(16, 16)
+#undef BP_PM2B
+    return BP_ERR_UNSUPPORTED;
+}
+
+bp_status launch_iteration_pair_batch(const PairEntry *tab, int n, int blocks, size_t lds, int fmt, int SEGV, int R,
+                                      bool ro, hipStream_t st)
+{
+    if (lds > 65536) return BP_ERR_UNSUPPORTED;
+    switch (fmt) {
+    case FMT_F16: return dispatch_pm2_batch<StoreF16>(tab, n, blocks, lds, SEGV, R, ro, st);
+    case FMT_BF16: return dispatch_pm2_batch<StoreBF16>(tab, n, blocks, lds, SEGV, R, ro, st);
+    default: return dispatch_pm2_batch<StoreF32>(tab, n, blocks, lds, SEGV, R, ro, st);
+    }
 }
 
 template <int SEG, int R, typename S>
@@ -245,7 +329,7 @@ bool pair_supported(int SEGV, int R)
 
 bp_status dispatch_iter_pm2(const PairArgs &a, int fmt, int SEGV, int R, bool ro, hipStream_t st)
 {
-    const size_t lds = pair_lds_bytes(a.tx, a.ty, (int)a.lp);
+    const size_t lds = pair_lds_bytes(a.tx, a.ty, (int)a.lp, fmt_bytes(fmt));
     if (lds > 65536 || (a.tx & 1) || a.tx <= 0 || a.ty <= 0) return BP_ERR_UNSUPPORTED;
     switch (fmt) {
     case FMT_F16: return dispatch_pm2<StoreF16>(a, lds, SEGV, R, ro, st);

@@ -7,7 +7,7 @@ stream around the half-sweep launches of each level, and writes the fastest
 to a text table:
 
     # width height labels fmt levels pm_from variant us
-    676 380 64 0 5 0 1 934.5
+    676 380 64 0 5 0 0 655.2
 
 libbpstereo reads the table named by the environment variable BP_TUNE_TABLE
 once, at its first bp_run / bp_workspace_size call, and uses the entry with
@@ -55,11 +55,28 @@ def time_candidate(cost, params: stereo.BPParams, reps: int = 3) -> float:
 
 
 def candidates(L: int, levels: int):
+    """(first pixel-major level, variant) pairs; variant 0 is the library's
+    own kernel choice (fused pairs of half-sweeps on pixel-major levels)."""
     lib = _abi.lib()
     nv = max(lib.bp_variant_count(L), 2)
     for pm_from in range(levels + 1):
-        for variant in range(1, nv + 1):
+        for variant in range(0, nv + 1):
             yield pm_from, variant
+
+
+def table_lines(shapes, fmt: str = "f32", levels: int = 5, iters: int = 10, device=None):
+    """Tune every (W, H, L) shape; returns the table's lines (header first)
+    and the picks as (W, H, L, levels, pm_from, variant, us)."""
+    lines = ["# width height labels fmt levels pm_from variant us"]
+    picks = []
+    for (W, H, L) in shapes:
+        lv = max(1, min(levels, int(math.log2(max(2, min(W, H))))))
+        best, _ = tune_shape(W, H, L, fmt, lv, iters, device)
+        if best is None:
+            continue
+        lines.append(f"{W} {H} {L} {stereo.MSG_DTYPES[fmt]} {lv} {best[0]} {best[1]} {best[2]:.1f}")
+        picks.append((W, H, L, lv, best[0], best[1], round(best[2], 1)))
+    return lines, picks
 
 
 def tune_shape(W: int, H: int, L: int, fmt: str = "f32", levels: int = 5, iters: int = 10, device=None):
@@ -96,14 +113,8 @@ def main():
     ap.add_argument("--levels", type=int, default=5)
     ap.add_argument("--iters", type=int, default=10)
     a = ap.parse_args()
-    lines = ["# width height labels fmt levels pm_from variant us"]
-    for (W, H, L) in a.shapes:
-        levels = max(1, min(a.levels, int(math.log2(max(2, min(W, H))))))
-        best, _ = tune_shape(W, H, L, a.fmt, levels, a.iters)
-        if best is None:
-            continue
-        lines.append(f"{W} {H} {L} {stereo.MSG_DTYPES[a.fmt]} {levels} {best[0]} {best[1]} {best[2]:.1f}")
-        print(lines[-1], flush=True)
+    lines, _ = table_lines(a.shapes, a.fmt, a.levels, a.iters)
+    print("\n".join(lines[1:]), flush=True)
     with open(a.out, "w") as f:
         f.write("\n".join(lines) + "\n")
 

@@ -91,3 +91,26 @@ def test_pairs_equal_oracle_integer(dev, L, H, W, levels, K):
     torch.cuda.synchronize()
     assert np.array_equal(g["disp"].cpu().numpy(), o["disp"])
     assert np.array_equal(g["msgs"].cpu().numpy().astype(np.float64), o["msgs"])
+
+
+@pytest.mark.parametrize("fmt,K,levels", [("f32", 6, 3), ("f32", 2, 2), ("f16", 8, 4), ("bf16", 4, 3),
+                                          ("f32", 10, 5)])
+def test_batched_pairs_equal_single_problems(dev, fmt, K, levels):
+    """Batched fused pairs (one launch per level, pair and lane split over
+    every problem) against each problem run alone with one launch per
+    half-sweep: same labels and messages on real-valued costs, mixed sizes
+    and label counts (several lane splits, tiles shrunk on small levels)."""
+    import paper_1902_09733_amd as bp
+    shapes = [(64, 37, 53), (32, 20, 29), (96, 17, 40), (17, 11, 60), (128, 12, 21), (64, 9, 9)]
+    print(f"batched pairs: {fmt} K={K} levels={levels}", flush=True)
+    rng = np.random.default_rng(K * 10 + levels)
+    vols = [torch.from_numpy(rng.uniform(0.0, 20.0, size=sh).astype(np.float32)).to(dev) for sh in shapes]
+    p0 = bp.BPParams(levels=levels, iters=K, lam=7.3, tau=2.6, msg_dtype=fmt)
+    got = bp.run(vols, p0, want_msgs=True)
+    torch.cuda.synchronize()
+    p1 = bp.BPParams(levels=levels, iters=K, lam=7.3, tau=2.6, msg_dtype=fmt, variant=1)
+    for v, g in zip(vols, got):
+        ref = bp.run(v, p1, want_msgs=True)
+        torch.cuda.synchronize()
+        assert torch.equal(ref["disp"], g["disp"])
+        assert torch.equal(ref["msgs"], g["msgs"])
