@@ -335,7 +335,7 @@ typedef struct {
                                (4 + 8 mb) / 2 (the active half reads its cost and four incoming
                                rows and writes four outgoing ones); a fused pair 4 + 4 mb (both
                                colours' costs, colour 0's rows read and written), plus 2 mb
-                               for the pair that ends a level (colour 1's rows stored) */
+                               for a pair that ends a level and stores colour 1's rows */
 } bp_launch_record;
 
 /*

@@ -149,7 +149,10 @@ bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
         plans[i].variant = p->variant != 0 ? p->variant : tv != 0 ? tv : default_variant(q.num_labels, p->msg_dtype);
         // The pixel-major adjoint repeats the sums of the plain-load split.
         if (p->checkpoint_every > 0 && pm_from == 0) plans[i].variant = 1;
-        plans[i].pairs = allow_pairs && p->variant == 0 && tv == 0 && p->checkpoint_every == 0;
+        // With checkpoints every `every` half-sweeps the saved halves are
+        // colour 0's (after an odd half-sweep, i.e. after a pair) only when
+        // `every` is even.
+        plans[i].pairs = allow_pairs && p->variant == 0 && tv == 0 && p->checkpoint_every % 2 == 0;
         plans[i].y_off = 0;
         if (plans[i].pairs) {
             size_t yb = 0;
@@ -258,16 +261,35 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
                 --np;
             }
             size_t src_off = own;
+            // Checkpoints (finest level only): out-of-grid slots of every saved
+            // state are zeroed once, the pairs write the in-grid rows.
+            const size_t ck_state = pl.lv[0].msg_bytes;
+            const int ck_n = ckpt ? checkpoint_states(K, p.checkpoint_every) : 0;
+            if (ckpt && (st = launch_zero_borders(pl, ckpt, ck_state, ck_n, s)) != BP_OK) return st;
             for (int pi = 0; pi < np; ++pi, t0 += 2, ++launches) {
                 const size_t dst_off = ((np - 1 - pi) & 1) ? other : own;
                 int kind = PAIR_SRC_OWN;
                 if (t0 == 0) kind = l == n - 1 ? PAIR_SRC_ZERO : (first_src ? PAIR_SRC_PARENT : PAIR_SRC_OWN);
                 const bool ends = pi == np - 1 && (K & 1) == 0;
                 int32_t *ro = (l == 0 && ends && fuse_ro) ? q.disparity : nullptr;
+                // Colour 1's final rows are stored for the next level's parent
+                // copy, the readout, the export and the final checkpoint; at the
+                // finest level with the readout fused here and neither of the
+                // others, nothing reads them.
+                const bool store_c1 = ends && (l > 0 || !ro || q.messages_out || ckpt);
+                // State after the pair: saved (its colour-0 half) every
+                // `every` half-sweeps, and whole at the end.
+                uint8_t *ck = nullptr;
+                if (ckpt) {
+                    const int tn = t0 + 2;
+                    if (ends) ck = ckpt + (size_t)(ck_n - 1) * ck_state;
+                    else if (tn % p.checkpoint_every == 0 && tn < K)
+                        ck = ckpt + (size_t)(tn / p.checkpoint_every - 1) * ck_state;
+                }
                 const bool rec = prof && !prof->per_level && prof->n < prof->cap;
                 if (rec && hipEventRecord(prof->ev[prof->n][0], s) != hipSuccess) return BP_ERR_HIP;
-                if ((st = launch_iteration_pair(pl, l, kind, src_off, dst_off, ends, p.lambda, p.tau, ro, ws, s)) !=
-                    BP_OK)
+                if ((st = launch_iteration_pair(pl, l, kind, src_off, dst_off, store_c1, p.lambda, p.tau, ro, ws, s,
+                                                ck)) != BP_OK)
                     return st;
                 if (rec) {
                     if (hipEventRecord(prof->ev[prof->n][1], s) != hipSuccess) return BP_ERR_HIP;
@@ -279,9 +301,9 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
                     r.msg_bytes = fmt_bytes(pl.lv[l].fmt);
                     r.units = 2.0 * pl.lv[l].w * pl.lv[l].h * pl.L;
                     r.ms = 0.0f;
-                    r.bytes = pair_bytes(pl, l, ends);
+                    r.bytes = pair_bytes(pl, l, store_c1);
                 }
-                lbytes += pair_bytes(pl, l, ends);
+                lbytes += pair_bytes(pl, l, store_c1);
                 src_off = dst_off;
             }
         }
@@ -331,7 +353,8 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
             r.bytes = lbytes;
         }
     }
-    if (ckpt) {
+    // The final state, unless the last pair has written it.
+    if (ckpt && !(level_pairs(pl, 0, K) && (K & 1) == 0)) {
         const size_t sb = pl.lv[0].msg_bytes;
         if ((st = launch_copy(ws + pl.lv[0].msg_off, ckpt + (size_t)(checkpoint_states(K, p.checkpoint_every) - 1) * sb,
                               sb, s)) != BP_OK)
@@ -472,8 +495,11 @@ bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *
                                            : (l == n - 1 ? PAIR_SRC_ZERO : (fusable ? PAIR_SRC_PARENT : PAIR_SRC_OWN));
                     const bool ends = q == np - 1;
                     int32_t *disp = (l == 0 && ends && fuse[i]) ? probs[i].disparity : nullptr;
+                    // Colour 1's final rows: not needed at the finest level
+                    // when its readout is fused here and nothing is exported.
+                    const bool store_c1 = ends && (l > 0 || !disp || probs[i].messages_out);
                     PairEntry &pe = host[e++];
-                    pe.a = make_pair_args(pl, l, kind, src, dst, ends, p.lambda, p.tau, disp, ws);
+                    pe.a = make_pair_args(pl, l, kind, src, dst, store_c1, p.lambda, p.tau, disp, ws);
                     pe.block0 = b0;
                     b0 += pair_blocks(pe.a);
                     const size_t lb = pair_lds_bytes(pe.a.tx, pe.a.ty, (int)pe.a.lp, fmt_bytes(pl.lv[l].fmt));

@@ -304,6 +304,27 @@ bp_status launch_pyramid_level(const Plan &p, int l, uint8_t *ws, hipStream_t s)
 // grid (blocks, levels + 1): block (x, y) is init_msgs_block(x, y).
 __global__ void __launch_bounds__(256) k_init_msgs(InitArgs a) { init_msgs_block(a, blockIdx.x, blockIdx.y); }
 
+bp_status launch_zero_borders(const Plan &p, uint8_t *base, size_t stride, int n, hipStream_t s)
+{
+    for (int i0 = 0; i0 < n; i0 += kMaxLevels) {
+        const int m = n - i0 < kMaxLevels ? n - i0 : kMaxLevels;
+        InitArgs a;
+        for (int i = 0; i < m; ++i) {
+            a.msg[i] = base + (size_t)(i0 + i) * stride;
+            a.d[i] = desc(p.lv[0]);
+            a.bytes[i] = fmt_bytes(p.lv[0].fmt);
+        }
+        a.L = p.L;
+        a.levels = m;
+        a.coarsest_words = 0;
+        const int64_t per = (2 * (int64_t)p.lv[0].h + 2 * (int64_t)p.lv[0].w) * p.L;
+        k_init_msgs<<<dim3((unsigned)((per + 255) / 256), m), 256, 0, s>>>(a);
+        const bp_status st = launch_status();
+        if (st != BP_OK) return st;
+    }
+    return BP_OK;
+}
+
 bp_status launch_init_messages(const Plan &p, uint8_t *ws, hipStream_t s)
 {
     unsigned blocks;
@@ -430,7 +451,7 @@ bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lamb
 }
 
 PairArgs make_pair_args(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
-                        float lambda, float tau, int32_t *disp, uint8_t *ws)
+                        float lambda, float tau, int32_t *disp, uint8_t *ws, uint8_t *ck)
 {
     const Level &v = p.lv[l];
     PairArgs a;
@@ -471,13 +492,15 @@ PairArgs make_pair_args(const Plan &p, int l, int src_kind, size_t src_off, size
     a.tiles_x = (v.w + a.tx - 1) / a.tx;
     a.ntiles = a.tiles_x * ((v.h + a.ty - 1) / a.ty);
     a.per_xcd = (a.ntiles + 7) / 8;
+    a.ck = ck;
+    a.ck_bytes = ck ? (uint32_t)v.msg_bytes : 0u;
     return a;
 }
 
 bp_status launch_iteration_pair(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
-                                float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s)
+                                float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s, uint8_t *ck)
 {
-    const PairArgs a = make_pair_args(p, l, src_kind, src_off, dst_off, write_c1, lambda, tau, disp, ws);
+    const PairArgs a = make_pair_args(p, l, src_kind, src_off, dst_off, write_c1, lambda, tau, disp, ws, ck);
     int S, R;
     pm_split(p.L, &S, &R);
     return dispatch_iter_pm2(a, p.lv[l].fmt, S, R, disp != nullptr, s);

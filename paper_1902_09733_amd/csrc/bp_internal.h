@@ -119,7 +119,8 @@ bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lamb
 // labels (finest level).
 enum { PAIR_SRC_OWN = 0, PAIR_SRC_PARENT = 1, PAIR_SRC_ZERO = 2 };
 bp_status launch_iteration_pair(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
-                                float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s);
+                                float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s,
+                                uint8_t *ck = nullptr);
 
 // Half-sweep t of the finest level reading its incoming messages from `src`
 // (a saved state in the level's layout) and writing the receivers' slots
@@ -246,6 +247,9 @@ struct PairArgs {
     float lambda, lt;
     int tx, ty;            // tile (tx even)
     int tiles_x, ntiles, per_xcd;
+    uint8_t *ck;           // checkpoint state in the level's layout that also receives phase 2's rows
+                           // (and phase 1's when write_c1), or NULL
+    uint32_t ck_bytes;
 };
 void pair_tile(int lp, int mb, int w, int h, int *tx, int *ty);
 size_t pair_lds_bytes(int tx, int ty, int lp, int mb);
@@ -253,7 +257,11 @@ bp_status dispatch_iter_pm2(const PairArgs &a, int fmt, int S, int R, bool ro, h
 // Whether the fused pair supports a level's lane split.
 bool pair_supported(int S, int R);
 PairArgs make_pair_args(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
-                        float lambda, float tau, int32_t *disp, uint8_t *ws);
+                        float lambda, float tau, int32_t *disp, uint8_t *ws, uint8_t *ck = nullptr);
+// Zero the out-of-grid slots of `n` message states laid out like level 0 of
+// plan p, `stride` bytes apart from `base` (checkpoint states written by the
+// fused pairs, which store in-grid rows only).
+bp_status launch_zero_borders(const Plan &p, uint8_t *base, size_t stride, int n, hipStream_t s);
 // Batched fused pairs: one launch over the problems of a lane split; entries
 // hold each problem's arguments and its first block (a multiple of 8).
 struct PairEntry {

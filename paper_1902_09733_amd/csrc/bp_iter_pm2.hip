@@ -30,6 +30,10 @@
 // colour 1's incoming rows into the level's state, which the next level's
 // parent copy and the readout read.
 //
+// A forward run that saves states for the adjoint passes a checkpoint state
+// (`ck`, the level's layout): phase 2's rows, and phase 1's when they are
+// stored, are written there too, which replaces a copy of the state half.
+//
 // Per message the arithmetic is the one-half-sweep kernel's variant 1
 // (bp_pm_core.h: h summed in slot order, the same transform), so results
 // equal two launches of that kernel bit for bit.
@@ -63,6 +67,7 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, a.src_bytes);
     const __amdgpu_buffer_rsrc_t rm = make_rsrc(a.msg, a.msg_bytes);
     const __amdgpu_buffer_rsrc_t rd = make_rsrc(a.dst, a.dst_bytes);
+    const __amdgpu_buffer_rsrc_t rk = make_rsrc(a.ck, a.ck_bytes);
 
     // Phase 1: colour-0 pixels of [tx0 - 1, tx0 + TX] x [ty0 - 1, ty0 + TY]
     // without the corners, HX + 1 per row.
@@ -129,7 +134,9 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
                 }
                 if (a.write_c1) {
                     const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
-                    st_row<S, R>(rm, ((4u + (uint32_t)(k ^ 1)) * a.blk + dj * lp + (uint32_t)f0) * S::bytes, out);
+                    const uint32_t off = ((4u + (uint32_t)(k ^ 1)) * a.blk + dj * lp + (uint32_t)f0) * S::bytes;
+                    st_row<S, R>(rm, off, out);
+                    if (a.ck) st_row<S, R>(rk, off, out);
                 }
             }
         }
@@ -193,7 +200,9 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
                 pm_h<R>(c[u], m, k, h);
                 pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, out);
                 const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
-                st_row<S, R>(rd, ((uint32_t)(k ^ 1) * a.blk + dj * lp + (uint32_t)f0) * S::bytes, out);
+                const uint32_t off = ((uint32_t)(k ^ 1) * a.blk + dj * lp + (uint32_t)f0) * S::bytes;
+                st_row<S, R>(rd, off, out);
+                if (a.ck) st_row<S, R>(rk, off, out);
             }
         }
     }
