@@ -427,8 +427,9 @@ def form_batch(args):
 
 
 def form_precision(args):
-    """1352x760 RGB pair, 128 labels, 6 levels x 12 half-sweeps: FP32 / FP16 /
-    BF16 message storage, times and deviation from the FP32 GPU result, on an
+    """1352x760 RGB pair, 128 labels, 6 levels x 12 half-sweeps, data term from
+    the pair inside bp_run: FP32 / FP16 / BF16 message storage, times and
+    deviation from the FP32 GPU result, on an
     integer-valued parameter set (16-bit storage is exact there) and a
     real-valued one (unrounded channel mean, lambda 7.3, tau 2.6).  The
     comparison with the FP64 oracle is made by the GPU test suite."""
@@ -444,21 +445,30 @@ def form_precision(args):
     units = level_units(1352, 760, L, levels, K)
     out = {"form": "precision", "workload": "aerial1352x760_L128", "updates_per_pair": units}
     for pset, rgb_mode, lam, tau in (("int", 0, 10.0, 2.0), ("real", 1, 7.3, 2.6)):
-        cost = bp.cost_volume(left, right, L, 20.0, rgb_mode=rgb_mode)
+        # The pair route: bp_run computes the data term itself (the values
+        # bp_cost_volume gives) straight into its layout.
+        pair = bp.Pair(left, right, L, 20.0, rgb_mode=rgb_mode)
         ref = None
         for fmt in ("f32", "f16", "bf16"):
             p = bp.BPParams(levels=levels, iters=K, lam=lam, tau=tau, msg_dtype=fmt)
-            r = bp.run(cost, p, want_msgs=True)
+            r = bp.run(pair, p, want_msgs=True)
             ws = bp.Workspace()
             outs = [{"disp": torch.empty_like(r["disp"]), "soft": None, "msgs": None}]
-            t = _time(lambda: bp.run(cost, p, workspace=ws, outputs=outs), 10)
+            t = _time(lambda: bp.run(pair, p, workspace=ws, outputs=outs), 10)
             rec = {"bp_ms": round(t * 1e3, 3), "updates_per_s": round(units / t, 1)}
             if ref is None:
                 ref = r
             else:
                 rec["bad_pixel_vs_gpu_f32"] = float((torch.abs(r["disp"] - ref["disp"]) > 1).float().mean())
-                rec["max_msg_diff_vs_gpu_f32_over_lambda_tau"] = float(
-                    (r["msgs"] - ref["msgs"]).abs().max() / (lam * tau))
+                d = ((r["msgs"] - ref["msgs"]).abs() / (lam * tau)).flatten()
+                rec["max_msg_diff_vs_gpu_f32_over_lambda_tau"] = float(d.max())
+                # Where the maximum comes from: a near-tie of the message's
+                # minimiser resolved differently moves whole messages, so the
+                # distribution matters more than its maximum.
+                k = max(1, int(d.numel() * 1e-3))
+                rec["msg_diff_p99_9_over_lambda_tau"] = float(torch.topk(d, k).values[-1])
+                rec["msg_entries_off_by_over_1pct_lambda_tau"] = float((d > 1e-2).float().mean())
+                rec["msg_entries_off_by_over_half_lambda_tau"] = float((d > 0.5).float().mean())
             out[f"{pset}_{fmt}"] = rec
         del ref
     return out

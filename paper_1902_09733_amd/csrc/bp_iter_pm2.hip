@@ -254,19 +254,23 @@ bp_status launch_write_pair_entries(PairEntry *dst, const PairEntry *src, int n,
 
 int pair_blocks(const PairArgs &a) { return 8 * a.per_xcd; }
 
-// Tile of a fused pair at a w x h level: the largest of a few shapes whose
-// colour-1 rows fit 64 KiB of LDS (TX x TY / 2 pixels x 4 rows x lp values of
+// Tile of a fused pair at a w x h level: the squarest of a few shapes whose
+// colour-1 rows fit 32 KiB of LDS (TX x TY / 2 pixels x 4 rows x lp values of
 // mb bytes, the storage format), halved (rows first) while the level has
 // fewer than 512 tiles, so that small levels still spread over every compute
-// unit (down to 4 x 4).
+// unit (down to 4 x 4).  Measured at 64 labels in FP32 (level sums of the
+// benchmarked pair's pairs, finest / next level): 8 x 8 tiles (32 KiB, four
+// blocks per CU) 315 / 94 us, 16 x 4 313 / 97, 16 x 8 (64 KiB, two blocks)
+// 356 / 119, 8 x 4 344 / 94, 32 x 4 369 / 121; a ring of 1.56 colour-0 pixels
+// per tile colour-1 pixel costs less than the lower occupancy of larger tiles.
 void pair_tile(int lp, int mb, int w, int h, int *tx, int *ty)
 {
-    const int px = 65536 / (4 * lp * mb);   // colour-1 pixels that fit
-    if (px >= 256) { *tx = 32; *ty = 16; }
-    else if (px >= 128) { *tx = 16; *ty = 16; }
+    const int px = 32768 / (4 * lp * mb);   // colour-1 pixels that fit
+    if (px >= 128) { *tx = 16; *ty = 16; }
     else if (px >= 64) { *tx = 16; *ty = 8; }
     else if (px >= 32) { *tx = 8; *ty = 8; }
-    else { *tx = 8; *ty = 4; }
+    else if (px >= 16) { *tx = 8; *ty = 4; }
+    else { *tx = 4; *ty = 4; }
     auto tiles = [&](int a, int b) { return (int64_t)((w + a - 1) / a) * ((h + b - 1) / b); };
     while (tiles(*tx, *ty) < 512 && (*tx > 4 || *ty > 4)) {
         if (*ty >= *tx && *ty > 4) *ty /= 2;
