@@ -193,7 +193,7 @@ def main():
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": stored_traffic("k_iter_pm2" if fused else "k_iter_pm") if args.msg_dtype == "f32" else None,
+        "traffic": stored_traffic("k_iter_pm2") if fused and args.msg_dtype == "f32" else None,
         "kernel": (f"k_iter_pm2 level-0 fused pair of checkerboard half-sweeps ({w}x{h}x{L}, {args.msg_dtype} "
                    "messages)") if fused else
                   f"k_iter_pm level-0 checkerboard half-sweep ({w}x{h}x{L}, {args.msg_dtype} messages)",
@@ -513,9 +513,6 @@ TRAFFIC = {
     "k_iter_pm2": ("traffic_k_iter_pm2_aerial676x380_L64_f32.txt",
                    ["paper_1902_09733_amd/csrc/bp_iter_pm2.hip", "paper_1902_09733_amd/csrc/bp_pm_core.h",
                     "paper_1902_09733_amd/csrc/bp_device.h", "paper_1902_09733_amd/csrc/bp_internal.h"]),
-    "k_iter_pm": ("traffic_k_iter_pm_aerial676x380_L64_f32.txt",
-                  ["paper_1902_09733_amd/csrc/bp_iter_pm.hip", "paper_1902_09733_amd/csrc/bp_pm_core.h",
-                   "paper_1902_09733_amd/csrc/bp_device.h", "paper_1902_09733_amd/csrc/bp_internal.h"]),
 }
 
 
