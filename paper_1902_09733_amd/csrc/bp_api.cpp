@@ -166,6 +166,10 @@ bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
             plans[i].y_off = off + plans[i].bytes;
             plans[i].bytes += yb;
         }
+        // The coarsest level's first half-sweeps run as a fused pair that
+        // reads zero messages in place of the state, so only the out-of-grid
+        // slots need zeroing there.
+        plans[i].zero_coarsest = !level_pairs(plans[i], plans[i].levels - 1, p->iters_per_level);
         off += plans[i].bytes;
     }
     *total = align_up(off);
@@ -219,8 +223,11 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
     if ((st = q.cost ? launch_split_cost(q.cost, pl, ws, s) : launch_pair_cost(*q.pair, pl, ws, s, &done)) != BP_OK)
         return st;
     if ((st = launch_pyramid(pl, done, ws, s)) != BP_OK) return st;
-    // The finest level's last half-sweep also reads out its senders' labels.
-    const bool fuse_ro = q.disparity && !q.soft_disparity && K >= 1;
+    // The finest level's last half-sweep also reads out its senders' labels,
+    // and their soft-argmin when it runs in a fused pair.
+    const bool last_pair = level_pairs(pl, 0, K) && (K & 1) == 0;
+    const bool fuse_ro = K >= 1 && (q.soft_disparity ? last_pair : q.disparity != nullptr);
+    const float inv_t = q.soft_disparity ? 1.0f / p.temperature : 0.0f;
     for (int l = n - 1; l >= 0; --l) {
         int first_src = 0;
         if (l < n - 1) {
@@ -265,18 +272,18 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
             // state are zeroed once, the pairs write the in-grid rows.
             const size_t ck_state = pl.lv[0].msg_bytes;
             const int ck_n = ckpt ? checkpoint_states(K, p.checkpoint_every) : 0;
-            if (ckpt && (st = launch_zero_borders(pl, ckpt, ck_state, ck_n, s)) != BP_OK) return st;
+            if (ckpt && (st = launch_zero_borders(&pl, &ckpt, 1, ck_n, s)) != BP_OK) return st;
             for (int pi = 0; pi < np; ++pi, t0 += 2, ++launches) {
                 const size_t dst_off = ((np - 1 - pi) & 1) ? other : own;
                 int kind = PAIR_SRC_OWN;
                 if (t0 == 0) kind = l == n - 1 ? PAIR_SRC_ZERO : (first_src ? PAIR_SRC_PARENT : PAIR_SRC_OWN);
                 const bool ends = pi == np - 1 && (K & 1) == 0;
-                int32_t *ro = (l == 0 && ends && fuse_ro) ? q.disparity : nullptr;
+                const bool rd = l == 0 && ends && fuse_ro;
                 // Colour 1's final rows are stored for the next level's parent
-                // copy, the readout, the export and the final checkpoint; at the
-                // finest level with the readout fused here and neither of the
-                // others, nothing reads them.
-                const bool store_c1 = ends && (l > 0 || !ro || q.messages_out || ckpt);
+                // copy, the readout and the export; at the finest level with the
+                // readout fused here and no export, nothing reads them (the
+                // final checkpoint receives them on its own).
+                const bool store_c1 = ends && (l > 0 || !rd || q.messages_out);
                 // State after the pair: saved (its colour-0 half) every
                 // `every` half-sweeps, and whole at the end.
                 uint8_t *ck = nullptr;
@@ -288,8 +295,9 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
                 }
                 const bool rec = prof && !prof->per_level && prof->n < prof->cap;
                 if (rec && hipEventRecord(prof->ev[prof->n][0], s) != hipSuccess) return BP_ERR_HIP;
-                if ((st = launch_iteration_pair(pl, l, kind, src_off, dst_off, store_c1, p.lambda, p.tau, ro, ws, s,
-                                                ck)) != BP_OK)
+                if ((st = launch_iteration_pair(pl, l, kind, src_off, dst_off, store_c1, p.lambda, p.tau,
+                                                rd ? q.disparity : nullptr, ws, s, ck, ends,
+                                                rd ? q.soft_disparity : nullptr, inv_t)) != BP_OK)
                     return st;
                 if (rec) {
                     if (hipEventRecord(prof->ev[prof->n][1], s) != hipSuccess) return BP_ERR_HIP;
@@ -297,7 +305,7 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
                     r.level = l;
                     r.half_sweep = t0;
                     r.launches = 1;
-                    r.readout_fused = ro != nullptr;
+                    r.readout_fused = rd;
                     r.msg_bytes = fmt_bytes(pl.lv[l].fmt);
                     r.units = 2.0 * pl.lv[l].w * pl.lv[l].h * pl.L;
                     r.ms = 0.0f;
@@ -371,10 +379,12 @@ bp_status run_one(const bp_problem &q, const Plan &pl, const bp_params &p, uint8
 }
 
 // The batched form: problems whose levels are all pixel-major run each
-// (level, half-sweep) as one launch per lane split, over all of them.
+// (level, half-sweep) as one launch per lane split, over all of them (with
+// checkpoints only as fused pairs, see plan_run).
 bool batched(const Plan *plans, int32_t count, const bp_params &p)
 {
-    if (count < 2 || p.checkpoint_every > 0) return false;
+    (void)p;
+    if (count < 2) return false;
     for (int i = 0; i < count; ++i)
         for (int l = 0; l < plans[i].levels; ++l)
             if (plans[i].lv[l].layout != PIXEL_MAJOR) return false;
@@ -389,7 +399,7 @@ bool batched(const Plan *plans, int32_t count, const bp_params &p)
 bool batch_pairs(const Plan *plans, int32_t count, const bp_params &p)
 {
     const int K = p.iters_per_level;
-    if (p.variant != 0 || K < 2 || (K & 1) || p.checkpoint_every > 0) return false;
+    if (p.variant != 0 || K < 2 || (K & 1)) return false;
     for (int i = 0; i < count; ++i) {
         if (!plans[i].pairs) return false;
         for (int l = 0; l < plans[i].levels; ++l) {
@@ -423,6 +433,12 @@ bool plan_run(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
     if (!plan_all(probs, count, p, plans, total, true)) return false;
     if (*batch) {
         const bool pairs = batch_pairs(plans, count, *p);
+        // Checkpoints are saved by the fused pairs only; without them each
+        // problem runs on its own.
+        if (!pairs && p->checkpoint_every > 0) {
+            *batch = false;
+            return true;
+        }
         if (!pairs && !plan_all(probs, count, p, plans, total)) return false;
         if (table) *table = batch_table_bytes(count, p->levels, p->iters_per_level, pairs);
     }
@@ -430,13 +446,15 @@ bool plan_run(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
 }
 
 // Readout of the colours the last half-sweep did not cover, and the message
-// export, problem by problem.
+// export, problem by problem (those with in_group[i] == g when in_group is
+// given).
 bp_status finish_batched(const bp_problem *probs, int32_t count, const Plan *plans, const bp_params &p,
-                         const bool *fuse, uint8_t *ws, hipStream_t s)
+                         const bool *fuse, uint8_t *ws, hipStream_t s, const int *in_group = nullptr, int g = 0)
 {
     bp_status st = BP_OK;
     const int K = p.iters_per_level;
     for (int i = 0; i < count && st == BP_OK; ++i) {
+        if (in_group && in_group[i] != g) continue;
         const bp_problem &q = probs[i];
         if (q.disparity || q.soft_disparity) {
             const int mask = fuse[i] ? (1 << (K & 1)) : 3;
@@ -447,13 +465,34 @@ bp_status finish_batched(const bp_problem *probs, int32_t count, const Plan *pla
     return st;
 }
 
+// Working-set budget of one cache group of the batched fused pairs: well
+// inside the 256 MB Infinity Cache that sits between the L2s and HBM, leaving
+// room for the streams that pass through it (saved states, the other
+// buffers).  Eight 320x240x64 problems (138 MB each at the finest level) run
+// 25 us per pair each one after the other, against 29 us each batched
+// together, where each pair's state has left the cache before the next pair.
+constexpr size_t kPairGroupBytes = (size_t)192 << 20;
+
 // The batched form with fused pairs (batch_pairs): per level, pair and lane
-// split one launch over all problems of that split.  Buffers alternate as in
-// run_one, so every level's last pair writes the level's own state.
+// split one launch over the problems of that split in one cache group
+// (kPairGroupBytes), each group's readout and export right after its last
+// pair.  Buffers alternate as in run_one, so every level's last pair writes
+// the level's own state.  With
+// checkpoints (ckpt non-null; problems' saved states back to back) the pairs
+// save them as in run_one.
 bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *plans, const bp_params &p,
-                            uint8_t *ws, size_t table_off, const bool *fuse, hipStream_t s)
+                            uint8_t *ws, size_t table_off, const bool *fuse, uint8_t *ckpt, hipStream_t s)
 {
     const int n = p.levels, K = p.iters_per_level, np = K / 2;
+    const int ck_n = ckpt ? checkpoint_states(K, p.checkpoint_every) : 0;
+    uint8_t **ck_of = new uint8_t *[count];
+    {
+        size_t off = 0;
+        for (int i = 0; i < count; ++i) {
+            ck_of[i] = ckpt ? ckpt + off : nullptr;
+            if (ckpt) off += checkpoint_bytes_of(plans[i], K, p.checkpoint_every);
+        }
+    }
     int cls_S[32], cls_R[32], ncls = 0;
     int *cls_of = new int[count];
     for (int i = 0; i < count; ++i) {
@@ -468,60 +507,111 @@ bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *
         }
         cls_of[i] = c;
     }
-    const size_t nslot = (size_t)n * np * ncls;
+    // Cache groups: per level, consecutive problems whose working sets at
+    // that level (cost, messages, second buffer) add up to at most
+    // kPairGroupBytes run all their pairs before the next group starts, so
+    // that a group's state stays in the Infinity Cache between its pairs.
+    int *grp = new int[(size_t)n * count], ng = 1;
+    for (int l = 0; l < n; ++l) {
+        int g = 0;
+        size_t acc = 0;
+        for (int i = 0; i < count; ++i) {
+            const Level &v = plans[i].lv[l];
+            const size_t wsz = v.cost_bytes + v.msg_bytes + (size_t)4 * v.blk * fmt_bytes(v.fmt);
+            if (acc > 0 && acc + wsz > kPairGroupBytes) {
+                ++g;
+                acc = 0;
+            }
+            acc += wsz;
+            grp[(size_t)l * count + i] = g;
+        }
+        if (g + 1 > ng) ng = g + 1;
+    }
+    const size_t nslot = (size_t)n * ng * np * ncls;
     PairEntry *host = new PairEntry[(size_t)n * np * count];
     PairEntry *dev = (PairEntry *)(ws + table_off);
     int *start = new int[nslot], *num = new int[nslot], *blocks = new int[nslot];
     size_t *lds = new size_t[nslot];
     bool *ro = new bool[nslot];
     int e = 0;
+    auto slot_of = [&](int l, int g, int q, int c) { return (((size_t)l * ng + g) * np + q) * ncls + c; };
     for (int l = 0; l < n; ++l)
-        for (int q = 0; q < np; ++q)
-            for (int c = 0; c < ncls; ++c) {
-                const size_t slot = ((size_t)l * np + q) * ncls + c;
-                start[slot] = e;
-                num[slot] = 0;
-                lds[slot] = 0;
-                ro[slot] = false;
-                int b0 = 0;
-                for (int i = 0; i < count; ++i) {
-                    if (cls_of[i] != c) continue;
-                    const Plan &pl = plans[i];
-                    const bool fusable = l == n - 1 || pl.lv[l].fmt == pl.lv[l + 1].fmt;
-                    const size_t own = pl.lv[l].msg_off, other = pl.y_off;
-                    const size_t dst = ((np - 1 - q) & 1) ? other : own;
-                    const size_t src = q == 0 ? own : (((np - q) & 1) ? other : own);
-                    const int kind = q > 0 ? PAIR_SRC_OWN
-                                           : (l == n - 1 ? PAIR_SRC_ZERO : (fusable ? PAIR_SRC_PARENT : PAIR_SRC_OWN));
-                    const bool ends = q == np - 1;
-                    int32_t *disp = (l == 0 && ends && fuse[i]) ? probs[i].disparity : nullptr;
-                    // Colour 1's final rows: not needed at the finest level
-                    // when its readout is fused here and nothing is exported.
-                    const bool store_c1 = ends && (l > 0 || !disp || probs[i].messages_out);
-                    PairEntry &pe = host[e++];
-                    pe.a = make_pair_args(pl, l, kind, src, dst, store_c1, p.lambda, p.tau, disp, ws);
-                    pe.block0 = b0;
-                    b0 += pair_blocks(pe.a);
-                    const size_t lb = pair_lds_bytes(pe.a.tx, pe.a.ty, (int)pe.a.lp, fmt_bytes(pl.lv[l].fmt));
-                    if (lb > lds[slot]) lds[slot] = lb;
-                    if (disp) ro[slot] = true;
-                    ++num[slot];
+        for (int g = 0; g < ng; ++g)
+            for (int q = 0; q < np; ++q)
+                for (int c = 0; c < ncls; ++c) {
+                    const size_t slot = slot_of(l, g, q, c);
+                    start[slot] = e;
+                    num[slot] = 0;
+                    lds[slot] = 0;
+                    ro[slot] = false;
+                    int b0 = 0;
+                    for (int i = 0; i < count; ++i) {
+                        if (cls_of[i] != c || grp[(size_t)l * count + i] != g) continue;
+                        const Plan &pl = plans[i];
+                        const bool fusable = l == n - 1 || pl.lv[l].fmt == pl.lv[l + 1].fmt;
+                        const size_t own = pl.lv[l].msg_off, other = pl.y_off;
+                        const size_t dst = ((np - 1 - q) & 1) ? other : own;
+                        const size_t src = q == 0 ? own : (((np - q) & 1) ? other : own);
+                        const int kind = q > 0 ? PAIR_SRC_OWN
+                                               : (l == n - 1 ? PAIR_SRC_ZERO
+                                                             : (fusable ? PAIR_SRC_PARENT : PAIR_SRC_OWN));
+                        const bool ends = q == np - 1;
+                        const bool rd = l == 0 && ends && fuse[i];
+                        // State after the pair (finest level): saved every
+                        // `every` half-sweeps and at the end.
+                        uint8_t *ck = nullptr;
+                        if (ck_of[i] && l == 0) {
+                            const size_t ck_state = pl.lv[0].msg_bytes;
+                            const int tn = 2 * q + 2;
+                            if (ends) ck = ck_of[i] + (size_t)(ck_n - 1) * ck_state;
+                            else if (tn % p.checkpoint_every == 0 && tn < K)
+                                ck = ck_of[i] + (size_t)(tn / p.checkpoint_every - 1) * ck_state;
+                        }
+                        // Colour 1's final rows: not needed at the finest
+                        // level when its readout is fused here and nothing is
+                        // exported (the final checkpoint receives them on
+                        // its own).
+                        const bool store_c1 = ends && (l > 0 || !rd || probs[i].messages_out);
+                        PairEntry &pe = host[e++];
+                        pe.a = make_pair_args(pl, l, kind, src, dst, store_c1, p.lambda, p.tau,
+                                              rd ? probs[i].disparity : nullptr, ws, ck, ends,
+                                              rd ? probs[i].soft_disparity : nullptr,
+                                              probs[i].soft_disparity ? 1.0f / p.temperature : 0.0f);
+                        pe.block0 = b0;
+                        b0 += pair_blocks(pe.a);
+                        const size_t lb = pair_lds_bytes(pe.a.tx, pe.a.ty, (int)pe.a.lp, fmt_bytes(pl.lv[l].fmt));
+                        if (lb > lds[slot]) lds[slot] = lb;
+                        if (rd) ro[slot] = true;
+                        ++num[slot];
+                    }
+                    blocks[slot] = b0;
                 }
-                blocks[slot] = b0;
-            }
     bp_status st = launch_write_pair_entries(dev, host, e, s);
+    // Out-of-grid slots of every saved state are zeroed once; the pairs write
+    // the in-grid rows.
+    if (st == BP_OK && ckpt) st = launch_zero_borders(plans, ck_of, count, ck_n, s);
     for (int l = n - 1; l >= 0 && st == BP_OK; --l) {
-        if (l < n - 1)
-            for (int i = 0; i < count && st == BP_OK; ++i)
-                if (plans[i].lv[l].fmt != plans[i].lv[l + 1].fmt) st = launch_parent_copy(plans[i], l, ws, s);
         const int fmt = plans[0].lv[l].fmt;   // every problem has the same levels
-        for (int q = 0; q < np && st == BP_OK; ++q)
-            for (int c = 0; c < ncls && st == BP_OK; ++c) {
-                const size_t slot = ((size_t)l * np + q) * ncls + c;
-                if (num[slot] == 0) continue;
-                st = launch_iteration_pair_batch(dev + start[slot], num[slot], blocks[slot], lds[slot], fmt, cls_S[c],
-                                                 cls_R[c], ro[slot], s);
-            }
+        for (int g = 0; g < ng && st == BP_OK; ++g) {
+            if (l < n - 1)
+                for (int i = 0; i < count && st == BP_OK; ++i)
+                    if (grp[(size_t)l * count + i] == g && plans[i].lv[l].fmt != plans[i].lv[l + 1].fmt)
+                        st = launch_parent_copy(plans[i], l, ws, s);
+            for (int q = 0; q < np && st == BP_OK; ++q)
+                for (int c = 0; c < ncls && st == BP_OK; ++c) {
+                    const size_t slot = slot_of(l, g, q, c);
+                    if (num[slot] == 0) continue;
+                    // A lone problem takes the one-problem kernel (labels
+                    // without padding skip the padded-label masks).
+                    if (num[slot] == 1)
+                        st = dispatch_iter_pm2(host[start[slot]].a, fmt, cls_S[c], cls_R[c], ro[slot], s);
+                    else
+                        st = launch_iteration_pair_batch(dev + start[slot], num[slot], blocks[slot], lds[slot], fmt,
+                                                         cls_S[c], cls_R[c], ro[slot], s);
+                }
+            // The group's readout and export while its state is in the cache.
+            if (l == 0 && st == BP_OK) st = finish_batched(probs, count, plans, p, fuse, ws, s, grp, g);
+        }
     }
     delete[] host;
     delete[] start;
@@ -530,11 +620,13 @@ bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *
     delete[] lds;
     delete[] ro;
     delete[] cls_of;
+    delete[] ck_of;
+    delete[] grp;
     return st;
 }
 
 bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans, const bp_params &p, uint8_t *ws,
-                      size_t table_off, hipStream_t s)
+                      size_t table_off, uint8_t *ckpt, hipStream_t s)
 {
     bp_status st;
     const int n = p.levels, K = p.iters_per_level;
@@ -548,9 +640,10 @@ bp_status run_batched(const bp_problem *probs, int32_t count, const Plan *plans,
     }
     if (batch_pairs(plans, count, p)) {
         bool *fz = new bool[count];
-        for (int i = 0; i < count; ++i) fz[i] = probs[i].disparity && !probs[i].soft_disparity && K >= 1;
-        st = run_batched_pairs(probs, count, plans, p, ws, table_off, fz, s);
-        if (st == BP_OK) st = finish_batched(probs, count, plans, p, fz, ws, s);
+        // K is even: the last half-sweep runs in a fused pair, which reads out
+        // labels and soft-argmin both.
+        for (int i = 0; i < count; ++i) fz[i] = (probs[i].disparity || probs[i].soft_disparity) && K >= 1;
+        st = run_batched_pairs(probs, count, plans, p, ws, table_off, fz, ckpt, s);
         delete[] fz;
         return st;
     }
@@ -692,7 +785,8 @@ bp_status run_checked(const bp_problem *probs, int32_t count, const bp_params *p
     }
     (void)hipGetLastError();
     if (batch) {
-        bp_status bs = run_batched(probs, count, plans, *params, (uint8_t *)workspace, table_off, stream);
+        bp_status bs = run_batched(probs, count, plans, *params, (uint8_t *)workspace, table_off,
+                                   ck ? (uint8_t *)checkpoints : nullptr, stream);
         delete[] plans;
         return bs;
     }

@@ -7,6 +7,7 @@
 #include "bp_device.h"
 #include "bp_internal.h"
 #include "bp_levels.h"
+#include "bp_pm_core.h"
 
 namespace bpk {
 
@@ -22,6 +23,9 @@ bool make_plan(int w, int h, int L, int levels, int msg_fmt, int pm_from, size_t
     p->levels = levels;
     p->variant = 0;
     p->pair_off = 0;
+    p->pairs = false;
+    p->y_off = 0;
+    p->zero_coarsest = true;
     size_t off = base;
     int lw = w, lh = h;
     int S, R;
@@ -144,6 +148,41 @@ __global__ void __launch_bounds__(256) k_to_pm(const float *__restrict__ src, Le
     }
 }
 
+// Planar [L][h][w] -> pixel-major level with 16-byte accesses both ways:
+// a block moves 64 pixels of one row x 64 labels through LDS, loading four
+// consecutive pixels of one label per lane (256-byte runs along the row) and
+// storing four consecutive labels of one pixel per lane (a pixel's labels
+// are contiguous).  Needs w % 4 == 0 and a 16-byte aligned source; labels
+// from L up to the next multiple of four are stored as zero (they lie inside
+// the pixel's padded row, lp being a multiple of four).  grid (w/64, h, L/64).
+__global__ void __launch_bounds__(256) k_split_pm4(const float *__restrict__ src, float *__restrict__ out,
+                                                  LevelDesc d, int L)
+{
+    __shared__ float tile[64][65];
+    const int x0 = blockIdx.x * 64, y = blockIdx.y, f0 = blockIdx.z * 64;
+    const int t = threadIdx.x, q = t & 15, r = t >> 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int fl = r + 16 * i, f = f0 + fl, x = x0 + 4 * q;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (f < L && x < d.w) v = *(const float4 *)(src + ((int64_t)f * d.h + y) * d.w + x);
+        tile[fl][4 * q] = v.x;
+        tile[fl][4 * q + 1] = v.y;
+        tile[fl][4 * q + 2] = v.z;
+        tile[fl][4 * q + 3] = v.w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int xl = r + 16 * i, x = x0 + xl, f = f0 + 4 * q;
+        if (x < d.w && f < L) {
+            const int fl = 4 * q;
+            const float4 v = make_float4(tile[fl][xl], tile[fl + 1][xl], tile[fl + 2][xl], tile[fl + 3][xl]);
+            *(float4 *)(out + cost_idx((x + y) & 1, f, y * d.wh + (x >> 1), d.blk, d.ls, d.ps)) = v;
+        }
+    }
+}
+
 // label-major -> label-major pyramid step.  grid (wc/256, hc, L).
 __global__ void __launch_bounds__(256) k_pyr_lm(const float *__restrict__ fine, LevelDesc s, float *__restrict__ out,
                                                LevelDesc d)
@@ -177,7 +216,9 @@ bp_status launch_split_cost(const float *planar, const Plan &p, uint8_t *ws, hip
     const Level &v = p.lv[0];
     float *out = (float *)(ws + v.cost_off);
     LevelDesc d = desc(v);
-    if (v.layout == PIXEL_MAJOR) {
+    if (v.layout == PIXEL_MAJOR && v.w % 4 == 0 && ((uintptr_t)planar % 16) == 0) {
+        k_split_pm4<<<dim3(cdiv(v.w, 64), v.h, cdiv(p.L, 64)), 256, 0, s>>>(planar, out, d, p.L);
+    } else if (v.layout == PIXEL_MAJOR) {
         LevelDesc src{v.w, v.h, 0, 0, 0, 0};
         k_to_pm<true, false><<<dim3(cdiv(v.w, 64), v.h, cdiv(p.L, 32)), 256, 0, s>>>(planar, src, out, d, p.L);
     } else {
@@ -304,25 +345,39 @@ bp_status launch_pyramid_level(const Plan &p, int l, uint8_t *ws, hipStream_t s)
 // grid (blocks, levels + 1): block (x, y) is init_msgs_block(x, y).
 __global__ void __launch_bounds__(256) k_init_msgs(InitArgs a) { init_msgs_block(a, blockIdx.x, blockIdx.y); }
 
-bp_status launch_zero_borders(const Plan &p, uint8_t *base, size_t stride, int n, hipStream_t s)
+bp_status launch_zero_borders(const Plan *plans, uint8_t *const *bases, int count, int n, hipStream_t s)
 {
-    for (int i0 = 0; i0 < n; i0 += kMaxLevels) {
-        const int m = n - i0 < kMaxLevels ? n - i0 : kMaxLevels;
-        InitArgs a;
-        for (int i = 0; i < m; ++i) {
-            a.msg[i] = base + (size_t)(i0 + i) * stride;
-            a.d[i] = desc(p.lv[0]);
-            a.bytes[i] = fmt_bytes(p.lv[0].fmt);
-        }
-        a.L = p.L;
+    // Entries (problem, state) in order, up to kMaxLevels per launch and one
+    // label count per launch.
+    InitArgs a;
+    int m = 0;
+    int64_t most = 0;
+    auto flush = [&]() -> bp_status {
+        if (m == 0) return BP_OK;
         a.levels = m;
         a.coarsest_words = 0;
-        const int64_t per = (2 * (int64_t)p.lv[0].h + 2 * (int64_t)p.lv[0].w) * p.L;
-        k_init_msgs<<<dim3((unsigned)((per + 255) / 256), m), 256, 0, s>>>(a);
-        const bp_status st = launch_status();
-        if (st != BP_OK) return st;
+        k_init_msgs<<<dim3((unsigned)((most + 255) / 256), m), 256, 0, s>>>(a);
+        m = 0;
+        most = 0;
+        return launch_status();
+    };
+    bp_status st = BP_OK;
+    for (int i = 0; i < count && st == BP_OK; ++i) {
+        const Plan &p = plans[i];
+        const Level &v = p.lv[0];
+        for (int j = 0; j < n && st == BP_OK; ++j) {
+            if (m == kMaxLevels || (m > 0 && a.L != p.L)) st = flush();
+            if (st != BP_OK) break;
+            a.msg[m] = bases[i] + (size_t)j * v.msg_bytes;
+            a.d[m] = desc(v);
+            a.bytes[m] = fmt_bytes(v.fmt);
+            a.L = p.L;
+            const int64_t per = (2 * (int64_t)v.h + 2 * (int64_t)v.w) * p.L;
+            if (per > most) most = per;
+            ++m;
+        }
     }
-    return BP_OK;
+    return st == BP_OK ? flush() : st;
 }
 
 bp_status launch_init_messages(const Plan &p, uint8_t *ws, hipStream_t s)
@@ -451,7 +506,8 @@ bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lamb
 }
 
 PairArgs make_pair_args(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
-                        float lambda, float tau, int32_t *disp, uint8_t *ws, uint8_t *ck)
+                        float lambda, float tau, int32_t *disp, uint8_t *ws, uint8_t *ck, bool ck_c1, float *soft,
+                        float inv_t)
 {
     const Level &v = p.lv[l];
     PairArgs a;
@@ -480,6 +536,8 @@ PairArgs make_pair_args(const Plan &p, int l, int src_kind, size_t src_off, size
     a.dst_bytes = half;
     a.write_c1 = write_c1;
     a.disp = disp;
+    a.soft = soft;
+    a.inv_t = inv_t;
     a.w = v.w;
     a.h = v.h;
     a.wh = v.wh;
@@ -494,16 +552,19 @@ PairArgs make_pair_args(const Plan &p, int l, int src_kind, size_t src_off, size
     a.per_xcd = (a.ntiles + 7) / 8;
     a.ck = ck;
     a.ck_bytes = ck ? (uint32_t)v.msg_bytes : 0u;
+    a.ck_c1 = ck != nullptr && ck_c1;
     return a;
 }
 
 bp_status launch_iteration_pair(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
-                                float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s, uint8_t *ck)
+                                float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s, uint8_t *ck,
+                                bool ck_c1, float *soft, float inv_t)
 {
-    const PairArgs a = make_pair_args(p, l, src_kind, src_off, dst_off, write_c1, lambda, tau, disp, ws, ck);
+    const PairArgs a =
+        make_pair_args(p, l, src_kind, src_off, dst_off, write_c1, lambda, tau, disp, ws, ck, ck_c1, soft, inv_t);
     int S, R;
     pm_split(p.L, &S, &R);
-    return dispatch_iter_pm2(a, p.lv[l].fmt, S, R, disp != nullptr, s);
+    return dispatch_iter_pm2(a, p.lv[l].fmt, S, R, disp != nullptr || soft != nullptr, s);
 }
 
 bp_status launch_iteration_from(const Plan &p, int t, const uint8_t *src, float lambda, float tau, int variant,
@@ -603,34 +664,11 @@ __global__ void __launch_bounds__(256) k_readout_pm(const float *__restrict__ co
 #pragma unroll
         for (int r = 0; r < R; ++r) b[r] += m[r];
     }
-    const float inf = __builtin_huge_valf();
-    float bv = inf;
-    int bi = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (f0 + r >= L) b[r] = inf;
-        if (b[r] < bv) {
-            bv = b[r];
-            bi = f0 + r;
-        }
-    }
-    seg_argmin<SEG>(bv, bi);
+    int bi;
+    float sv;
+    pm_readout<SEG, R>(b, f0, L, soft != nullptr, inv_t, bi, sv);
     const int64_t o = (int64_t)y * d.w + x;
-    if (soft) {
-        float num = 0.0f, den = 0.0f;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (f0 + r < L) {
-                const float wgt = expf(-(b[r] - bv) * inv_t);
-                num += (float)(f0 + r) * wgt;
-                den += wgt;
-            }
-        }
-        auto add = [](float p, float q) { return p + q; };
-        num = seg_allreduce<SEG>(num, add);
-        den = seg_allreduce<SEG>(den, add);
-        if (s == 0) soft[o] = num / den;
-    }
+    if (soft && s == 0) soft[o] = sv;
     if (disp && s == 0) disp[o] = bi;
 }
 

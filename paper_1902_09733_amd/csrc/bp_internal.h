@@ -54,6 +54,8 @@ struct Plan {
     bool pairs;           // pixel-major levels run fused pairs of half-sweeps (bp_iter_pm2.hip)
     size_t y_off;         // second buffer of colour 0's incoming rows for the fused pairs
                           // (the finest pixel-major level's size; 0 when !pairs)
+    bool zero_coarsest;   // the initialisation zeros the coarsest level's whole state
+                          // (false when its first fused pair reads zeros in its place)
     size_t bytes;         // total workspace bytes of this problem (aligned)
 };
 
@@ -120,7 +122,8 @@ bp_status launch_iteration(const Plan &p, int l, int t, int src_mode, float lamb
 enum { PAIR_SRC_OWN = 0, PAIR_SRC_PARENT = 1, PAIR_SRC_ZERO = 2 };
 bp_status launch_iteration_pair(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
                                 float lambda, float tau, int32_t *disp, uint8_t *ws, hipStream_t s,
-                                uint8_t *ck = nullptr);
+                                uint8_t *ck = nullptr, bool ck_c1 = false, float *soft = nullptr,
+                                float inv_t = 0.0f);
 
 // Half-sweep t of the finest level reading its incoming messages from `src`
 // (a saved state in the level's layout) and writing the receivers' slots
@@ -238,6 +241,8 @@ struct PairArgs {
     uint8_t *dst;
     uint32_t dst_bytes;
     int32_t *disp;         // argmin labels of phase 2's senders, or NULL
+    float *soft;           // their soft-argmin disparity (temperature 1 / inv_t), or NULL
+    float inv_t;
     int w, h, wh;
     uint32_t blk, lp;      // this level's strides (pixel-major: ls = 1, ps = lp)
     uint32_t sblk, sps;    // strides of `src`
@@ -247,8 +252,9 @@ struct PairArgs {
     float lambda, lt;
     int tx, ty;            // tile (tx even)
     int tiles_x, ntiles, per_xcd;
-    uint8_t *ck;           // checkpoint state in the level's layout that also receives phase 2's rows
-                           // (and phase 1's when write_c1), or NULL
+    uint8_t *ck;           // checkpoint state in the level's layout that also receives phase 2's rows,
+                           // or NULL
+    int ck_c1;             // phase 1's rows also go to ck (the final state)
     uint32_t ck_bytes;
 };
 void pair_tile(int lp, int mb, int w, int h, int *tx, int *ty);
@@ -257,11 +263,13 @@ bp_status dispatch_iter_pm2(const PairArgs &a, int fmt, int S, int R, bool ro, h
 // Whether the fused pair supports a level's lane split.
 bool pair_supported(int S, int R);
 PairArgs make_pair_args(const Plan &p, int l, int src_kind, size_t src_off, size_t dst_off, bool write_c1,
-                        float lambda, float tau, int32_t *disp, uint8_t *ws, uint8_t *ck = nullptr);
-// Zero the out-of-grid slots of `n` message states laid out like level 0 of
-// plan p, `stride` bytes apart from `base` (checkpoint states written by the
-// fused pairs, which store in-grid rows only).
-bp_status launch_zero_borders(const Plan &p, uint8_t *base, size_t stride, int n, hipStream_t s);
+                        float lambda, float tau, int32_t *disp, uint8_t *ws, uint8_t *ck = nullptr,
+                        bool ck_c1 = false, float *soft = nullptr, float inv_t = 0.0f);
+// Zero the out-of-grid slots of `n` message states of each of `count`
+// problems: problem i's states are laid out like level 0 of plans[i], back to
+// back from bases[i] (checkpoint states written by the fused pairs, which
+// store in-grid rows only).
+bp_status launch_zero_borders(const Plan *plans, uint8_t *const *bases, int count, int n, hipStream_t s);
 // Batched fused pairs: one launch over the problems of a lane split; entries
 // hold each problem's arguments and its first block (a multiple of 8).
 struct PairEntry {

@@ -31,8 +31,10 @@
 // parent copy and the readout read.
 //
 // A forward run that saves states for the adjoint passes a checkpoint state
-// (`ck`, the level's layout): phase 2's rows, and phase 1's when they are
-// stored, are written there too, which replaces a copy of the state half.
+// (`ck`, the level's layout): phase 2's rows are written there too, which
+// replaces a copy of the state half, and phase 1's as well for the final
+// state (`ck_c1`; the level's own colour-1 block then need not be written
+// when nothing else reads it).
 //
 // Per message the arithmetic is the one-half-sweep kernel's variant 1
 // (bp_pm_core.h: h summed in slot order, the same transform), so results
@@ -132,11 +134,11 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
                     for (int q = 0; q < R / 2; ++q)
                         ((uint32_t *)row)[q] = (uint32_t)S::encode(out[2 * q]) | ((uint32_t)S::encode(out[2 * q + 1]) << 16);
                 }
-                if (a.write_c1) {
+                if (a.write_c1 || a.ck_c1) {
                     const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
                     const uint32_t off = ((4u + (uint32_t)(k ^ 1)) * a.blk + dj * lp + (uint32_t)f0) * S::bytes;
-                    st_row<S, R>(rm, off, out);
-                    if (a.ck) st_row<S, R>(rk, off, out);
+                    if (a.write_c1) st_row<S, R>(rm, off, out);
+                    if (a.ck_c1) st_row<S, R>(rk, off, out);
                 }
             }
         }
@@ -187,10 +189,12 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
                 }
             }
             if constexpr (RO) {
-                float bel[R];
+                float bel[R], sv;
+                int bi;
                 pm_belief<R>(c[u], m, bel);
-                const int bi = pm_argmin<SEG, R, EXACT>(bel, f0, a.L);
+                pm_readout<SEG, R>(bel, f0, a.L, a.soft != nullptr, a.inv_t, bi, sv);
                 if (s == 0 && a.disp) a.disp[(int64_t)y * a.w + x] = bi;
+                if (s == 0 && a.soft) a.soft[(int64_t)y * a.w + x] = sv;
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {

@@ -52,7 +52,7 @@ static inline InitArgs init_args(const Plan &p, uint8_t *ws, unsigned *blocks)
     }
     a.L = p.L;
     a.levels = p.levels;
-    a.coarsest_words = (int64_t)(p.lv[p.levels - 1].msg_bytes / 4);
+    a.coarsest_words = p.zero_coarsest ? (int64_t)(p.lv[p.levels - 1].msg_bytes / 4) : 0;
     if (a.coarsest_words / 4 > most) most = a.coarsest_words / 4;
     *blocks = (unsigned)((most + 255) / 256);
     return a;
@@ -61,7 +61,8 @@ static inline InitArgs init_args(const Plan &p, uint8_t *ws, unsigned *blocks)
 // Block (bx, l) of the initialisation.  l < levels: zero the out-of-grid
 // slots of level l (for every label: slot 0 of the left column, 1 of the right
 // column, 2 of the top row, 3 of the bottom row).  l == levels: zero every
-// message of the coarsest level, where BP starts from zero messages.
+// message of the coarsest level, where BP starts from zero messages (nothing
+// to do when the plan's first fused pair reads zeros instead).
 __device__ __forceinline__ void init_msgs_block(const InitArgs &a, int bx, int l)
 {
     const int64_t i = (int64_t)bx * 256 + threadIdx.x;

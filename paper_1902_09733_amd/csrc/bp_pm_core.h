@@ -1,8 +1,8 @@
 // The per-message arithmetic of a pixel-major half-sweep, shared by the
 // one-half-sweep kernels (bp_iter_pm.hip) and the fused pair of half-sweeps
 // (bp_iter_pm2.hip): the distance transform of h over a message's SEG lanes
-// (R labels per lane), truncation and normalisation, and the argmin of a
-// belief.  The identities behind the split scans are in bp_iter_pm.hip.
+// (R labels per lane), truncation and normalisation, and the readout of a
+// belief (argmin and soft-argmin, also used by the readout pass).  The identities behind the split scans are in bp_iter_pm.hip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -132,6 +132,49 @@ __device__ __forceinline__ int pm_argmin(const float (&bel)[R], int f0, int L)
     }
     seg_argmin<SEG>(bv, bi);
     return bi;
+}
+
+// Readout of a pixel from its belief (Eq. 1's minimiser): the lowest label
+// minimising it over the segment and, when soft, the soft-argmin
+//   sum_f f w(f) / sum_f w(f),  w(f) = exp(-(b(f) - min b) / T)
+// (inv_t = 1 / T), both on every lane.  Labels at or past L are ignored.
+// Products are rounded before they are added, so that every kernel reading
+// out a pixel (the readout pass, the fused pair's last phase) agrees bit for
+// bit.
+template <int SEG, int R>
+__device__ __forceinline__ void pm_readout(const float (&bel)[R], int f0, int L, bool soft, float inv_t, int &bi,
+                                           float &sv)
+{
+#pragma clang fp contract(off)
+    const float inf = __builtin_huge_valf();
+    float b[R];
+    float bv = inf;
+    bi = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        b[r] = f0 + r < L ? bel[r] : inf;
+        if (b[r] < bv) {
+            bv = b[r];
+            bi = f0 + r;
+        }
+    }
+    seg_argmin<SEG>(bv, bi);
+    sv = 0.0f;
+    if (soft) {
+        float num = 0.0f, den = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (f0 + r < L) {
+                const float wgt = expf(-(b[r] - bv) * inv_t);
+                num += (float)(f0 + r) * wgt;
+                den += wgt;
+            }
+        }
+        auto add = [](float p, float q) { return p + q; };
+        num = seg_allreduce<SEG>(num, add);
+        den = seg_allreduce<SEG>(den, add);
+        sv = num / den;
+    }
 }
 
 }  // namespace bpk

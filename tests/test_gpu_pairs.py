@@ -6,11 +6,11 @@ The library runs pixel-major levels as fused pairs when the kernel choice is
 left to it (variant 0); variant 1 is the one-half-sweep kernel with the same
 per-message arithmetic (h summed in slot order).  On real-valued costs --
 where any change of operation order would show -- both must give the same
-labels and final finest-level messages bit for bit, over tile edges and
-ragged grids (1x1 up to several tiles), every lane split (2 to 256 labels),
-odd and even K (single half-sweeps before or after the pairs), one to five
-levels, and the three storage formats (16-bit levels under an FP32 coarsest
-level take the materialised parent copy).  On integer data the fused path
+labels, soft-argmin disparities and final finest-level messages bit for
+bit, over tile edges and ragged grids (1x1 up to several tiles), every lane
+split (2 to 256 labels), odd and even K (single half-sweeps before or after
+the pairs), one to five levels, and the three storage formats (16-bit levels
+under an FP32 coarsest level take the materialised parent copy).  On integer data the fused path
 also equals the FP64 oracle.
 """
 import numpy as np
@@ -34,8 +34,8 @@ def dev():
 def both(bp, cost, levels, K, fmt, lam=7.3, tau=2.6):
     outs = []
     for variant in (0, 1):
-        p = bp.BPParams(levels=levels, iters=K, lam=lam, tau=tau, msg_dtype=fmt, variant=variant)
-        o = bp.run(cost, p, want_msgs=True)
+        p = bp.BPParams(levels=levels, iters=K, lam=lam, tau=tau, msg_dtype=fmt, variant=variant, temperature=0.7)
+        o = bp.run(cost, p, want_soft=True, want_msgs=True)
         torch.cuda.synchronize()
         outs.append(o)
     return outs
@@ -78,6 +78,9 @@ def test_pairs_equal_single_half_sweeps(dev, L, H, W, levels, K, fmt):
     a, b = both(bp, cost, levels, K, fmt)
     assert torch.equal(a["disp"], b["disp"])
     assert torch.equal(a["msgs"], b["msgs"])
+    # Soft-argmin: read out by the last fused pair (even K) or by the readout
+    # pass, with the same arithmetic.
+    assert torch.equal(a["soft"], b["soft"])
 
 
 @pytest.mark.parametrize("L,H,W,levels,K", [(64, 47, 61, 3, 10), (32, 20, 29, 2, 7), (96, 13, 22, 2, 6)])
@@ -114,3 +117,41 @@ def test_batched_pairs_equal_single_problems(dev, fmt, K, levels):
         torch.cuda.synchronize()
         assert torch.equal(ref["disp"], g["disp"])
         assert torch.equal(ref["msgs"], g["msgs"])
+
+
+@pytest.mark.parametrize("K,every", [(8, 2), (6, 2), (8, 4), (4, 4), (2, 2)])
+def test_batched_pairs_checkpoints_equal_single_problems(dev, K, every):
+    """Forward calls that save states for the adjoint run batched fused pairs
+    over several problems.  The saved states (buffers zeroed beforehand, so
+    every byte compares), the soft-argmin disparity and the adjoint's
+    gradients equal those of each problem run on its own, bit for bit, on
+    real-valued costs of mixed sizes and label counts."""
+    import paper_1902_09733_amd as bp
+    shapes = [(64, 37, 53), (32, 20, 29), (96, 17, 40), (64, 9, 9), (17, 11, 60)]
+    print(f"batched pairs with checkpoints: K={K} every={every}", flush=True)
+    rng = np.random.default_rng(K * 100 + every)
+    vols = [torch.from_numpy(rng.uniform(0.0, 20.0, size=sh).astype(np.float32)).to(dev) for sh in shapes]
+    gs = [torch.from_numpy(rng.standard_normal(size=sh[1:]).astype(np.float32)).to(dev) for sh in shapes]
+    p = bp.BPParams(levels=1, iters=K, lam=7.3, tau=2.6, temperature=0.5, checkpoint_every=every)
+    ck = torch.zeros(bp.checkpoint_bytes(vols, p), dtype=torch.uint8, device=dev)
+    got = bp.run(vols, p, want_disp=False, want_soft=True, checkpoints=ck)
+    gc, gl, gt = bp.backward(vols, p, ck, gs)
+    torch.cuda.synchronize()
+    off = 0
+    gl_ref = gt_ref = 0.0
+    for i, (v, g) in enumerate(zip(vols, gs)):
+        n = bp.checkpoint_bytes(v, p)
+        ck1 = torch.zeros(n, dtype=torch.uint8, device=dev)
+        ref = bp.run(v, p, want_disp=False, want_soft=True, checkpoints=ck1)
+        gc1, gl1, gt1 = bp.backward(v, p, ck1, g)
+        torch.cuda.synchronize()
+        assert torch.equal(ck[off:off + n], ck1), f"problem {i}: saved states differ"
+        assert torch.equal(got[i]["soft"], ref["soft"]), f"problem {i}: soft disparity differs"
+        assert torch.equal(gc[i], gc1), f"problem {i}: cost gradient differs"
+        off += n
+        gl_ref += float(gl1.item())
+        gt_ref += float(gt1.item())
+    assert off == ck.numel()
+    # lambda and tau gradients sum over the batch (in another order here).
+    assert abs(float(gl.item()) - gl_ref) <= 1e-5 * max(1.0, abs(gl_ref))
+    assert abs(float(gt.item()) - gt_ref) <= 1e-5 * max(1.0, abs(gt_ref))
