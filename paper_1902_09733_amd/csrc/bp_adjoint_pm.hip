@@ -1,9 +1,10 @@
 // a8 on pixel-major states: the reverse half-sweep with the labels of a
-// pixel spread over lanes, as in the forward pixel-major kernel with plain
-// loads (a sender pixel owns 4*SEG lanes, SEG per outgoing message k, R
-// labels per lane).
+// pixel spread over lanes, as in the forward pixel-major kernels (a sender
+// pixel owns SEG lanes, R labels per lane, and handles its four outgoing
+// messages k in turn, sharing the loads of its cost, incoming rows and
+// adjoints and the partial sums of h).
 //
-// Per lane the forward arithmetic is repeated exactly (same sums, same
+// Per message the forward arithmetic is repeated exactly (same sums, same
 // lane-local passes and cross-lane carries), now carrying the winner label
 // along every minimum:
 //   forward pass  A(f) = min(h(f), A(f-1) + lambda), the later label on ties
@@ -23,6 +24,7 @@
 
 #include "bp_device.h"
 #include "bp_internal.h"
+#include "bp_pm_core.h"
 
 namespace bpk {
 
@@ -148,17 +150,15 @@ __device__ __forceinline__ void bwd_step_pm(const BwdPmArgs &a, uint32_t block)
     // The forward arithmetic is repeated exactly as the half-sweep kernels
     // do it: products rounded before they are added (bp_pm_core.h).
 #pragma clang fp contract(off)
-    constexpr int GP = 4 * SEG;           // lanes per pixel
     constexpr int LP = SEG * R;           // labels stored per pixel
-    __shared__ float2 s_post[256 * R];    // posted (mb, winner bits), one row of LP per (pixel, message)
+    constexpr int PPB = 256 / SEG;        // pixels per block
+    __shared__ float2 s_post[PPB * 4 * LP];   // posted (mb, winner bits): a row of LP per (pixel, message)
     __shared__ float s_part[4][2];
     const uint32_t gid = block * 256u + threadIdx.x;
-    const int j = (int)(gid / GP);
-    const int lane = (int)(gid % GP);
-    const int k = lane / SEG;             // outgoing message, excluded incoming slot
-    const int s = lane % SEG;
+    const int j = (int)(gid / SEG);
+    const int s = (int)(gid % SEG);
     const int f0 = s * R;
-    const int row = (int)(threadIdx.x / SEG) * LP;
+    const int prow = (int)(threadIdx.x / SEG) * 4 * LP;
     bool live = j < a.ncomp;
     int y = 0, x = 0;
     if (live) {
@@ -171,181 +171,191 @@ __device__ __forceinline__ void bwd_step_pm(const BwdPmArgs &a, uint32_t block)
     const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost, a.cost_bytes);
     const __amdgpu_buffer_rsrc_t rm = make_rsrc(a.msg, a.msg_bytes);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(a.mbar, a.mbar_bytes);
+    const __amdgpu_buffer_rsrc_t rg = make_rsrc(a.gcost, a.cost_bytes);
     const float inf = __builtin_huge_valf();
     const float lam = a.lambda;
     const float lamR = lam * (float)R;
     const uint32_t base = jj * a.lp + (uint32_t)f0;
 
-    // The receiver slot's adjoint, loaded with the rows below (offset 0 and
-    // zeros for a sender without that neighbour).  The slot is not cleared:
-    // every in-grid slot of the receivers' colour is overwritten by the next
-    // reverse step's sender side before anything reads it again.
-    const bool hq = has[k];
-    uint32_t roff = 0;
-    if (hq) {
-        int nx = x, ny = y;
-        if (k == 0) nx = x - 1;
-        else if (k == 1) nx = x + 1;
-        else if (k == 2) ny = y - 1;
-        else ny = y + 1;
-        const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
-        roff = (((uint32_t)(a.colour ^ 1) * 4u + (uint32_t)(k ^ 1)) * a.blk + dj * a.lp + (uint32_t)f0) * 4u;
-    }
-    float mbv[R];
-    ld_row<StoreF32, R>(rb, roff, mbv);
+    // The four receiver slots' adjoints (zeros for a missing neighbour), the
+    // cost adjoint this pixel accumulates, the cost and the four incoming
+    // rows, all loaded before any arithmetic.  The receiver slots are not
+    // cleared: every in-grid slot of the receivers' colour is overwritten by
+    // the next reverse step's sender side before anything reads it again.
+    float mbv[4][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) mbv[r] = hq ? mbv[r] : 0.0f;
-    // The cost adjoint this pixel accumulates (message-0 lanes), also early.
-    const __amdgpu_buffer_rsrc_t rg = make_rsrc(a.gcost, a.cost_bytes);
+    for (int k = 0; k < 4; ++k) {
+        uint32_t roff = 0;
+        if (has[k]) {
+            int nx = x, ny = y;
+            if (k == 0) nx = x - 1;
+            else if (k == 1) nx = x + 1;
+            else if (k == 2) ny = y - 1;
+            else ny = y + 1;
+            const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
+            roff = (((uint32_t)(a.colour ^ 1) * 4u + (uint32_t)(k ^ 1)) * a.blk + dj * a.lp + (uint32_t)f0) * 4u;
+        }
+        ld_row<StoreF32, R>(rb, roff, mbv[k]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) mbv[k][r] = has[k] ? mbv[k][r] : 0.0f;
+    }
     const uint32_t goff = ((uint32_t)a.colour * a.blk + base) * 4u;
     float gc[R];
-    if (live && k == 0) ld_row<StoreF32, R>(rg, goff, gc);
-
-    // h of this lane's labels, summed as in the forward kernel.
-    float h[R];
+    if (live) ld_row<StoreF32, R>(rg, goff, gc);
+    // h of the four outgoing messages, summed as in the forward kernels.
+    float h[4][R];
     {
         float c[R], m[4][R];
         ld_row<StoreF32, R>(rc, ((uint32_t)a.colour * a.blk + base) * 4u, c);
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
             ld_row<StoreF32, R>(rm, (((uint32_t)a.colour * 4u + (uint32_t)kk) * a.blk + base) * 4u, m[kk]);
+        pm_h4<R>(c, m, h);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            float v = c[r];
+        for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) v += (kk == k) ? 0.0f : m[kk][r];
-            h[r] = (f0 + r < a.L) ? v : inf;
-        }
+            for (int r = 0; r < R; ++r)
+                if (f0 + r >= a.L) h[k][r] = inf;
     }
-    // Lowest minimiser of h.
-    float hmin = inf;
-    int gmin = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (h[r] < hmin) {
-            hmin = h[r];
-            gmin = f0 + r;
-        }
-    seg_argmin<SEG>(hmin, gmin);
 
-    // Forward pass with winners.
-    float A[R];
-    int wa[R];
-    A[0] = h[0];
-    wa[0] = f0;
+    // Phase 1, message by message: the transform with winners, then post
+    // (winner, mb) of the receiver slot's adjoint.
+    float lsum = 0.0f, tsum = 0.0f, nsum[4];
+    int gmin[4];
 #pragma unroll
-    for (int r = 1; r < R; ++r) {
-        const float v = A[r - 1] + lam;
-        const bool keep = h[r] <= v;
-        A[r] = keep ? h[r] : v;
-        wa[r] = keep ? f0 + r : wa[r - 1];
-    }
-    {
-        float pv;
-        int pi;
-        pair_prefix_excl<SEG>(A[R - 1] - lamR * (float)s, wa[R - 1], s, pv, pi);
-        const float carry = pv + lamR * (float)(s - 1);
+    for (int k = 0; k < 4; ++k) {
+        // Lowest minimiser of h.
+        float hmin = inf;
+        int gm = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float cand = carry + lam * (float)(r + 1);
-            if (cand < A[r]) {
-                A[r] = cand;
-                wa[r] = pi;
+        for (int r = 0; r < R; ++r)
+            if (h[k][r] < hmin) {
+                hmin = h[k][r];
+                gm = f0 + r;
+            }
+        seg_argmin<SEG>(hmin, gm);
+        gmin[k] = gm;
+        // Forward pass with winners.
+        float A[R];
+        int wa[R];
+        A[0] = h[k][0];
+        wa[0] = f0;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            const float v = A[r - 1] + lam;
+            const bool keep = h[k][r] <= v;
+            A[r] = keep ? h[k][r] : v;
+            wa[r] = keep ? f0 + r : wa[r - 1];
+        }
+        {
+            float pv;
+            int pi;
+            pair_prefix_excl<SEG>(A[R - 1] - lamR * (float)s, wa[R - 1], s, pv, pi);
+            const float carry = pv + lamR * (float)(s - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float cand = carry + lam * (float)(r + 1);
+                if (cand < A[r]) {
+                    A[r] = cand;
+                    wa[r] = pi;
+                }
             }
         }
-    }
-    // Backward pass with winners.
-    float B[R];
-    int wb[R];
-    B[R - 1] = A[R - 1];
-    wb[R - 1] = wa[R - 1];
+        // Backward pass with winners.
+        float B[R];
+        int wb[R];
+        B[R - 1] = A[R - 1];
+        wb[R - 1] = wa[R - 1];
 #pragma unroll
-    for (int r = R - 2; r >= 0; --r) {
-        const float v = B[r + 1] + lam;
-        const bool take = v < A[r];
-        B[r] = take ? v : A[r];
-        wb[r] = take ? wb[r + 1] : wa[r];
-    }
-    {
-        float qv;
-        int qi;
-        pair_suffix_excl<SEG>(B[0] + lamR * (float)s, wb[0], s, qv, qi);
-        const float carry = qv - lamR * (float)(s + 1);
+        for (int r = R - 2; r >= 0; --r) {
+            const float v = B[r + 1] + lam;
+            const bool take = v < A[r];
+            B[r] = take ? v : A[r];
+            wb[r] = take ? wb[r + 1] : wa[r];
+        }
+        {
+            float qv;
+            int qi;
+            pair_suffix_excl<SEG>(B[0] + lamR * (float)s, wb[0], s, qv, qi);
+            const float carry = qv - lamR * (float)(s + 1);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float cand = carry + lam * (float)(R - r);
-            if (cand < B[r]) {
-                B[r] = cand;
-                wb[r] = qi;
+            for (int r = 0; r < R; ++r) {
+                const float cand = carry + lam * (float)(R - r);
+                if (cand < B[r]) {
+                    B[r] = cand;
+                    wb[r] = qi;
+                }
             }
         }
-    }
-    const float cap = hmin + a.lt;
-
-    // Phase 1: post (winner, mb) of the receiver slot's adjoint.
-    float lsum = 0.0f, tsum = 0.0f, nsum = 0.0f;
+        const float cap = hmin + a.lt;
+        float ns = 0.0f;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int f = f0 + r;
-        const float mb = f < a.L ? mbv[r] : 0.0f;
-        int src = -1;
-        float post = 0.0f;
-        if (cap < B[r]) {
-            lsum += mb * a.tau;
-            tsum += mb * a.lambda;
-        } else {
-            src = wb[r];
-            post = mb;
-            nsum += mb;
-            lsum += mb * fabsf((float)(f - src));
+        for (int r = 0; r < R; ++r) {
+            const int f = f0 + r;
+            const float mb = f < a.L ? mbv[k][r] : 0.0f;
+            int src = -1;
+            float post = 0.0f;
+            if (cap < B[r]) {
+                lsum += mb * a.tau;
+                tsum += mb * a.lambda;
+            } else {
+                src = wb[r];
+                post = mb;
+                ns += mb;
+                lsum += mb * fabsf((float)(f - src));
+            }
+            s_post[prow + k * LP + f] = make_float2(post, __int_as_float(src));
         }
-        s_post[row + f] = make_float2(post, __int_as_float(src));
+        nsum[k] = ns;
     }
     __syncthreads();
 
-    // Phase 2: h-bar of this lane's labels.  One pass over the posts that can
-    // reach them (winners lie within `win` of their label); every h-bar(g)
-    // still adds its posts in increasing f.
-    const float ntot = seg_allreduce<SEG>(nsum, [](float p, float q) { return p + q; });
-    float hb[R];
+    // Phase 2: h-bar of this lane's labels for each message.  One pass over
+    // the posts that can reach them (winners lie within `win` of their
+    // label); every h-bar(g) still adds its posts in increasing f.
+    float hb[4][R];
+    const int lo = f0 - a.win > 0 ? f0 - a.win : 0;
+    const int hi = f0 + R - 1 + a.win < LP - 1 ? f0 + R - 1 + a.win : LP - 1;
 #pragma unroll
-    for (int r = 0; r < R; ++r) hb[r] = 0.0f;
-    {
-        const int lo = f0 - a.win > 0 ? f0 - a.win : 0;
-        const int hi = f0 + R - 1 + a.win < LP - 1 ? f0 + R - 1 + a.win : LP - 1;
+    for (int k = 0; k < 4; ++k) {
+        const float ntot = seg_allreduce<SEG>(nsum[k], [](float p, float q) { return p + q; });
+#pragma unroll
+        for (int r = 0; r < R; ++r) hb[k][r] = 0.0f;
         for (int f = lo; f <= hi; ++f) {
-            const float2 pst = s_post[row + f];
+            const float2 pst = s_post[prow + k * LP + f];
             const int d = __float_as_int(pst.y) - f0;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (d == r) hb[r] += pst.x;
+                if (d == r) hb[k][r] += pst.x;
         }
-    }
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (f0 + r == gmin) hb[r] -= ntot;
+        for (int r = 0; r < R; ++r)
+            if (f0 + r == gmin[k]) hb[k][r] -= ntot;
+    }
 
     // Sender side: cost-bar += sum over messages; slot k's adjoint gets the
     // other three messages' h-bar, added to the readout adjoint at the first
     // reverse step and written over the consumed value afterwards.
     float tot[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) tot[r] = xor_sum<2 * SEG>(xor_sum<SEG>(hb[r]));
-    if (live && k == 0) {
+    for (int r = 0; r < R; ++r) tot[r] = (hb[0][r] + hb[1][r]) + (hb[2][r] + hb[3][r]);
+    if (live) {
 #pragma unroll
         for (int r = 0; r < R; ++r) gc[r] += tot[r];
         st_row<StoreF32, R>(rg, goff, gc);
     }
-    if (hq) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (!has[k]) continue;
         const uint32_t moff = (((uint32_t)a.colour * 4u + (uint32_t)k) * a.blk + base) * 4u;
         float cur[R];
         if (a.first) {
             ld_row<StoreF32, R>(rb, moff, cur);
 #pragma unroll
-            for (int r = 0; r < R; ++r) cur[r] += tot[r] - hb[r];
+            for (int r = 0; r < R; ++r) cur[r] += tot[r] - hb[k][r];
         } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) cur[r] = tot[r] - hb[r];
+            for (int r = 0; r < R; ++r) cur[r] = tot[r] - hb[k][r];
         }
         st_row<StoreF32, R>(rb, moff, cur);
     }
@@ -492,7 +502,7 @@ int bwd_pm_blocks(const Plan &p)
 {
     int S, R;
     pm_split(p.L, &S, &R);
-    return pm_blocks(p.lv[0].h * p.lv[0].wh, S);
+    return (int)(((int64_t)p.lv[0].h * p.lv[0].wh * S + 255) / 256);
 }
 
 bp_status launch_bwd_readout_pm(const Plan &p, const uint8_t *msg, float *mbar, float *gcost, const float *grad_soft,

@@ -1035,17 +1035,24 @@ bp_status bp_upsample_points(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo,
 // Backward workspace: per problem its forward plan (cost + a message state
 // rebuilt from checkpoints), the message adjoint and, for pixel-major states,
 // the cost adjoint in the cost's layout; then the (lambda, tau) partials of
-// every reverse step of every problem and the launch table.
+// every reverse step of every problem, a zero colour half as large as the
+// largest problem's (the colour-0 half of the zero state M_0, read in place)
+// and the launch table.
 static bool backward_layout(const bp_problem *probs, int32_t count, const bp_params *params, Plan *plans,
                             size_t *mbar_off, size_t *gcost_off, size_t *partial_off, int *n_partial,
-                            size_t *table_off, size_t *total)
+                            size_t *zero_off, size_t *zero_bytes, size_t *table_off, size_t *total)
 {
     const bool lm = adjoint_label_major(*params);
-    size_t off = 0;
+    size_t off = 0, zb = 0;
     int np = 0;
     for (int i = 0; i < count; ++i) {
         const bp_problem &q = probs[i];
         if (!make_plan(q.width, q.height, q.num_labels, 1, BP_MSG_F32, lm ? 1 : 0, off, &plans[i])) return false;
+        // Replays write every slot a reverse step reads, and M_0's colour-0
+        // half is read from the zero half: the state's out-of-grid slots are
+        // all that needs zeroing.
+        plans[i].zero_coarsest = false;
+        zb = std::max(zb, (size_t)4 * plans[i].lv[0].blk * fmt_bytes(plans[i].lv[0].fmt));
         plans[i].variant = lm ? params->variant : 1;
         off += plans[i].bytes;
         mbar_off[i] = off;
@@ -1057,6 +1064,9 @@ static bool backward_layout(const bp_problem *probs, int32_t count, const bp_par
     *partial_off = off;
     *n_partial = np;
     off += align_up((size_t)(np > 0 ? np : 1) * 2 * sizeof(float));
+    *zero_off = off;
+    *zero_bytes = align_up(zb);
+    off += align_up(zb);
     *table_off = off;
     off += std::max(bwd_table_bytes(count), bwd_pm_table_bytes(count)) + bwd_finish_bytes();
     *total = off;
@@ -1080,9 +1090,9 @@ size_t bp_backward_workspace_size(const bp_problem *probs, int32_t count, const 
         if (probs[i].num_labels > kMaxBackwardLabels) return 0;
     Plan *plans = new Plan[count];
     size_t *mo = new size_t[count], *go = new size_t[count];
-    size_t po = 0, to = 0, total = 0;
+    size_t po = 0, zo = 0, zb = 0, to = 0, total = 0;
     int np = 0;
-    bool ok = backward_layout(probs, count, params, plans, mo, go, &po, &np, &to, &total);
+    bool ok = backward_layout(probs, count, params, plans, mo, go, &po, &np, &zo, &zb, &to, &total);
     delete[] plans;
     delete[] mo;
     delete[] go;
@@ -1103,12 +1113,12 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
         if (probs[i].num_labels > kMaxBackwardLabels) return BP_ERR_UNSUPPORTED;
     Plan *plans = new Plan[count];
     size_t *mo = new size_t[count], *go = new size_t[count];
-    size_t po = 0, to = 0, total = 0;
+    size_t po = 0, zo = 0, zb = 0, to = 0, total = 0;
     int np = 0;
     bp_status st = BP_OK;
     const int K = params->iters_per_level, every = params->checkpoint_every;
     const bool lm = adjoint_label_major(*params);
-    if (!backward_layout(probs, count, params, plans, mo, go, &po, &np, &to, &total)) st = BP_ERR_UNSUPPORTED;
+    if (!backward_layout(probs, count, params, plans, mo, go, &po, &np, &zo, &zb, &to, &total)) st = BP_ERR_UNSUPPORTED;
     size_t ck_total = 0;
     for (int i = 0; st == BP_OK && i < count; ++i) ck_total += checkpoint_bytes_of(plans[i], K, every);
     if (st == BP_OK && (ws_bytes < total || ckpt_bytes < ck_total)) st = BP_ERR_WORKSPACE_TOO_SMALL;
@@ -1121,7 +1131,9 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
     (void)hipGetLastError();
     uint8_t *ws = (uint8_t *)workspace;
     float *partial = (float *)(ws + po);
+    const uint8_t *zero_half = ws + zo;
     const int nst = checkpoint_states(K, every);
+    st = launch_zero(ws + zo, zb, stream);
     // Per problem: its checkpoints, state buffer, adjoints; the readout adjoint
     // from the final state initialises the message adjoint and the cost adjoint.
     const uint8_t **ck = new const uint8_t *[count];
@@ -1139,8 +1151,9 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
             bp[i] = BwdProblem{&pl, ws, ws + pl.lv[0].msg_off, mbar, grad_cost + cost_off, nullptr};
             bq[i] = BwdPmProblem{&pl, ws, ws + pl.lv[0].msg_off, mbar, (float *)(ws + go[i]), nullptr};
             if ((st = launch_split_cost(probs[i].cost, pl, ws, stream)) != BP_OK) break;
-            // Zero state: its out-of-grid slots are never written afterwards, and
-            // replays below write only the slots the reverse steps read.
+            // Out-of-grid slots of the state buffer: zero, and never written
+            // afterwards (replays below write only the in-grid slots the
+            // reverse steps read).
             if ((st = launch_init_messages(pl, ws, stream)) != BP_OK) break;
             const uint8_t *last = ck[i] + (size_t)(nst - 1) * sb;
             if (lm)
@@ -1167,22 +1180,20 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
             if (saved && t == t0) {
                 // M_t is a saved state: the reverse step reads it in place.
                 mt = saved;
+            } else if (!saved && t == 0) {
+                // M_0 is zero and the reverse step at t = 0 reads only its
+                // colour-0 half: the zero half, in place.
+                mt = zero_half;
             } else {
                 // Half-sweep r reads the slots of colour r & 1 and writes those of
                 // the other colour, and the reverse step at t reads only the slots
-                // of colour t & 1: the first replay reads the saved state in place
-                // and writes into the state buffer, no copy needed.
+                // of colour t & 1: the first replay reads the saved state (or M_0's
+                // colour-0 half, the zero half) in place and writes into the state
+                // buffer, no copy needed.
                 int r = t0;
-                if (!saved) {
-                    // M_0 is zero; half-sweep 0 (or the reverse step at t = 0)
-                    // reads only the colour-0 half, and the out-of-grid slots of
-                    // the other half were zeroed at the start.
-                    const Level &v0 = pl.lv[0];
-                    st = launch_zero(state, (size_t)4 * v0.blk * fmt_bytes(v0.fmt), stream);
-                } else {
-                    st = launch_iteration_from(pl, r, saved, params->lambda, params->tau, pl.variant, ws, stream);
-                    ++r;
-                }
+                st = launch_iteration_from(pl, r, saved ? saved : zero_half, params->lambda, params->tau, pl.variant,
+                                           ws, stream);
+                ++r;
                 for (; r < t && st == BP_OK; ++r)
                     st = launch_iteration(pl, 0, r, 0, params->lambda, params->tau, nullptr, pl.variant, ws, stream);
             }
