@@ -152,13 +152,28 @@ __device__ __forceinline__ void bwd_step_pm(const BwdPmArgs &a, uint32_t block)
 #pragma clang fp contract(off)
     constexpr int LP = SEG * R;           // labels stored per pixel
     constexpr int PPB = 256 / SEG;        // pixels per block
-    __shared__ float2 s_post[PPB * 4 * LP];   // posted (mb, winner bits): a row of LP per (pixel, message)
+    // Posted mb and winner (a byte: labels are fewer than 128 here): per
+    // pixel its four messages' rows of LP labels, each row preceded and
+    // followed by PAD entries that post nothing (winner -1), so that a window
+    // of up to PAD labels around a lane's labels needs no clamping at the
+    // row's ends.
+    static_assert(LP <= kMaxBackwardLabels && kMaxBackwardLabels <= 128, "winners must fit a signed byte");
+    constexpr int PAD = 4;
+    constexpr int PROW = 4 * (LP + PAD) + PAD;
+    __shared__ float s_pv[PPB * PROW];
+    __shared__ int8_t s_pw[PPB * PROW];
     __shared__ float s_part[4][2];
     const uint32_t gid = block * 256u + threadIdx.x;
     const int j = (int)(gid / SEG);
     const int s = (int)(gid % SEG);
     const int f0 = s * R;
-    const int prow = (int)(threadIdx.x / SEG) * 4 * LP;
+    const int prow = (int)(threadIdx.x / SEG) * PROW;
+    for (int e = (int)threadIdx.x; e < PPB * 5 * PAD; e += 256) {
+        const int px = e / (5 * PAD), q = e - px * (5 * PAD);
+        const int at = px * PROW + (q / PAD) * (LP + PAD) + q % PAD;
+        s_pv[at] = 0.0f;
+        s_pw[at] = -1;
+    }
     bool live = j < a.ncomp;
     int y = 0, x = 0;
     if (live) {
@@ -304,7 +319,8 @@ __device__ __forceinline__ void bwd_step_pm(const BwdPmArgs &a, uint32_t block)
                 ns += mb;
                 lsum += mb * fabsf((float)(f - src));
             }
-            s_post[prow + k * LP + f] = make_float2(post, __int_as_float(src));
+            s_pv[prow + PAD + k * (LP + PAD) + f] = post;
+            s_pw[prow + PAD + k * (LP + PAD) + f] = (int8_t)src;
         }
         nsum[k] = ns;
     }
@@ -321,12 +337,26 @@ __device__ __forceinline__ void bwd_step_pm(const BwdPmArgs &a, uint32_t block)
         const float ntot = seg_allreduce<SEG>(nsum[k], [](float p, float q) { return p + q; });
 #pragma unroll
         for (int r = 0; r < R; ++r) hb[k][r] = 0.0f;
-        for (int f = lo; f <= hi; ++f) {
-            const float2 pst = s_post[prow + k * LP + f];
-            const int d = __float_as_int(pst.y) - f0;
+        const int row = prow + PAD + k * (LP + PAD);
+        if (a.win <= PAD) {
+            // Every lane the same count of posts, the pads past the row's
+            // ends included (they match no label).
+            const int n = R + 2 * a.win, p0 = row + f0 - a.win;
+            for (int i = 0; i < n; ++i) {
+                const float pv = s_pv[p0 + i];
+                const int wv = s_pw[p0 + i];
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (d == r) hb[k][r] += pst.x;
+                for (int r = 0; r < R; ++r)
+                    if (wv == f0 + r) hb[k][r] += pv;
+            }
+        } else {
+            for (int f = lo; f <= hi; ++f) {
+                const float pv = s_pv[row + f];
+                const int d = (int)s_pw[row + f] - f0;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (d == r) hb[k][r] += pv;
+            }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r)
