@@ -638,20 +638,20 @@ __global__ void __launch_bounds__(256) k_readout_lm(const float *__restrict__ co
     if (soft) soft[o] = num / den;
 }
 
-// Pixel-major readout: SEG lanes per pixel, R labels per lane.  grid (ncomp*SEG/256, 2).
+// Pixel-major readout: SEG lanes per pixel, R labels per lane; a block
+// covers 256 / SEG pixels of one row of one colour.  grid (ceil(wh * SEG /
+// 256), h, colours), colour c0 + blockIdx.z.
 template <int SEG, int R, typename S>
 __global__ void __launch_bounds__(256) k_readout_pm(const float *__restrict__ cost, uint32_t cost_bytes,
                                                    const uint8_t *__restrict__ msg, uint32_t msg_bytes, LevelDesc d,
-                                                   int lp, int L, int mask, int32_t *__restrict__ disp,
+                                                   int lp, int L, int c0, int32_t *__restrict__ disp,
                                                    float *__restrict__ soft, float inv_t)
 {
-    const int c = blockIdx.y;
-    if (!((mask >> c) & 1)) return;
-    const int gid = blockIdx.x * 256 + threadIdx.x;
-    const int j = gid / SEG, s = gid % SEG;
-    if (j >= d.h * d.wh) return;
-    const int y = j / d.wh;
-    const int x = 2 * (j - y * d.wh) + ((y + c) & 1);
+    const int c = c0 + (int)blockIdx.z, y = (int)blockIdx.y;
+    const int i = (int)(blockIdx.x * 256 + threadIdx.x) / SEG, s = (int)threadIdx.x % SEG;
+    if (i >= d.wh) return;
+    const int j = y * d.wh + i;
+    const int x = 2 * i + ((y + c) & 1);
     if (x >= d.w) return;
     const __amdgpu_buffer_rsrc_t rc = make_rsrc(cost, cost_bytes);
     const __amdgpu_buffer_rsrc_t rm = make_rsrc(msg, msg_bytes);
@@ -666,7 +666,7 @@ __global__ void __launch_bounds__(256) k_readout_pm(const float *__restrict__ co
     }
     int bi;
     float sv;
-    pm_readout<SEG, R>(b, f0, L, soft != nullptr, inv_t, bi, sv);
+    pm_readout<SEG, R, false>(b, f0, L, soft != nullptr, inv_t, bi, sv);
     const int64_t o = (int64_t)y * d.w + x;
     if (soft && s == 0) soft[o] = sv;
     if (disp && s == 0) disp[o] = bi;
@@ -690,12 +690,13 @@ bp_status launch_readout(const Plan &p, int colour_mask, int32_t *disp, float *s
         }
         int SEGV, R;
         pm_split(p.L, &SEGV, &R);
-#define BP_RO_CASE(SV, RV)                                                                                         \
-    if (SEGV == SV && R == RV) {                                                                                   \
-        k_readout_pm<SV, RV, S><<<dim3(cdiv(ncomp * SV, 256), 2), 256, 0, s>>>(                                    \
-            cost, (uint32_t)v.cost_bytes, msg, (uint32_t)v.msg_bytes, desc(v), v.lp, p.L, colour_mask, disp, soft, \
-            inv_t);                                                                                                \
-        return launch_status();                                                                                    \
+        // Colours 0 and 1, or just the one the mask names.
+        const int c0 = colour_mask == 2 ? 1 : 0, nc = colour_mask == 3 ? 2 : 1;
+#define BP_RO_CASE(SV, RV)                                                                                      \
+    if (SEGV == SV && R == RV) {                                                                                \
+        k_readout_pm<SV, RV, S><<<dim3(cdiv((int64_t)v.wh * SV, 256), v.h, nc), 256, 0, s>>>(                   \
+            cost, (uint32_t)v.cost_bytes, msg, (uint32_t)v.msg_bytes, desc(v), v.lp, p.L, c0, disp, soft, inv_t); \
+        return launch_status();                                                                                 \
     }
         BP_RO_CASE(4, 4)
         BP_RO_CASE(8, 4)

@@ -192,7 +192,7 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
                 float bel[R], sv;
                 int bi;
                 pm_belief<R>(c[u], m, bel);
-                pm_readout<SEG, R>(bel, f0, a.L, a.soft != nullptr, a.inv_t, bi, sv);
+                pm_readout<SEG, R, EXACT>(bel, f0, a.L, a.soft != nullptr, a.inv_t, bi, sv);
                 if (s == 0 && a.disp) a.disp[(int64_t)y * a.w + x] = bi;
                 if (s == 0 && a.soft) a.soft[(int64_t)y * a.w + x] = sv;
             }

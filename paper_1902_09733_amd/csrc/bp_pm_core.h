@@ -137,11 +137,11 @@ __device__ __forceinline__ int pm_argmin(const float (&bel)[R], int f0, int L)
 // Readout of a pixel from its belief (Eq. 1's minimiser): the lowest label
 // minimising it over the segment and, when soft, the soft-argmin
 //   sum_f f w(f) / sum_f w(f),  w(f) = exp(-(b(f) - min b) / T)
-// (inv_t = 1 / T), both on every lane.  Labels at or past L are ignored.
-// Products are rounded before they are added, so that every kernel reading
-// out a pixel (the readout pass, the fused pair's last phase) agrees bit for
-// bit.
-template <int SEG, int R>
+// (inv_t = 1 / T), both on every lane.  Labels at or past L are ignored
+// (there are none when EXACT, L == SEG * R).  Products are rounded before
+// they are added, so that every kernel reading out a pixel (the readout pass,
+// the fused pair's last phase) agrees bit for bit.
+template <int SEG, int R, bool EXACT>
 __device__ __forceinline__ void pm_readout(const float (&bel)[R], int f0, int L, bool soft, float inv_t, int &bi,
                                            float &sv)
 {
@@ -152,7 +152,7 @@ __device__ __forceinline__ void pm_readout(const float (&bel)[R], int f0, int L,
     bi = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        b[r] = f0 + r < L ? bel[r] : inf;
+        b[r] = (EXACT || f0 + r < L) ? bel[r] : inf;
         if (b[r] < bv) {
             bv = b[r];
             bi = f0 + r;
@@ -164,7 +164,7 @@ __device__ __forceinline__ void pm_readout(const float (&bel)[R], int f0, int L,
         float num = 0.0f, den = 0.0f;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if (f0 + r < L) {
+            if (EXACT || f0 + r < L) {
                 const float wgt = expf(-(b[r] - bv) * inv_t);
                 num += (float)(f0 + r) * wgt;
                 den += wgt;
