@@ -155,3 +155,23 @@ def test_batched_pairs_checkpoints_equal_single_problems(dev, K, every):
     # lambda and tau gradients sum over the batch (in another order here).
     assert abs(float(gl.item()) - gl_ref) <= 1e-5 * max(1.0, abs(gl_ref))
     assert abs(float(gt.item()) - gt_ref) <= 1e-5 * max(1.0, abs(gt_ref))
+
+
+def test_batched_pairs_streaming_and_cache_groups(dev):
+    """Problems whose finest level does not fit the batched form's cache
+    budget share launches (two of them with the same lane split), the small
+    ones run in cache groups: labels and messages equal each problem run
+    alone with one launch per half-sweep, on real-valued costs."""
+    import paper_1902_09733_amd as bp
+    shapes = [(64, 500, 900), (64, 37, 53), (96, 400, 640), (64, 300, 1000), (17, 11, 60)]
+    rng = np.random.default_rng(7)
+    vols = [torch.from_numpy(rng.uniform(0.0, 20.0, size=sh).astype(np.float32)).to(dev) for sh in shapes]
+    p0 = bp.BPParams(levels=3, iters=4, lam=7.3, tau=2.6)
+    got = bp.run(vols, p0, want_msgs=True)
+    torch.cuda.synchronize()
+    p1 = bp.BPParams(levels=3, iters=4, lam=7.3, tau=2.6, variant=1)
+    for i, (v, g) in enumerate(zip(vols, got)):
+        ref = bp.run(v, p1, want_msgs=True)
+        torch.cuda.synchronize()
+        assert torch.equal(ref["disp"], g["disp"]), f"problem {i}: labels differ"
+        assert torch.equal(ref["msgs"], g["msgs"]), f"problem {i}: messages differ"
