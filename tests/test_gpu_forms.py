@@ -24,7 +24,9 @@ def test_precision_form_vs_fp64(dev, pset):
     """FP32 / FP16 / BF16 message storage against the FP64 oracle.  Integer
     parameter set: every message is an integer <= lambda*tau = 20, exact in
     all three formats, so labels and messages must match bit for bit.
-    Real-valued set: at most 0.5% of pixels more than one label off."""
+    Real-valued set: at most 0.5% of pixels more than one label off, FP32
+    messages within 1e-4 * lambda * tau but for a few near-tie entries, 16-bit
+    messages within their format's rounding but for near-tie entries."""
     import paper_1902_09733_amd as bp
     wl = workload("aerial1352x760_L128")
     L, levels, K = wl["num_labels"], wl["levels"], wl["iters"]
@@ -38,14 +40,33 @@ def test_precision_form_vs_fp64(dev, pset):
         r = bp.run(cost, bp.BPParams(levels=levels, iters=K, lam=lam, tau=tau, msg_dtype=fmt), want_msgs=True)
         torch.cuda.synchronize()
         d = r["disp"].cpu().numpy()
-        err = float(np.abs(r["msgs"].double().cpu().numpy() - o["msgs"]).max() / (lam * tau))
+        diff = np.abs(r["msgs"].double().cpu().numpy() - o["msgs"]) / (lam * tau)
+        err = float(diff.max())
         bad = float((np.abs(d - o["disp"]) > 1).mean())
-        report[fmt] = {"bad_pixel_vs_fp64": bad, "max_msg_err_over_lambda_tau": err}
+        report[fmt] = {"bad_pixel_vs_fp64": bad, "max_msg_err_over_lambda_tau": err,
+                       "p99_9_msg_err_over_lambda_tau": float(np.quantile(diff, 0.999)),
+                       "msg_entries_over_1e-4_lambda_tau": float((diff > 1e-4).mean()),
+                       "msg_entries_over_1e-2_lambda_tau": float((diff > 1e-2).mean())}
+        del diff
         del r
         if pset == "int":
             assert bad == 0.0 and err == 0.0, (fmt, report[fmt])
         else:
             assert bad <= 0.005, (fmt, report[fmt])
+            rep = report[fmt]
+            if fmt == "f32":
+                # The 1e-4 * lambda * tau message bar holds for every entry
+                # but a few near-tie senders, whose two near-equal minimisers
+                # FP32 and FP64 order differently (measured: 2.5e-6 of the
+                # entries, the largest 0.017 lambda * tau; 99.9% within 2e-7).
+                assert rep["msg_entries_over_1e-4_lambda_tau"] <= 1e-5, (fmt, rep)
+                assert rep["p99_9_msg_err_over_lambda_tau"] <= 1e-4, (fmt, rep)
+            else:
+                # 16-bit rows: the format's rounding (99.9% within 2.3e-4 /
+                # 1.3e-3 lambda * tau for FP16 / BF16), full-range changes
+                # only at near-tie senders.
+                assert rep["p99_9_msg_err_over_lambda_tau"] <= 4e-3, (fmt, rep)
+                assert rep["msg_entries_over_1e-2_lambda_tau"] <= 1e-3, (fmt, rep)
     print("precision", pset, json.dumps(report))
 
 
