@@ -159,9 +159,10 @@ def test_batched_pairs_checkpoints_equal_single_problems(dev, K, every):
 
 def test_batched_pairs_streaming_and_cache_groups(dev):
     """Problems whose finest level does not fit the batched form's cache
-    budget share launches (two of them with the same lane split), the small
-    ones run in cache groups: labels and messages equal each problem run
-    alone with one launch per half-sweep, on real-valued costs."""
+    budget run as groups of their own there and share launches at coarser
+    levels, small ones share cache groups: labels and messages equal each
+    problem run alone with one launch per half-sweep, on real-valued
+    costs."""
     import paper_1902_09733_amd as bp
     shapes = [(64, 500, 900), (64, 37, 53), (96, 400, 640), (64, 300, 1000), (17, 11, 60)]
     rng = np.random.default_rng(7)
