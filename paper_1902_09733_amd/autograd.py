@@ -25,8 +25,10 @@ class BPSoftArgmin(torch.autograd.Function):
                                  temperature=float(temperature), checkpoint_every=int(checkpoint_every))
         vols = list(cost.unbind(0))
         ck = torch.empty(stereo.checkpoint_bytes(vols, params), dtype=torch.uint8, device=cost.device)
-        outs = stereo.run(vols, params, want_disp=False, want_soft=True, checkpoints=ck)
-        soft = torch.stack([o["soft"] for o in outs])
+        B, _, H, W = cost.shape
+        soft = torch.empty((B, H, W), dtype=torch.float32, device=cost.device)
+        stereo.run(vols, params, checkpoints=ck, outputs=[{"disp": None, "soft": soft[i], "msgs": None}
+                                                          for i in range(B)])
         ctx.save_for_backward(cost, ck)
         ctx.params = params
         return soft
@@ -36,8 +38,8 @@ class BPSoftArgmin(torch.autograd.Function):
         cost, ck = ctx.saved_tensors
         vols = list(cost.unbind(0))
         grads = list(grad_soft.contiguous().float().unbind(0))
-        gc, gl, gt = stereo.backward(vols, ctx.params, ck, grads)
-        gcost = torch.stack(gc)
+        gcost = torch.empty_like(cost)
+        _, gl, gt = stereo.backward(vols, ctx.params, ck, grads, grad_out=gcost)
         return gcost, gl.reshape(()), gt.reshape(()), None, None, None
 
 

@@ -223,6 +223,19 @@ def _run_args(costs, params, want_disp, want_soft, want_msgs, outputs):
                 "soft": torch.empty((h, w), dtype=torch.float32, device=dev) if want_soft else None,
                 "msgs": torch.empty((4, L, h, w), dtype=torch.float32, device=dev) if want_msgs else None,
             })
+    else:
+        if len(outputs) != len(costs):
+            raise ValueError("outputs must hold one dict per problem")
+        for c, o in zip(costs, outputs):
+            L, h, w = c.shape
+            for key, dt, shape in (("disp", torch.int32, (h, w)), ("soft", torch.float32, (h, w)),
+                                   ("msgs", torch.float32, (4, L, h, w))):
+                t = o.get(key)
+                if t is None:
+                    continue
+                _need_gpu(t)
+                if t.device != dev or t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous():
+                    raise ValueError(f"outputs['{key}'] must be a contiguous {dt} tensor of shape {shape} on {dev}")
     probs = _problems(costs, [o.get("disp") for o in outputs], [o.get("soft") for o in outputs],
                       [o.get("msgs") for o in outputs])
     return single, costs, outputs, probs, params.c()
@@ -237,11 +250,14 @@ def checkpoint_bytes(costs, params: BPParams) -> int:
 
 
 def backward(costs, params: BPParams, checkpoints: torch.Tensor, grad_soft, workspace: Workspace | None = None,
-             stream=None):
+             stream=None, grad_out: torch.Tensor | None = None):
     """Gradient of sum(grad_soft * soft_disparity) with respect to the cost
     volumes, lambda and tau, from the checkpoints of a forward ``run`` with the
     same costs and params.  ``grad_soft`` is a tensor [H][W] (or a list).
-    Returns (grad_costs (tensor or list), grad_lambda [1], grad_tau [1])."""
+    ``grad_out`` may pass a contiguous float32 tensor holding every cost
+    gradient back to back (e.g. [B][L][H][W] for a batch of equal volumes).
+    Returns (grad_costs (tensor or list, views of grad_out when given),
+    grad_lambda [1], grad_tau [1])."""
     single = isinstance(costs, torch.Tensor)
     costs = [costs] if single else list(costs)
     grads_soft = [grad_soft] if single else list(grad_soft)
@@ -250,7 +266,13 @@ def backward(costs, params: BPParams, checkpoints: torch.Tensor, grad_soft, work
         _need_gpu(c, g)
     gs = torch.cat([g.reshape(-1).float() for g in grads_soft]).contiguous()
     total = sum(c.numel() for c in costs)
-    gc = torch.empty(total, dtype=torch.float32, device=dev)
+    if grad_out is None:
+        gc = torch.empty(total, dtype=torch.float32, device=dev)
+    else:
+        _need_gpu(grad_out)
+        if grad_out.dtype != torch.float32 or not grad_out.is_contiguous() or grad_out.numel() != total:
+            raise ValueError("grad_out must be a contiguous float32 tensor with one entry per cost entry")
+        gc = grad_out.view(-1)
     gl = torch.empty(1, dtype=torch.float32, device=dev)
     gt = torch.empty(1, dtype=torch.float32, device=dev)
     probs = _problems(costs, [None] * len(costs), [None] * len(costs), [None] * len(costs))

@@ -494,3 +494,26 @@ def test_batched_shuffled_sum_variants_exact(dev, variant):
     for c, o_gpu, shp in zip(costs, outs, BATCH_SHAPES):
         o = oracle_run(c, 3, 5, 10.0, 2.0)
         assert_exact({k: v.cpu().numpy() for k, v in o_gpu.items()}, o, f"batched {shp} variant {variant}")
+
+
+def test_run_rejects_mismatched_outputs(dev):
+    """Preallocated outputs are checked before anything is enqueued: shape,
+    dtype, device and contiguity must match the problem."""
+    bp = bp_mod()
+    cost = torch.zeros((8, 5, 6), dtype=torch.float32, device=dev)
+    p = bp.BPParams(levels=1, iters=2)
+    bad = [
+        {"disp": torch.empty((5, 7), dtype=torch.int32, device=dev)},
+        {"disp": torch.empty((5, 6), dtype=torch.int64, device=dev)},
+        {"soft": torch.empty((6, 5), dtype=torch.float32, device=dev).t()},
+        {"msgs": torch.empty((4, 8, 5, 6), dtype=torch.float32)},
+    ]
+    for o in bad:
+        with pytest.raises(ValueError):
+            bp.run(cost, p, outputs=[o])
+    with pytest.raises(ValueError):
+        bp.run([cost, cost], p, outputs=[{"disp": torch.empty((5, 6), dtype=torch.int32, device=dev)}])
+    good = {"disp": torch.empty((5, 6), dtype=torch.int32, device=dev), "soft": None, "msgs": None}
+    bp.run(cost, p, outputs=[good])
+    torch.cuda.synchronize()
+    assert int(good["disp"].max()) == 0   # all-zero costs: label 0 everywhere
