@@ -24,7 +24,13 @@ __device__ __forceinline__ void st_f32(__amdgpu_buffer_rsrc_t r, float v, uint32
 }
 
 // Message storage formats.  Arithmetic is always FP32; a stored value is
-// rounded to nearest-even in the storage format.
+// rounded to nearest-even in the storage format.  pack2 rounds two values
+// into one 32-bit word (low half first) with gfx950's two-value conversion
+// instructions; encode rounds one value the same way.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
 struct StoreF32 {
     static constexpr int bytes = 4;
     static constexpr int fmt = 0;
@@ -43,6 +49,11 @@ struct StoreF16 {
     static constexpr int fmt = 1;
     static __device__ __forceinline__ float decode(uint16_t u) { return (float)__builtin_bit_cast(_Float16, u); }
     static __device__ __forceinline__ uint16_t encode(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+    static __device__ __forceinline__ uint32_t pack2(float a, float b)
+    {
+        const f32x2_t v = {a, b};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2_t));   // v_cvt_pk_f16_f32
+    }
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
     {
         uint16_t u = __builtin_bit_cast(uint16_t, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
@@ -64,12 +75,14 @@ struct StoreBF16 {
         uint16_t u = __builtin_bit_cast(uint16_t, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
         return __builtin_bit_cast(float, (uint32_t)u << 16);
     }
-    // Round to nearest even on the upper 16 bits (messages are finite).
-    static __device__ __forceinline__ uint16_t encode(float v)
+    // Round to nearest even on the upper 16 bits (v_cvt_pk_bf16_f32; the
+    // same bits as adding 0x7fff plus the kept part's lowest bit and
+    // truncating, for the finite values messages are).
+    static __device__ __forceinline__ uint16_t encode(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+    static __device__ __forceinline__ uint32_t pack2(float a, float b)
     {
-        uint32_t u = __builtin_bit_cast(uint32_t, v);
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return (uint16_t)(u >> 16);
+        const f32x2_t v = {a, b};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, float v, uint32_t voff, uint32_t soff)
     {
@@ -143,7 +156,7 @@ __device__ __forceinline__ void st_row(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
     } else {
         uint32_t w[R / 2];
 #pragma unroll
-        for (int i = 0; i < R / 2; ++i) w[i] = (uint32_t)S::encode(v[2 * i]) | ((uint32_t)S::encode(v[2 * i + 1]) << 16);
+        for (int i = 0; i < R / 2; ++i) w[i] = S::pack2(v[2 * i], v[2 * i + 1]);
         st_words<R / 2>(r, voff, w);
     }
 }

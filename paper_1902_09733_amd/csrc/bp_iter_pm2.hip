@@ -132,7 +132,7 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
                 } else {
 #pragma unroll
                     for (int q = 0; q < R / 2; ++q)
-                        ((uint32_t *)row)[q] = (uint32_t)S::encode(out[2 * q]) | ((uint32_t)S::encode(out[2 * q + 1]) << 16);
+                        ((uint32_t *)row)[q] = S::pack2(out[2 * q], out[2 * q + 1]);
                 }
                 if (a.write_c1 || a.ck_c1) {
                     const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
