@@ -93,12 +93,15 @@ typedef struct {
                                   level, the part of the message state the adjoint reads
                                   (and the whole final state) into the checkpoint buffer,
                                   whose contents only bp_backward interprets */
-    int32_t variant;           /* 0 = library choice: on a single problem (or problems that do
-                                  not run batched), pixel-major levels with K >= 2 run two
+    int32_t variant;           /* 0 = library choice: pixel-major levels with K >= 2 run two
                                   half-sweeps per launch (tiles whose colour-1 messages stay
                                   on chip between the two; a second buffer of half a level's
-                                  messages in the workspace), without checkpoints; otherwise
-                                  one half-sweep per launch.  Else a half-sweep kernel variant in
+                                  messages in the workspace), also when checkpoints are saved
+                                  every even number of half-sweeps; with count > 1 when K is
+                                  even and every level of every problem does so (one launch
+                                  per level, pair and lane split over the problems of a group
+                                  whose working sets fit the on-package cache), otherwise one
+                                  half-sweep per launch.  Else a half-sweep kernel variant in
                                   1..bp_variant_count() (testing and tuning).  Label-major
                                   levels: lanes per pixel 1/2/4 by label count.  Pixel-major
                                   levels: 1 default lane split, 2 half the lanes with twice
