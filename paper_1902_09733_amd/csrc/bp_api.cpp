@@ -536,7 +536,7 @@ bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *
     PairEntry *dev = (PairEntry *)(ws + table_off);
     int *start = new int[nslot], *num = new int[nslot], *blocks = new int[nslot];
     size_t *lds = new size_t[nslot];
-    bool *ro = new bool[nslot];
+    bool *ro = new bool[nslot], *exact = new bool[nslot];
     int e = 0;
     auto slot_of = [&](int l, int g, int q, int c) { return (((size_t)l * ng + g) * np + q) * ncls + c; };
     for (int l = 0; l < n; ++l)
@@ -548,6 +548,7 @@ bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *
                     num[slot] = 0;
                     lds[slot] = 0;
                     ro[slot] = false;
+                    exact[slot] = true;
                     int b0 = 0;
                     for (int i = 0; i < count; ++i) {
                         if (cls_of[i] != c || grp[(size_t)l * count + i] != g) continue;
@@ -586,6 +587,7 @@ bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *
                         const size_t lb = pair_lds_bytes(pe.a.tx, pe.a.ty, (int)pe.a.lp, fmt_bytes(pl.lv[l].fmt));
                         if (lb > lds[slot]) lds[slot] = lb;
                         if (rd) ro[slot] = true;
+                        if (pl.L != cls_S[c] * cls_R[c]) exact[slot] = false;
                         ++num[slot];
                     }
                     blocks[slot] = b0;
@@ -611,7 +613,7 @@ bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *
                         st = dispatch_iter_pm2(host[start[slot]].a, fmt, cls_S[c], cls_R[c], ro[slot], s);
                     else
                         st = launch_iteration_pair_batch(dev + start[slot], num[slot], blocks[slot], lds[slot], fmt,
-                                                         cls_S[c], cls_R[c], ro[slot], s);
+                                                         cls_S[c], cls_R[c], exact[slot], ro[slot], s);
                 }
             // The group's readout and export while its state is in the cache.
             if (l == 0 && st == BP_OK) st = finish_batched(probs, count, plans, p, fuse, ws, s, grp, g);
@@ -623,6 +625,7 @@ bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *
     delete[] blocks;
     delete[] lds;
     delete[] ro;
+    delete[] exact;
     delete[] cls_of;
     delete[] ck_of;
     delete[] grp;

@@ -284,8 +284,9 @@ struct PairChunk {
 };
 int pair_blocks(const PairArgs &a);
 bp_status launch_write_pair_entries(PairEntry *dst, const PairEntry *src, int n, hipStream_t s);
+// exact: every entry's label count equals its lane split's S * R.
 bp_status launch_iteration_pair_batch(const PairEntry *tab, int n, int blocks, size_t lds, int fmt, int S, int R,
-                                      bool ro, hipStream_t s);
+                                      bool exact, bool ro, hipStream_t s);
 
 // Pixel-major kernel variants (1 default split; 2 half the lanes per message,
 // twice the labels per lane; 3 and 4 the same with each lane group reading

@@ -221,8 +221,9 @@ __global__ void __launch_bounds__(NT) k_iter_pm2(const PairArgs a)
 
 // Batched fused pair: block b belongs to the last table entry whose first
 // block is <= b; every entry's first block is a multiple of 8, so the XCD
-// grouping of tiles holds within each problem.
-template <int SEG, int R, typename S, bool RO, int NT, int U>
+// grouping of tiles holds within each problem.  EXACT: every entry's label
+// count fills its lane split.
+template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U>
 __global__ void __launch_bounds__(NT) k_iter_pm2_batch(const PairEntry *__restrict__ tab, int n)
 {
     extern __shared__ uint8_t lds[];
@@ -233,7 +234,7 @@ __global__ void __launch_bounds__(NT) k_iter_pm2_batch(const PairEntry *__restri
         else hi = mid - 1;
     }
     const PairArgs a = tab[lo].a;
-    pm2_tile<SEG, R, S, false, RO, NT, U>(a, (int)blockIdx.x - tab[lo].block0, lds);
+    pm2_tile<SEG, R, S, EXACT, RO, NT, U>(a, (int)blockIdx.x - tab[lo].block0, lds);
 }
 
 // Table of batch entries written from kernel arguments (capture-safe).
@@ -294,14 +295,14 @@ static bp_status launch_pm2(const PairArgs &a, size_t lds, hipStream_t st)
     return launch_status();
 }
 
-template <typename S>
+template <typename S, bool EXACT>
 static bp_status dispatch_pm2_batch(const PairEntry *tab, int n, int blocks, size_t lds, int SEGV, int R, bool ro,
                                     hipStream_t st)
 {
 #define BP_PM2B(SV, RV)                                                                                        \
     if (SEGV == SV && R == RV) {                                                                               \
-        if (ro) k_iter_pm2_batch<SV, RV, S, true, kPairThreads, 1><<<blocks, kPairThreads, lds, st>>>(tab, n); \
-        else k_iter_pm2_batch<SV, RV, S, false, kPairThreads, 1><<<blocks, kPairThreads, lds, st>>>(tab, n);  \
+        if (ro) k_iter_pm2_batch<SV, RV, S, EXACT, true, kPairThreads, 1><<<blocks, kPairThreads, lds, st>>>(tab, n);  \
+        else k_iter_pm2_batch<SV, RV, S, EXACT, false, kPairThreads, 1><<<blocks, kPairThreads, lds, st>>>(tab, n);    \
         return launch_status();                                                                                \
     }
     BP_PM2B(4, 4) BP_PM2B(8, 4) BP_PM2B(16, 4) BP_PM2B(16, 6) BP_PM2B(16, 8) BP_PM2B(16, 12) BP_PM2B(16, 16)
@@ -309,16 +310,25 @@ static bp_status dispatch_pm2_batch(const PairEntry *tab, int n, int blocks, siz
     return BP_ERR_UNSUPPORTED;
 }
 
+template <typename S>
+static bp_status dispatch_pm2_batch_exact(const PairEntry *tab, int n, int blocks, size_t lds, int SEGV, int R,
+                                          bool exact, bool ro, hipStream_t st)
+{
+    return exact ? dispatch_pm2_batch<S, true>(tab, n, blocks, lds, SEGV, R, ro, st)
+                 : dispatch_pm2_batch<S, false>(tab, n, blocks, lds, SEGV, R, ro, st);
+}
+
 bp_status launch_iteration_pair_batch(const PairEntry *tab, int n, int blocks, size_t lds, int fmt, int SEGV, int R,
-                                      bool ro, hipStream_t st)
+                                      bool exact, bool ro, hipStream_t st)
 {
     if (lds > 65536) return BP_ERR_UNSUPPORTED;
     switch (fmt) {
-    case FMT_F16: return dispatch_pm2_batch<StoreF16>(tab, n, blocks, lds, SEGV, R, ro, st);
-    case FMT_BF16: return dispatch_pm2_batch<StoreBF16>(tab, n, blocks, lds, SEGV, R, ro, st);
-    default: return dispatch_pm2_batch<StoreF32>(tab, n, blocks, lds, SEGV, R, ro, st);
+    case FMT_F16: return dispatch_pm2_batch_exact<StoreF16>(tab, n, blocks, lds, SEGV, R, exact, ro, st);
+    case FMT_BF16: return dispatch_pm2_batch_exact<StoreBF16>(tab, n, blocks, lds, SEGV, R, exact, ro, st);
+    default: return dispatch_pm2_batch_exact<StoreF32>(tab, n, blocks, lds, SEGV, R, exact, ro, st);
     }
 }
+
 
 template <int SEG, int R, typename S>
 static bp_status launch_pm2_ro(const PairArgs &a, size_t lds, bool ro, hipStream_t st)
