@@ -592,7 +592,20 @@ bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *
                     }
                     blocks[slot] = b0;
                 }
-    bp_status st = launch_write_pair_entries(dev, host, e, s);
+    // The device table holds the entries of launches over several problems
+    // (runs of consecutive such slots written together); a lone problem's
+    // launch takes its arguments directly.
+    bp_status st = BP_OK;
+    for (size_t slot = 0; slot < nslot && st == BP_OK;) {
+        if (num[slot] < 2) {
+            ++slot;
+            continue;
+        }
+        const int first = start[slot];
+        int n_run = 0;
+        for (; slot < nslot && (num[slot] > 1 || num[slot] == 0); ++slot) n_run += num[slot];
+        st = launch_write_pair_entries(dev + first, host + first, n_run, s);
+    }
     // Out-of-grid slots of every saved state are zeroed once; the pairs write
     // the in-grid rows.
     if (st == BP_OK && ckpt) st = launch_zero_borders(plans, ck_of, count, ck_n, s);
