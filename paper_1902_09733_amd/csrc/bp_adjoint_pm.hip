@@ -528,6 +528,41 @@ __global__ void __launch_bounds__(256) k_gcost_to_planar(const float *__restrict
     }
 }
 
+// The same transpose with 16-byte accesses both ways (w % 4 == 0, 16-byte
+// aligned output): a block moves 64 pixels of one row x 64 labels through
+// LDS, loading four consecutive labels of one pixel per lane (a pixel's
+// labels are contiguous) and storing four consecutive pixels of one label.
+// grid (w / 64, h, L / 64).
+__global__ void __launch_bounds__(256) k_gcost_to_planar4(const float *__restrict__ gcost, PmDesc d, int L,
+                                                         float *__restrict__ out)
+{
+    __shared__ float tile[64][65];
+    const int x0 = blockIdx.x * 64, y = blockIdx.y, f0 = blockIdx.z * 64;
+    const int t = threadIdx.x, q = t & 15, r = t >> 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int xl = r + 16 * i, x = x0 + xl, f = f0 + 4 * q;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (x < d.w && f < L) {
+            const int c = (x + y) & 1;
+            v = *(const float4 *)(gcost + (int64_t)c * d.blk + ((int64_t)y * d.wh + (x >> 1)) * d.lp + f);
+        }
+        tile[4 * q][xl] = v.x;
+        tile[4 * q + 1][xl] = v.y;
+        tile[4 * q + 2][xl] = v.z;
+        tile[4 * q + 3][xl] = v.w;
+    }
+    __syncthreads();
+    const int64_t plane = (int64_t)d.h * d.w;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int fl = r + 16 * i, f = f0 + fl, x = x0 + 4 * q;
+        if (f < L && x < d.w)
+            *(float4 *)(out + f * plane + (int64_t)y * d.w + x) =
+                make_float4(tile[fl][4 * q], tile[fl][4 * q + 1], tile[fl][4 * q + 2], tile[fl][4 * q + 3]);
+    }
+}
+
 int bwd_pm_blocks(const Plan &p)
 {
     int S, R;
@@ -558,6 +593,11 @@ bp_status launch_bwd_readout_pm(const Plan &p, const uint8_t *msg, float *mbar, 
 bp_status launch_gcost_to_planar(const Plan &p, const float *gcost, float *grad_cost, hipStream_t s)
 {
     const Level &v = p.lv[0];
+    if (v.w % 4 == 0 && ((uintptr_t)grad_cost % 16) == 0) {
+        k_gcost_to_planar4<<<dim3((unsigned)((v.w + 63) / 64), (unsigned)v.h, (unsigned)((p.L + 63) / 64)), 256, 0, s>>>(
+            gcost, pm_desc(v), p.L, grad_cost);
+        return launch_status();
+    }
     const dim3 grid((unsigned)((v.w + 31) / 32), (unsigned)v.h);
     switch (v.lp) {
     case 16: k_gcost_to_planar<16><<<grid, 256, 0, s>>>(gcost, pm_desc(v), p.L, grad_cost); break;
