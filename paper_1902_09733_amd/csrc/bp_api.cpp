@@ -1052,6 +1052,54 @@ bp_status bp_upsample_points(const int32_t *disp_lo, int32_t w_lo, int32_t h_lo,
                            R, disp_hi, camera, points, stream);
 }
 
+// Launch tables of the backward call: the reverse steps' entries, or the
+// batched rebuild half-sweeps' (one region, rewritten in stream order).
+static size_t bwd_tables_bytes(int32_t count)
+{
+    return std::max(std::max(bwd_table_bytes(count), bwd_pm_table_bytes(count)),
+                    align_up((size_t)count * sizeof(BatchEntry)));
+}
+
+// One rebuild half-sweep r of every problem's finest level in one launch per
+// lane split (pixel-major states): entry i reads srcs[i] (a saved state, the
+// zero half, or the problem's own state when NULL) and writes the problem's
+// state buffer.
+static bp_status rebuild_batched(const Plan *plans, int32_t count, int r, const uint8_t *const *srcs, float lambda,
+                                 float tau, uint8_t *ws, uint8_t *table, hipStream_t s)
+{
+    BatchEntry *host = new BatchEntry[count];
+    BatchEntry *dev = (BatchEntry *)table;
+    bool *done = new bool[count]();
+    bp_status st = BP_OK;
+    int used = 0;
+    for (int i = 0; i < count && st == BP_OK; ++i) {
+        if (done[i]) continue;
+        int S, R;
+        bool X;
+        pm_split_variant(plans[i].L, plans[i].variant, &S, &R, &X);
+        const int first = used;
+        int blocks = 0;
+        for (int k = i; k < count; ++k) {
+            int Sk, Rk;
+            bool Xk;
+            pm_split_variant(plans[k].L, plans[k].variant, &Sk, &Rk, &Xk);
+            if (done[k] || Sk != S || Rk != R || Xk != X) continue;
+            done[k] = true;
+            BatchEntry &e = host[used++];
+            e.a = make_iter_args(plans[k], 0, r, 0, lambda, tau, nullptr, ws);
+            if (srcs[k]) e.a.src = srcs[k];
+            e.block0 = blocks;
+            blocks += pm_sweep_blocks(e.a.ncomp, S, X);
+        }
+        st = launch_write_entries(dev + first, host + first, used - first, s);
+        if (st == BP_OK)
+            st = launch_iteration_batch(dev + first, used - first, blocks, plans[i].lv[0].fmt, S, R, X, false, s);
+    }
+    delete[] host;
+    delete[] done;
+    return st;
+}
+
 // Backward workspace: per problem its forward plan (cost + a message state
 // rebuilt from checkpoints), the message adjoint and, for pixel-major states,
 // the cost adjoint in the cost's layout; then the (lambda, tau) partials of
@@ -1088,7 +1136,7 @@ static bool backward_layout(const bp_problem *probs, int32_t count, const bp_par
     *zero_bytes = align_up(zb);
     off += align_up(zb);
     *table_off = off;
-    off += std::max(bwd_table_bytes(count), bwd_pm_table_bytes(count)) + bwd_finish_bytes();
+    off += bwd_tables_bytes(count) + bwd_finish_bytes();
     *total = off;
     return true;
 }
@@ -1188,9 +1236,21 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
     }
     // Reverse half-sweeps, newest first: rebuild every problem's M_t (restore
     // the last saved state at or before t, replay), then one batched step.
+    // Pixel-major states of several problems replay in one launch per
+    // half-sweep and lane split.
+    const bool batch_rebuild = !lm && count > 1;
+    const uint8_t **rsrc = new const uint8_t *[count];
     int part = 0;
     for (int t = K - 1; t >= 0 && st == BP_OK; --t) {
         const int t0 = (t / every) * every;
+        if (batch_rebuild && t > t0) {
+            for (int i = 0; i < count; ++i)
+                rsrc[i] = t0 > 0 ? ck[i] + (size_t)(t0 / every - 1) * plans[i].lv[0].msg_bytes : zero_half;
+            st = rebuild_batched(plans, count, t0, rsrc, params->lambda, params->tau, ws, ws + to, stream);
+            for (int i = 0; i < count; ++i) rsrc[i] = nullptr;
+            for (int r = t0 + 1; r < t && st == BP_OK; ++r)
+                st = rebuild_batched(plans, count, r, rsrc, params->lambda, params->tau, ws, ws + to, stream);
+        }
         for (int i = 0; i < count && st == BP_OK; ++i) {
             const Plan &pl = plans[i];
             const size_t sb = pl.lv[0].msg_bytes;
@@ -1204,7 +1264,7 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
                 // M_0 is zero and the reverse step at t = 0 reads only its
                 // colour-0 half: the zero half, in place.
                 mt = zero_half;
-            } else {
+            } else if (!batch_rebuild) {
                 // Half-sweep r reads the slots of colour r & 1 and writes those of
                 // the other colour, and the reverse step at t reads only the slots
                 // of colour t & 1: the first replay reads the saved state (or M_0's
@@ -1235,9 +1295,10 @@ bp_status bp_backward(const bp_problem *probs, int32_t count, const bp_params *p
     delete[] ck;
     delete[] bp;
     delete[] bq;
+    delete[] rsrc;
     if (st == BP_OK)
         st = launch_bwd_finish(partial, np, grad_lambda, grad_tau,
-                               ws + to + std::max(bwd_table_bytes(count), bwd_pm_table_bytes(count)), stream);
+                               ws + to + bwd_tables_bytes(count), stream);
     delete[] plans;
     delete[] mo;
     delete[] go;
