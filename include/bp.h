@@ -438,7 +438,10 @@ size_t bp_backward_workspace_size(const bp_problem *probs, int32_t count, const 
  * text lines "width height labels fmt levels pm_from variant us".  When
  * bp_params.pm_from == -1 and variant == 0, a problem uses the entry with its
  * label count, format and level count whose pixel count is nearest (log
- * scale); results never depend on the choice.  The table named by the
+ * scale); results never depend on the choice.  In a batch (count > 1) that
+ * can run fused pairs, the entries' layouts apply but not their half-sweep
+ * variants (one problem on single half-sweeps would take the whole batch off
+ * the pairs).  The table named by the
  * environment variable BP_TUNE_TABLE is read at the first planning call;
  * bp_load_tune_table replaces it (NULL clears it).  Errors:
  * BP_ERR_INVALID_ARGUMENT if the file cannot be opened.  Not to be called

@@ -128,7 +128,7 @@ bool level_pairs(const Plan &pl, int l, int K)
 // as fused pairs of half-sweeps, which need a second buffer of colour 0's
 // incoming rows (the size of the finest such level's block).
 bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *plans, size_t *total,
-              bool allow_pairs = false)
+              bool allow_pairs = false, bool tuned_layout_only = false)
 {
     size_t off = 0;
     for (int i = 0; i < count; ++i) {
@@ -137,6 +137,7 @@ bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
         if (pm_from < 0 && !(p->variant == 0 && tuned_choice(q.width, q.height, q.num_labels, p->msg_dtype,
                                                              p->levels, &pm_from, &tv)))
             pm_from = default_pm_from(q.width, q.height, q.num_labels, p->levels, p->msg_dtype);
+        if (tuned_layout_only) tv = 0;
         // A forward call that saves states for the adjoint stores them
         // pixel-major (or label-major when asked with pm_from = levels), the
         // layouts the two adjoints read.
@@ -432,7 +433,15 @@ bool plan_run(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
     *batch = batched(plans, count, *p);
     if (!plan_all(probs, count, p, plans, total, true)) return false;
     if (*batch) {
-        const bool pairs = batch_pairs(plans, count, *p);
+        bool pairs = batch_pairs(plans, count, *p);
+        if (!pairs && p->variant == 0) {
+            // A tuned one-half-sweep variant of a single problem would take
+            // the whole batch off the fused pairs: inside a batch the table
+            // chooses the layouts only.
+            if (!plan_all(probs, count, p, plans, total, true, true)) return false;
+            pairs = batch_pairs(plans, count, *p);
+            if (!pairs && !plan_all(probs, count, p, plans, total, true)) return false;
+        }
         // Checkpoints are saved by the fused pairs only; without them each
         // problem runs on its own.
         if (!pairs && p->checkpoint_every > 0) {
