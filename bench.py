@@ -719,7 +719,8 @@ def form_counters(args):
 def form_ceiling(args):
     """Practical bandwidth ceiling for the level-0 launches' read/write mixes:
     bp_stream_probe moves the same bytes in 16-byte accesses (no BP work),
-    timed with HIP events on its stream, median of 20.  Mixes at the
+    timed with HIP events on its stream around 20 back-to-back launches (as
+    the BP launches run), median of 5 such batches.  Mixes at the
     benchmarked 676x380x64 level 0: a single half-sweep (reads 164.4 MB,
     writes 131.5 MB), a fused pair (reads both costs and colour 0's rows,
     197.3 MB, writes colour 0's rows, 131.5 MB), and a plain 1:1 copy."""
@@ -750,13 +751,14 @@ def form_ceiling(args):
         for _ in range(3):
             once()
         times = []
-        for _ in range(20):
+        for _ in range(5):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            once()
+            for _ in range(20):
+                once()
             e1.record()
             torch.cuda.synchronize()
-            times.append(e0.elapsed_time(e1))
+            times.append(e0.elapsed_time(e1) / 20)
         ms = float(np.median(times))
         out[name] = {"read_bytes": rb, "write_bytes": wb, "us": round(ms * 1e3, 2),
                      "GBps": round((rb + wb) / (ms * 1e-3) / 1e9, 1),
