@@ -229,32 +229,35 @@ __device__ __forceinline__ float seg_from_upper(float v, float ident, int s)
     return r;
 }
 
-// Minimum scans of a whole 16-lane row written as DPP minimum instructions
-// (the compiler emits a copy, a DPP move and a minimum per step).  A lane
-// whose source lane lies outside the row is not written by a DPP operation
-// without bound_ctrl, so it keeps its own value, which is what an inclusive
-// minimum scan needs there.  Every DPP read of a register written by the
-// previous VALU instruction needs two wait states, which the compiler cannot
-// see inside the asm: each step is preceded by s_nop 1, and the block ends
-// with one for a DPP read that may follow it.  The values are never NaN.
-__device__ __forceinline__ float row_prefix_min16(float v)
+// The three DPP chains of one message's transform over a whole 16-lane row,
+// written as DPP minimum instructions and interleaved: p becomes the inclusive
+// prefix minimum over lanes 0..s, q the inclusive suffix minimum over lanes
+// s..15, and m the row's minimum on every lane.  A lane whose source lane lies
+// outside the row is not written by a shifting DPP operation without
+// bound_ctrl, so it keeps its own value, which is what an inclusive scan needs
+// there; the butterfly's sources are all inside the row.  A DPP read of a
+// register written by a VALU instruction needs two wait states, which the
+// compiler cannot see inside the asm: within the block the other two chains'
+// instructions provide them, an s_nop 1 covers a register written just before
+// the block, and another one a DPP read just after it.  The values are never
+// NaN.
+__device__ __forceinline__ void row_scans16(float &p, float &q, float &m)
 {
-    asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
-                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
-                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\ts_nop 1"
-                 : "+v"(v));
-    return v;
-}
-
-__device__ __forceinline__ float row_suffix_min16(float v)
-{
-    asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shl:1 row_mask:0xf bank_mask:0xf\n\t"
-                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shl:2 row_mask:0xf bank_mask:0xf\n\t"
-                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shl:4 row_mask:0xf bank_mask:0xf\n\t"
-                 "s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shl:8 row_mask:0xf bank_mask:0xf\n\ts_nop 1"
-                 : "+v"(v));
-    return v;
+    asm volatile("s_nop 1\n\t"
+                 "v_min_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %1, %1, %1 row_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %2, %2, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %1, %1, %1 row_shl:2 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %2, %2, %2 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %1, %1, %1 row_shl:4 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %2, %2, %2 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %1, %1, %1 row_shl:8 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %2, %2, %2 row_mirror row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1"
+                 : "+v"(p), "+v"(q), "+v"(m));
 }
 
 // Minimum over aligned groups of SEG lanes (2, 4, 8 or 16), every lane ending
@@ -281,7 +284,6 @@ __device__ __forceinline__ float seg_allmin(float v)
 template <int SEG>
 __device__ __forceinline__ float seg_prefix_min(float v, int s)
 {
-    if constexpr (SEG == 16) return row_prefix_min16(v);
     v = fminf(v, seg_from_lower<SEG, 1>(v, v, s));
     if constexpr (SEG > 2) v = fminf(v, seg_from_lower<SEG, 2>(v, v, s));
     if constexpr (SEG > 4) v = fminf(v, seg_from_lower<SEG, 4>(v, v, s));
@@ -294,12 +296,25 @@ __device__ __forceinline__ float seg_prefix_min(float v, int s)
 template <int SEG>
 __device__ __forceinline__ float seg_suffix_min(float v, int s)
 {
-    if constexpr (SEG == 16) return row_suffix_min16(v);
     v = fminf(v, seg_from_upper<SEG, 1>(v, v, s));
     if constexpr (SEG > 2) v = fminf(v, seg_from_upper<SEG, 2>(v, v, s));
     if constexpr (SEG > 4) v = fminf(v, seg_from_upper<SEG, 4>(v, v, s));
     if constexpr (SEG > 8) v = fminf(v, seg_from_upper<SEG, 8>(v, v, s));
     return v;
+}
+
+// The transform's three segment reductions at once: p the inclusive prefix
+// minimum, q the inclusive suffix minimum, m the segment minimum.
+template <int SEG>
+__device__ __forceinline__ void seg_scans(float &p, float &q, float &m, int s)
+{
+    if constexpr (SEG == 16) {
+        row_scans16(p, q, m);
+    } else {
+        p = seg_prefix_min<SEG>(p, s);
+        q = seg_suffix_min<SEG>(q, s);
+        m = seg_allmin<SEG>(m);
+    }
 }
 
 // Butterfly combine over the segment: every lane ends with op over all lanes.

@@ -13,18 +13,18 @@
 // labels), most of them index arithmetic and h sums repeated by each of the
 // four lane groups, and left the finest half-sweep bound by instruction issue;
 // the lane holding all four messages spends about 82.
-// The two passes of the transform are split into a lane-local pass over R
-// labels and a scan across the SEG lanes of the message:
-//   forward   A(f) = min_{g<=f} h(g) + lambda (f - g):
-//             local a(f) within the lane, then the value entering lane s is
-//             A(sR - 1) = lambda R (s - 1) + min_{s'<s} (e_s' - lambda R s'),
-//             e_s' = lane s' local value at its last label (exclusive DPP
+// The transform splits the minimum over g by where g lies:
+//   own lane  two lane-local passes over its R labels, forward
+//             a(f) = min(h(f), a(f - 1) + lambda) and backward
+//             b(f) = min(a(f), b(f + 1) + lambda);
+//   below     min_{s'<s} (a_s'(last) - lambda R s') + lambda R (s - 1) is the
+//             value entering the lane at label sR - 1 (exclusive DPP
 //             prefix-min over the segment);
-//   backward  B(f) = min_{g>=f} A(g) + lambda (g - f): local pass over A,
-//             then B((s+1)R) = min_{s'>s} (b_s' + lambda R s') - lambda R (s+1)
-//             (exclusive DPP suffix-min), b_s' = lane s' local value at its
-//             first label;
-//   out(f)    = min(B(f), min h + lambda tau) - min h   (DPP min-reduction).
+//   above     min_{s'>s} (b_s'(first) + lambda R s') - lambda R (s + 1) is the
+//             value entering at label (s + 1) R (exclusive DPP suffix-min);
+//   out(f)    = min(b(f), below + lambda (f - sR + 1), above + lambda (sR + R - f),
+//                   min h + lambda tau) - min h   (DPP min-reduction for min h).
+// The two scans and the reduction are independent and run interleaved.
 // With integer-valued data every step is exact, so the result equals the
 // sequential two-pass transform bit for bit.  Labels past L are +inf in h and
 // never influence real labels.

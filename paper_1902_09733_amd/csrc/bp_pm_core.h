@@ -15,6 +15,14 @@ namespace bpk {
 // labels [s R, s R + R) of lane s of its segment; labels at or past L must
 // hold +inf in h unless EXACT (L == SEG * R).
 //
+// The minimum over g splits by where g lies: in the lane itself (the two
+// lane-local passes), in a lower lane (the exclusive prefix scan of the local
+// forward values, entering at label s R - 1) or in a higher lane (the
+// exclusive suffix scan of the local backward values, entering at label
+// s R + R); the three candidates meet in one three-way minimum per label.  The
+// two scans and the segment minimum of h are independent, so they run
+// interleaved.
+//
 // Every product is rounded before it is added (no multiply-add contraction):
 // the compiler would otherwise fuse or not depending on what it hoists out of
 // the calling kernel's loops, and two kernels running this transform on the
@@ -31,35 +39,27 @@ __device__ __forceinline__ void pm_transform(float (&h)[R], int s, int f0, int L
         if (!EXACT && f0 + r >= L) h[r] = inf;
         hmin = fminf(hmin, h[r]);
     }
-    hmin = seg_allmin<SEG>(hmin);
-
-    // Forward pass.
-    float A[R];
+    // Lane-local forward and backward passes.
+    float A[R], B[R];
     A[0] = h[0];
 #pragma unroll
     for (int r = 1; r < R; ++r) A[r] = fminf(h[r], A[r - 1] + lam);
-    {
-        const float u = A[R - 1] - lamR * (float)s;
-        const float P = seg_prefix_min<SEG>(seg_from_lower<SEG, 1>(u, inf, s), s);
-        const float carry = P + lamR * (float)(s - 1);
-#pragma unroll
-        for (int r = 0; r < R; ++r) A[r] = fminf(A[r], carry + lam * (float)(r + 1));
-    }
-    // Backward pass.
-    float B[R];
     B[R - 1] = A[R - 1];
 #pragma unroll
     for (int r = R - 2; r >= 0; --r) B[r] = fminf(A[r], B[r + 1] + lam);
-    {
-        const float v = B[0] + lamR * (float)s;
-        const float Q = seg_suffix_min<SEG>(seg_from_upper<SEG, 1>(v, inf, s), s);
-        const float carry = Q - lamR * (float)(s + 1);
-#pragma unroll
-        for (int r = 0; r < R; ++r) B[r] = fminf(B[r], carry + lam * (float)(R - r));
-    }
+    // From the lanes below: min over s' < s of A_s'(last) - lambda R s';
+    // from the lanes above: min over s' > s of B_s'(first) + lambda R s'.
+    float P = seg_from_lower<SEG, 1>(A[R - 1] - lamR * (float)s, inf, s);
+    float Q = seg_from_upper<SEG, 1>(B[0] + lamR * (float)s, inf, s);
+    seg_scans<SEG>(P, Q, hmin, s);
+    const float lc = P + lamR * (float)(s - 1);
+    const float rc = Q - lamR * (float)(s + 1);
     const float cap = hmin + lt;
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[r] = fminf(B[r], cap) - hmin;
+    for (int r = 0; r < R; ++r) {
+        const float t = fminf(fminf(B[r], lc + lam * (float)(r + 1)), rc + lam * (float)(R - r));
+        out[r] = fminf(t, cap) - hmin;
+    }
 }
 
 // h for outgoing message k (to the neighbour on side k): the cost plus the
