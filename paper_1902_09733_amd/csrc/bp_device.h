@@ -303,6 +303,39 @@ __device__ __forceinline__ float seg_suffix_min(float v, int s)
     return v;
 }
 
+// The three-label transform's exchanges over a whole 16-lane row, interleaved
+// like row_scans16: `first` takes the minimum with `below` of the next lower
+// lane, `last` with `above` of the next higher lane (a lane at the row's edge
+// has none and keeps its value), and m becomes the row's minimum.
+__device__ __forceinline__ void row_near16(float &first, float &last, float &m, float below, float above)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_min_f32_dpp %2, %2, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %0, %3, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %1, %4, %1 row_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %2, %2, %2 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\t"
+                 "v_min_f32_dpp %2, %2, %2 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\t"
+                 "v_min_f32_dpp %2, %2, %2 row_mirror row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1"
+                 : "+v"(first), "+v"(last), "+v"(m)
+                 : "v"(below), "v"(above));
+}
+
+template <int SEG>
+__device__ __forceinline__ void seg_near(float &first, float &last, float &m, float below, float above, int s)
+{
+    if constexpr (SEG == 16) {
+        row_near16(first, last, m, below, above);
+    } else {
+        const float inf = __builtin_huge_valf();
+        first = fminf(first, seg_from_lower<SEG, 1>(below, inf, s));
+        last = fminf(last, seg_from_upper<SEG, 1>(above, inf, s));
+        m = seg_allmin<SEG>(m);
+    }
+}
+
 // The transform's three segment reductions at once: p the inclusive prefix
 // minimum, q the inclusive suffix minimum, m the segment minimum.
 template <int SEG>

@@ -176,6 +176,7 @@ struct IterArgs {
     int L;                 // label count
     int ncomp;             // h * wh
     float lambda, lt;      // lambda and lambda * tau
+    int near;              // tau <= 2: the transform's three-label form
 };
 bp_status dispatch_iter_lm(const IterArgs &a, int fmt, int G, bool ro, hipStream_t s);
 
@@ -250,6 +251,7 @@ struct PairArgs {
     int src_parent, src_zero, write_c1;
     int L;
     float lambda, lt;
+    int near;              // tau <= 2: the transform's three-label form
     int tx, ty;            // tile (tx even)
     int tiles_x, ntiles, per_xcd;
     uint8_t *ck;           // checkpoint state in the level's layout that also receives phase 2's rows,

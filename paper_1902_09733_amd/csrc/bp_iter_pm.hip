@@ -24,7 +24,8 @@
 //             value entering at label (s + 1) R (exclusive DPP suffix-min);
 //   out(f)    = min(b(f), below + lambda (f - sR + 1), above + lambda (sR + R - f),
 //                   min h + lambda tau) - min h   (DPP min-reduction for min h).
-// The two scans and the reduction are independent and run interleaved.
+// The two scans and the reduction are independent and run interleaved.  When
+// tau <= 2 the transform reduces to its three-label form (bp_pm_core.h).
 // With integer-valued data every step is exact, so the result equals the
 // sequential two-pass transform bit for bit.  Labels past L are +inf in h and
 // never influence real labels.
@@ -90,7 +91,7 @@ __device__ __forceinline__ void pm_sweep4(const IterArgs &a, uint32_t block)
         } else {
             pm_h<R>(c, m, k, h);
         }
-        pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, out);
+        pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, a.near != 0, out);
         int nx, ny;
         if (pm_receiver(k, x, y, a.w, a.h, nx, ny)) {
             const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
@@ -180,7 +181,7 @@ __device__ __forceinline__ void pm_sweep(const IterArgs &a, uint32_t block)
     }
 
     float out[R];
-    pm_transform<SEG, R, EXACT>(h, s, f0, a.L, lam, a.lt, out);
+    pm_transform<SEG, R, EXACT>(h, s, f0, a.L, lam, a.lt, a.near != 0, out);
 
     // Receiver of message k and its slot k^1.
     int nx = x, ny = y;

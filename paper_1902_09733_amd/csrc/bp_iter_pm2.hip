@@ -123,7 +123,7 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
                 if (!(ok && nx >= tx0 && nx < tx0 + TX && ny >= ty0 && ny < ty0 + TY)) continue;
                 float h[R], out[R];
                 pm_h<R>(c[u], m[u], k, h);
-                pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, out);
+                pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, a.near != 0, out);
                 const int slot = (ny - ty0) * HX + ((nx - tx0) >> 1);
                 uint8_t *row = lds + (((uint32_t)slot * 4u + (uint32_t)(k ^ 1)) * lp + f0) * S::bytes;
                 if constexpr (S::bytes == 4) {
@@ -202,7 +202,7 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
                 if (!pm_receiver(k, x, y, a.w, a.h, nx, ny)) continue;
                 float h[R], out[R];
                 pm_h<R>(c[u], m, k, h);
-                pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, out);
+                pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, a.near != 0, out);
                 const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
                 const uint32_t off = ((uint32_t)(k ^ 1) * a.blk + dj * lp + (uint32_t)f0) * S::bytes;
                 st_row<S, R>(rd, off, out);

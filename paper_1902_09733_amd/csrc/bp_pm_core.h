@@ -27,10 +27,52 @@ namespace bpk {
 // the compiler would otherwise fuse or not depending on what it hoists out of
 // the calling kernel's loops, and two kernels running this transform on the
 // same data (one half-sweep per launch, or two) must agree bit for bit.
+//
+// When tau <= 2 (`near`) a label g two or more labels from f costs
+// h(g) + lambda min(|f - g|, tau) = h(g) + lambda tau >= min h + lt, never less
+// than the truncation cap, so only f - 1, f and f + 1 remain:
+//   out(f) = min(h(f), h(f - 1) + lambda, h(f + 1) + lambda, min h + lt) - min h,
+// the same function without the passes and scans (pm_transform_near).
 template <int SEG, int R, bool EXACT>
-__device__ __forceinline__ void pm_transform(float (&h)[R], int s, int f0, int L, float lam, float lt, float (&out)[R])
+__device__ __forceinline__ void pm_transform_near(float (&h)[R], int s, int f0, int L, float lam, float lt,
+                                                  float (&out)[R])
 {
 #pragma clang fp contract(off)
+    static_assert(R >= 2, "a lane holds at least two labels");
+    const float inf = __builtin_huge_valf();
+    float hmin = inf;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!EXACT && f0 + r >= L) h[r] = inf;
+        hmin = fminf(hmin, h[r]);
+    }
+    float hp[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) hp[r] = h[r] + lam;
+    // The lane's first label also sees the last label of the lane below, its
+    // last label the first of the lane above.
+    float first = h[0], last = h[R - 1];
+    seg_near<SEG>(first, last, hmin, hp[R - 1], hp[0], s);
+    const float cap = hmin + lt;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float v;
+        if (r == 0) v = fminf(first, hp[1]);
+        else if (r == R - 1) v = fminf(last, hp[R - 2]);
+        else v = fminf(fminf(h[r], hp[r - 1]), hp[r + 1]);
+        out[r] = fminf(v, cap) - hmin;
+    }
+}
+
+template <int SEG, int R, bool EXACT>
+__device__ __forceinline__ void pm_transform(float (&h)[R], int s, int f0, int L, float lam, float lt, bool near,
+                                             float (&out)[R])
+{
+#pragma clang fp contract(off)
+    if (near) {
+        pm_transform_near<SEG, R, EXACT>(h, s, f0, L, lam, lt, out);
+        return;
+    }
     const float inf = __builtin_huge_valf();
     const float lamR = lam * (float)R;
     float hmin = inf;
