@@ -2,6 +2,7 @@
 // planning and the launch sequence of the hierarchical BP path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -123,6 +124,36 @@ bool level_pairs(const Plan &pl, int l, int K)
     return pl.pairs && pl.lv[l].layout == PIXEL_MAJOR && K >= 2 && pair_supported(S, R);
 }
 
+// Whether a pair's finest-level cost is stored as FP16: its values are the
+// integers 0..255 (grey, or the rounded channel mean) and the truncation, all
+// exact in FP16 when the truncation is, and the level is written by the fused
+// level-0/1 cost kernel (two pixel-major finest levels), whose level 1 and the
+// pyramid above it stay FP32.  Every kernel that reads a pixel-major level's
+// cost reads either format.
+static bool fp16_exact(float t)
+{
+    if (!(t >= 0.0f) || t > 65504.0f) return false;
+    if (t == 0.0f) return true;
+    int e;
+    std::frexp(t, &e);                       // t = m 2^e, m in [0.5, 1)
+    const int lsb = std::max(e - 11, -24);   // 11 significant bits; subnormal step 2^-24
+    return std::ldexp(std::nearbyint(std::ldexp(t, -lsb)), lsb) == t;
+}
+
+static bool pair_cost16(const bp_pair &pr, const Plan &pl, int K)
+{
+    if (!((pr.channels == 1 || pr.rgb_mode == 0) && fp16_exact(pr.data_trunc) && pl.levels >= 2 &&
+          pl.lv[0].layout == PIXEL_MAJOR && pl.lv[1].layout == PIXEL_MAJOR))
+        return false;
+    // Only the fused pairs and the readout read it: the finest level runs
+    // pairs alone (K even, and no single half-sweeps ahead of the first pair
+    // after a materialised parent copy).
+    if (!level_pairs(pl, 0, K) || (K & 1)) return false;
+    const Level &c = pl.lv[0], &pa = pl.lv[1];
+    const bool fusable = K >= 2 && c.fmt == pa.fmt;
+    return fusable || ((K / 2) & 1) == 0;
+}
+
 // Problem plans laid out back to back in the workspace.  With allow_pairs,
 // problems that leave the kernel choice to the library run pixel-major levels
 // as fused pairs of half-sweeps, which need a second buffer of colour 0's
@@ -171,6 +202,7 @@ bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
         // reads zero messages in place of the state, so only the out-of-grid
         // slots need zeroing there.
         plans[i].zero_coarsest = !level_pairs(plans[i], plans[i].levels - 1, p->iters_per_level);
+        plans[i].lv[0].cost16 = !q.cost && pair_cost16(*q.pair, plans[i], p->iters_per_level);
         off += plans[i].bytes;
     }
     *total = align_up(off);
@@ -208,7 +240,8 @@ double sweep_bytes(const Plan &pl, int l)
 double pair_bytes(const Plan &pl, int l, bool ends)
 {
     const double nl = (double)pl.lv[l].w * pl.lv[l].h * pl.L, mb = fmt_bytes(pl.lv[l].fmt);
-    return nl * (4.0 + 4.0 * mb + (ends ? 2.0 * mb : 0.0));
+    const double cb = pl.lv[l].cost16 ? 2.0 : 4.0;   // both colours' costs
+    return nl * (cb + 4.0 * mb + (ends ? 2.0 * mb : 0.0));
 }
 
 // Runs the whole hierarchical BP of one problem.
@@ -450,6 +483,12 @@ bool plan_run(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
         }
         if (!pairs && !plan_all(probs, count, p, plans, total)) return false;
         if (table) *table = batch_table_bytes(count, p->levels, p->iters_per_level, pairs);
+        // A batched launch covers several problems with one kernel, so their
+        // finest levels share the cost storage: FP16 only when every problem's
+        // allows it (and never for the one-half-sweep kernels).
+        bool all16 = pairs;
+        for (int i = 0; i < count; ++i) all16 = all16 && plans[i].lv[0].cost16;
+        for (int i = 0; i < count; ++i) plans[i].lv[0].cost16 = all16;
     }
     return true;
 }
@@ -635,7 +674,8 @@ bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *
                         st = dispatch_iter_pm2(host[start[slot]].a, fmt, cls_S[c], cls_R[c], ro[slot], s);
                     else
                         st = launch_iteration_pair_batch(dev + start[slot], num[slot], blocks[slot], lds[slot], fmt,
-                                                         cls_S[c], cls_R[c], exact[slot], ro[slot], s);
+                                                         cls_S[c], cls_R[c], exact[slot], ro[slot],
+                                                         host[start[slot]].a.cost16 != 0, s);
                 }
             // The group's readout and export while its state is in the cache.
             if (l == 0 && st == BP_OK) st = finish_batched(probs, count, plans, p, fuse, ws, s, grp, g);

@@ -270,10 +270,12 @@ __global__ void __launch_bounds__(256) k_cost_level0(const uint32_t *__restrict_
 // vector, and stores their sum, added in the order (0,0), (1,0), (0,1), (1,1)
 // as the separate pyramid step does.  Labels past L (inside the level's
 // padded row) get the truncation value; no kernel reads them.
-template <int C>
+// H16: level 0 is stored as FP16 (four labels in one 8-byte store; the plan
+// chooses it only where every value is exact in FP16).
+template <int C, bool H16>
 __global__ void __launch_bounds__(256) k_cost_level01(const uint32_t *__restrict__ packed, int w, int h, int L,
                                                      float trunc, int rgb_mode, int xb1, int q4, int wh0,
-                                                     int64_t blk0, int64_t ps0, float *__restrict__ out0, int w1,
+                                                     int64_t blk0, int64_t ps0, void *__restrict__ out0, int w1,
                                                      int wh1, int64_t blk1, int64_t ps1, float *__restrict__ out1)
 {
     extern __shared__ uint32_t lds[];
@@ -318,8 +320,14 @@ __global__ void __launch_bounds__(256) k_cost_level01(const uint32_t *__restrict
                     const int f = f0 + e;
                     v[e] = (f < L && x - f >= 0) ? ad_cost<C>(lv, rpx[xl + (L - 1) - f], rgb_mode, trunc) : trunc;
                 }
-                *(float4 *)(out0 + (int64_t)((x + y) & 1) * blk0 + (int64_t)(y * wh0 + (x >> 1)) * ps0 + f0) =
-                    make_float4(v[0], v[1], v[2], v[3]);
+                const int64_t e0 = (int64_t)((x + y) & 1) * blk0 + (int64_t)(y * wh0 + (x >> 1)) * ps0 + f0;
+                if constexpr (H16) {
+                    typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+                    const h4_t hv = {(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
+                    *(h4_t *)((_Float16 *)out0 + e0) = hv;
+                } else {
+                    *(float4 *)((float *)out0 + e0) = make_float4(v[0], v[1], v[2], v[3]);
+                }
                 acc.x += v[0];
                 acc.y += v[1];
                 acc.z += v[2];
@@ -367,13 +375,19 @@ bp_status launch_pair_cost(const bp_pair &pr, const Plan &p, uint8_t *ws, hipStr
         const int xb1 = 16;   // 16: 19.0 us at 676x380x64, against 19.9 (32) and 20.5 (64)
         const dim3 grid1((unsigned)((v1.w + xb1 - 1) / xb1), (unsigned)v1.h);
         const size_t lds1 = sizeof(uint32_t) * (size_t)2 * (2 * xb1 + 2 * xb1 + L - 1);
-        float *out0 = (float *)(ws + v.cost_off), *out1 = (float *)(ws + v1.cost_off);
-        if (pr.channels == 1)
-            k_cost_level01<1><<<grid1, 256, lds1, st>>>(packed, w, h, L, pr.data_trunc, pr.rgb_mode, xb1, q4, v.wh,
-                                                        v.blk, v.ps, out0, v1.w, v1.wh, v1.blk, v1.ps, out1);
-        else
-            k_cost_level01<3><<<grid1, 256, lds1, st>>>(packed, w, h, L, pr.data_trunc, pr.rgb_mode, xb1, q4, v.wh,
-                                                        v.blk, v.ps, out0, v1.w, v1.wh, v1.blk, v1.ps, out1);
+        void *out0 = ws + v.cost_off;
+        float *out1 = (float *)(ws + v1.cost_off);
+#define BP_COST01(CV, HV)                                                                                   \
+    k_cost_level01<CV, HV><<<grid1, 256, lds1, st>>>(packed, w, h, L, pr.data_trunc, pr.rgb_mode, xb1, q4, v.wh, \
+                                                     v.blk, v.ps, out0, v1.w, v1.wh, v1.blk, v1.ps, out1)
+        if (pr.channels == 1) {
+            if (v.cost16) BP_COST01(1, true);
+            else BP_COST01(1, false);
+        } else {
+            if (v.cost16) BP_COST01(3, true);
+            else BP_COST01(3, false);
+        }
+#undef BP_COST01
         *levels_done = 2;
         return launch_status();
     }

@@ -145,6 +145,15 @@ __device__ __forceinline__ void ld_row(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
     }
 }
 
+// R cost values of a pixel-major level at element offset e: FP32, or FP16
+// where the level stores its cost in half precision (c16, uniform).
+template <int R>
+__device__ __forceinline__ void ld_cost(__amdgpu_buffer_rsrc_t r, uint32_t e, bool c16, float (&v)[R])
+{
+    if (c16) ld_row<StoreF16, R>(r, e * 2u, v);
+    else ld_row<StoreF32, R>(r, e * 4u, v);
+}
+
 template <typename S, int R>
 __device__ __forceinline__ void st_row(__amdgpu_buffer_rsrc_t r, uint32_t voff, const float (&v)[R])
 {

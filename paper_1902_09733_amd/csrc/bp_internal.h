@@ -41,6 +41,8 @@ struct Level {
     int64_t blk, ls, ps;  // element strides: per (colour[, slot]) block, per label, per pixel
     int fmt;              // message storage format at this level
     size_t cost_off;      // byte offset of this level's cost in the workspace
+    bool cost16;          // cost stored as FP16 at the same element offsets (level 0 of a pair whose
+                          // costs FP16 holds exactly); FP32 otherwise
     size_t msg_off;       // byte offset of this level's messages
     size_t cost_bytes, msg_bytes;
 };
@@ -252,6 +254,7 @@ struct PairArgs {
     int L;
     float lambda, lt;
     int near;              // tau <= 2: the transform's three-label form
+    int cost16;            // the level's cost is stored as FP16 (selects the kernel)
     int tx, ty;            // tile (tx even)
     int tiles_x, ntiles, per_xcd;
     uint8_t *ck;           // checkpoint state in the level's layout that also receives phase 2's rows,
@@ -288,7 +291,7 @@ int pair_blocks(const PairArgs &a);
 bp_status launch_write_pair_entries(PairEntry *dst, const PairEntry *src, int n, hipStream_t s);
 // exact: every entry's label count equals its lane split's S * R.
 bp_status launch_iteration_pair_batch(const PairEntry *tab, int n, int blocks, size_t lds, int fmt, int S, int R,
-                                      bool exact, bool ro, hipStream_t s);
+                                      bool exact, bool ro, bool cost16, hipStream_t s);
 
 // Pixel-major kernel variants (1 default split; 2 half the lanes per message,
 // twice the labels per lane; 3 and 4 the same with each lane group reading

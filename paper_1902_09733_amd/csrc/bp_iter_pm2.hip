@@ -36,6 +36,9 @@
 // state (`ck_c1`; the level's own colour-1 block then need not be written
 // when nothing else reads it).
 //
+// The level's cost is read as FP32, or as FP16 (C16) where the plan keeps the
+// finest level's cost in half precision (a pair's integer costs, exact there).
+//
 // Per message the arithmetic is the one-half-sweep kernel's variant 1
 // (bp_pm_core.h: h summed in slot order, the same transform), so results
 // equal two launches of that kernel bit for bit.
@@ -51,7 +54,7 @@ namespace bpk {
 // incoming rows, and computes its four outgoing messages in turn (as the
 // one-half-sweep kernel's variant 1).  U pixels per lane group are loaded
 // before any is computed, to keep more rows in flight per wave.
-template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U>
+template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U, bool C16>
 __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
 {
     // lds: [tile colour-1 pixel][slot][lp] in the storage format
@@ -96,7 +99,7 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
                 sc = (sx + sy) & 1;
                 sj = sy * a.src_wh + (sx >> 1);
             }
-            ld_row<StoreF32, R>(rc, ((uint32_t)j * lp + (uint32_t)f0) * 4u, c[u]);
+            ld_cost<R>(rc, (uint32_t)j * lp + (uint32_t)f0, C16, c[u]);
             const uint32_t base = (uint32_t)sj * a.sps + (uint32_t)f0;
             // Slots from outside the grid are zero; they are not read, since
             // the second buffer never holds them.
@@ -162,7 +165,7 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
             live[u] = i < n2 && x < a.w && y < a.h;
             if (!live[u]) continue;
             const int j = y * a.wh + (x >> 1);
-            ld_row<StoreF32, R>(rc, ((a.blk + (uint32_t)j * lp) + (uint32_t)f0) * 4u, c[u]);
+            ld_cost<R>(rc, (a.blk + (uint32_t)j * lp) + (uint32_t)f0, C16, c[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -212,18 +215,18 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
     }
 }
 
-template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U>
+template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U, bool C16>
 __global__ void __launch_bounds__(NT) k_iter_pm2(const PairArgs a)
 {
     extern __shared__ uint8_t lds[];
-    pm2_tile<SEG, R, S, EXACT, RO, NT, U>(a, (int)blockIdx.x, lds);
+    pm2_tile<SEG, R, S, EXACT, RO, NT, U, C16>(a, (int)blockIdx.x, lds);
 }
 
 // Batched fused pair: block b belongs to the last table entry whose first
 // block is <= b; every entry's first block is a multiple of 8, so the XCD
 // grouping of tiles holds within each problem.  EXACT: every entry's label
 // count fills its lane split.
-template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U>
+template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U, bool C16>
 __global__ void __launch_bounds__(NT) k_iter_pm2_batch(const PairEntry *__restrict__ tab, int n)
 {
     extern __shared__ uint8_t lds[];
@@ -234,7 +237,7 @@ __global__ void __launch_bounds__(NT) k_iter_pm2_batch(const PairEntry *__restri
         else hi = mid - 1;
     }
     const PairArgs a = tab[lo].a;
-    pm2_tile<SEG, R, S, EXACT, RO, NT, U>(a, (int)blockIdx.x - tab[lo].block0, lds);
+    pm2_tile<SEG, R, S, EXACT, RO, NT, U, C16>(a, (int)blockIdx.x - tab[lo].block0, lds);
 }
 
 // Table of batch entries written from kernel arguments (capture-safe).
@@ -291,19 +294,20 @@ template <int SEG, int R, typename S, bool EXACT, bool RO>
 static bp_status launch_pm2(const PairArgs &a, size_t lds, hipStream_t st)
 {
     const unsigned grid = (unsigned)pair_blocks(a);
-    k_iter_pm2<SEG, R, S, EXACT, RO, kPairThreads, 1><<<grid, kPairThreads, lds, st>>>(a);
+    if (a.cost16) k_iter_pm2<SEG, R, S, EXACT, RO, kPairThreads, 1, true><<<grid, kPairThreads, lds, st>>>(a);
+    else k_iter_pm2<SEG, R, S, EXACT, RO, kPairThreads, 1, false><<<grid, kPairThreads, lds, st>>>(a);
     return launch_status();
 }
 
-template <typename S, bool EXACT>
+template <typename S, bool EXACT, bool C16>
 static bp_status dispatch_pm2_batch(const PairEntry *tab, int n, int blocks, size_t lds, int SEGV, int R, bool ro,
                                     hipStream_t st)
 {
-#define BP_PM2B(SV, RV)                                                                                        \
-    if (SEGV == SV && R == RV) {                                                                               \
-        if (ro) k_iter_pm2_batch<SV, RV, S, EXACT, true, kPairThreads, 1><<<blocks, kPairThreads, lds, st>>>(tab, n);  \
-        else k_iter_pm2_batch<SV, RV, S, EXACT, false, kPairThreads, 1><<<blocks, kPairThreads, lds, st>>>(tab, n);    \
-        return launch_status();                                                                                \
+#define BP_PM2B(SV, RV)                                                                                          \
+    if (SEGV == SV && R == RV) {                                                                                 \
+        if (ro) k_iter_pm2_batch<SV, RV, S, EXACT, true, kPairThreads, 1, C16><<<blocks, kPairThreads, lds, st>>>(tab, n); \
+        else k_iter_pm2_batch<SV, RV, S, EXACT, false, kPairThreads, 1, C16><<<blocks, kPairThreads, lds, st>>>(tab, n);  \
+        return launch_status();                                                                                  \
     }
     BP_PM2B(4, 4) BP_PM2B(8, 4) BP_PM2B(16, 4) BP_PM2B(16, 6) BP_PM2B(16, 8) BP_PM2B(16, 12) BP_PM2B(16, 16)
 #undef BP_PM2B
@@ -312,20 +316,24 @@ static bp_status dispatch_pm2_batch(const PairEntry *tab, int n, int blocks, siz
 
 template <typename S>
 static bp_status dispatch_pm2_batch_exact(const PairEntry *tab, int n, int blocks, size_t lds, int SEGV, int R,
-                                          bool exact, bool ro, hipStream_t st)
+                                          bool exact, bool ro, bool c16, hipStream_t st)
 {
-    return exact ? dispatch_pm2_batch<S, true>(tab, n, blocks, lds, SEGV, R, ro, st)
-                 : dispatch_pm2_batch<S, false>(tab, n, blocks, lds, SEGV, R, ro, st);
+    if (c16)
+        return exact ? dispatch_pm2_batch<S, true, true>(tab, n, blocks, lds, SEGV, R, ro, st)
+                     : dispatch_pm2_batch<S, false, true>(tab, n, blocks, lds, SEGV, R, ro, st);
+    return exact ? dispatch_pm2_batch<S, true, false>(tab, n, blocks, lds, SEGV, R, ro, st)
+                 : dispatch_pm2_batch<S, false, false>(tab, n, blocks, lds, SEGV, R, ro, st);
 }
 
+// Every entry of a launch has the same cost storage (c16).
 bp_status launch_iteration_pair_batch(const PairEntry *tab, int n, int blocks, size_t lds, int fmt, int SEGV, int R,
-                                      bool exact, bool ro, hipStream_t st)
+                                      bool exact, bool ro, bool c16, hipStream_t st)
 {
     if (lds > 65536) return BP_ERR_UNSUPPORTED;
     switch (fmt) {
-    case FMT_F16: return dispatch_pm2_batch_exact<StoreF16>(tab, n, blocks, lds, SEGV, R, exact, ro, st);
-    case FMT_BF16: return dispatch_pm2_batch_exact<StoreBF16>(tab, n, blocks, lds, SEGV, R, exact, ro, st);
-    default: return dispatch_pm2_batch_exact<StoreF32>(tab, n, blocks, lds, SEGV, R, exact, ro, st);
+    case FMT_F16: return dispatch_pm2_batch_exact<StoreF16>(tab, n, blocks, lds, SEGV, R, exact, ro, c16, st);
+    case FMT_BF16: return dispatch_pm2_batch_exact<StoreBF16>(tab, n, blocks, lds, SEGV, R, exact, ro, c16, st);
+    default: return dispatch_pm2_batch_exact<StoreF32>(tab, n, blocks, lds, SEGV, R, exact, ro, c16, st);
     }
 }
 

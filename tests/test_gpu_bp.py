@@ -382,6 +382,29 @@ def test_pair_input_truncations(dev, trunc, levels):
         assert np.abs(g["msgs"] - o["msgs"]).max() <= MSG_TOL_REL * 10.0 * 2.0
 
 
+@pytest.mark.parametrize("trunc", [20.0, 20.5, 20.3, 300.0, 65504.0, 70000.0, 0.0])
+@pytest.mark.parametrize("ch,mode", [(1, 0), (3, 0), (3, 1)])
+def test_pair_cost_storage_invisible(dev, trunc, ch, mode):
+    """On the pair route the finest level may keep its cost in FP16 (integer
+    costs and a truncation FP16 holds exactly: 20, 20.5, 300, 65504, 0) or in
+    FP32 (20.3, 70000, or the exact RGB mean); either way the messages and
+    labels equal the volume route's, which is always FP32, bit for bit."""
+    bp = bp_mod()
+    w, h, s, L = 58, 34, 2, 24
+    rng = np.random.default_rng(int(trunc * 10) + 7 * ch + mode)
+    shp = (h * s, w * s) + ((3,) if ch == 3 else ())
+    left_np = rng.integers(0, 256, size=shp, dtype=np.uint8)
+    right_np = np.roll(left_np, 3, axis=1) // 2 + rng.integers(0, 128, size=shp, dtype=np.uint8)
+    left, right = torch.from_numpy(left_np).to(dev), torch.from_numpy(right_np).to(dev)
+    for levels, K in ((3, 4), (2, 5)):
+        p = bp.BPParams(levels=levels, iters=K, lam=3.5, tau=1.5)
+        a = bp.run(bp.cost_volume(left, right, L, trunc, downsample=s, rgb_mode=mode), p, want_msgs=True)
+        b = bp.run(bp.Pair(left, right, L, trunc, downsample=s, rgb_mode=mode), p, want_msgs=True)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(b["disp"].cpu().numpy(), a["disp"].cpu().numpy())
+        np.testing.assert_array_equal(b["msgs"].cpu().numpy(), a["msgs"].cpu().numpy())
+
+
 def test_pair_input_unaligned_images(dev):
     """Images at an odd byte address take the byte-load downsampling path."""
     bp = bp_mod()
