@@ -725,7 +725,9 @@ def form_ceiling(args):
     the BP launches run), median of 5 such batches.  Mixes at the
     benchmarked 676x380x64 level 0: a single half-sweep (reads 164.4 MB,
     writes 131.5 MB), a fused pair (reads both costs and colour 0's rows,
-    197.3 MB, writes colour 0's rows, 131.5 MB), and a plain 1:1 copy."""
+    197.3 MB, writes colour 0's rows, 131.5 MB), the fused pair with the
+    finest level's cost in FP16 (reads 164.4 MB, writes 131.5 MB: the same
+    volumes as the single half-sweep), and a plain 1:1 copy."""
     import ctypes
 
     import torch
@@ -736,6 +738,7 @@ def form_ceiling(args):
     mixes = {
         "single_half_sweep": (nl * (4 + 16) // 2, nl * 16 // 2),
         "fused_pair": (nl * (4 + 8), nl * 8),
+        "fused_pair_cost16": (nl * (2 + 8), nl * 8),
         "copy_256MiB": (256 << 20, 256 << 20),
     }
     dev = torch.device("cuda:0")
