@@ -82,24 +82,27 @@ __device__ __forceinline__ void pm_sweep4(const IterArgs &a, uint32_t block)
     constexpr bool H4 = R <= 8;
     float h4[H4 ? 4 : 1][R];
     if constexpr (H4) pm_h4<R>(c, m, h4);
+    with_near(a.near != 0, [&](auto near_form) {
+        constexpr bool NEAR = decltype(near_form)::value;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        float h[R], out[R];
-        if constexpr (H4) {
+        for (int k = 0; k < 4; ++k) {
+            float h[R], out[R];
+            if constexpr (H4) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) h[r] = h4[k][r];
-        } else {
-            pm_h<R>(c, m, k, h);
+                for (int r = 0; r < R; ++r) h[r] = h4[k][r];
+            } else {
+                pm_h<R>(c, m, k, h);
+            }
+            pm_transform<SEG, R, EXACT, NEAR>(h, s, f0, a.L, a.lambda, a.lt, out);
+            int nx, ny;
+            if (pm_receiver(k, x, y, a.w, a.h, nx, ny)) {
+                const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
+                st_row<S, R>(rm, (((uint32_t)(a.colour ^ 1) * 4u + (uint32_t)(k ^ 1)) * a.blk + dj * a.lp +
+                                  (uint32_t)f0) * S::bytes,
+                             out);
+            }
         }
-        pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, a.near != 0, out);
-        int nx, ny;
-        if (pm_receiver(k, x, y, a.w, a.h, nx, ny)) {
-            const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
-            st_row<S, R>(rm, (((uint32_t)(a.colour ^ 1) * 4u + (uint32_t)(k ^ 1)) * a.blk + dj * a.lp +
-                              (uint32_t)f0) * S::bytes,
-                         out);
-        }
-    }
+    });
 }
 
 // Variants 3 to 5: a sender pixel owns 4 SEG lanes, SEG per outgoing message.
@@ -181,7 +184,8 @@ __device__ __forceinline__ void pm_sweep(const IterArgs &a, uint32_t block)
     }
 
     float out[R];
-    pm_transform<SEG, R, EXACT>(h, s, f0, a.L, lam, a.lt, a.near != 0, out);
+    if (a.near) pm_transform<SEG, R, EXACT, true>(h, s, f0, a.L, lam, a.lt, out);
+    else pm_transform<SEG, R, EXACT, false>(h, s, f0, a.L, lam, a.lt, out);
 
     // Receiver of message k and its slot k^1.
     int nx = x, ny = y;

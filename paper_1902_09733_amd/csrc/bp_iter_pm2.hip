@@ -117,33 +117,36 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (!live[u]) continue;
+            with_near(a.near != 0, [&](auto near_form) {
+                constexpr bool NEAR = decltype(near_form)::value;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                int nx, ny;
-                const bool ok = pm_receiver(k, xs[u], ys[u], a.w, a.h, nx, ny);
-                // Only receivers inside the tile (colour 1 by construction);
-                // the same for every lane of the pixel.
-                if (!(ok && nx >= tx0 && nx < tx0 + TX && ny >= ty0 && ny < ty0 + TY)) continue;
-                float h[R], out[R];
-                pm_h<R>(c[u], m[u], k, h);
-                pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, a.near != 0, out);
-                const int slot = (ny - ty0) * HX + ((nx - tx0) >> 1);
-                uint8_t *row = lds + (((uint32_t)slot * 4u + (uint32_t)(k ^ 1)) * lp + f0) * S::bytes;
-                if constexpr (S::bytes == 4) {
+                for (int k = 0; k < 4; ++k) {
+                    int nx, ny;
+                    const bool ok = pm_receiver(k, xs[u], ys[u], a.w, a.h, nx, ny);
+                    // Only receivers inside the tile (colour 1 by construction);
+                    // the same for every lane of the pixel.
+                    if (!(ok && nx >= tx0 && nx < tx0 + TX && ny >= ty0 && ny < ty0 + TY)) continue;
+                    float h[R], out[R];
+                    pm_h<R>(c[u], m[u], k, h);
+                    pm_transform<SEG, R, EXACT, NEAR>(h, s, f0, a.L, a.lambda, a.lt, out);
+                    const int slot = (ny - ty0) * HX + ((nx - tx0) >> 1);
+                    uint8_t *row = lds + (((uint32_t)slot * 4u + (uint32_t)(k ^ 1)) * lp + f0) * S::bytes;
+                    if constexpr (S::bytes == 4) {
 #pragma unroll
-                    for (int q = 0; q < R; ++q) ((float *)row)[q] = out[q];
-                } else {
+                        for (int q = 0; q < R; ++q) ((float *)row)[q] = out[q];
+                    } else {
 #pragma unroll
-                    for (int q = 0; q < R / 2; ++q)
-                        ((uint32_t *)row)[q] = S::pack2(out[2 * q], out[2 * q + 1]);
+                        for (int q = 0; q < R / 2; ++q)
+                            ((uint32_t *)row)[q] = S::pack2(out[2 * q], out[2 * q + 1]);
+                    }
+                    if (a.write_c1 || a.ck_c1) {
+                        const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
+                        const uint32_t off = ((4u + (uint32_t)(k ^ 1)) * a.blk + dj * lp + (uint32_t)f0) * S::bytes;
+                        if (a.write_c1) st_row<S, R>(rm, off, out);
+                        if (a.ck_c1) st_row<S, R>(rk, off, out);
+                    }
                 }
-                if (a.write_c1 || a.ck_c1) {
-                    const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
-                    const uint32_t off = ((4u + (uint32_t)(k ^ 1)) * a.blk + dj * lp + (uint32_t)f0) * S::bytes;
-                    if (a.write_c1) st_row<S, R>(rm, off, out);
-                    if (a.ck_c1) st_row<S, R>(rk, off, out);
-                }
-            }
+            });
         }
     }
     __syncthreads();
@@ -199,18 +202,21 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
                 if (s == 0 && a.disp) a.disp[(int64_t)y * a.w + x] = bi;
                 if (s == 0 && a.soft) a.soft[(int64_t)y * a.w + x] = sv;
             }
+            with_near(a.near != 0, [&](auto near_form) {
+                constexpr bool NEAR = decltype(near_form)::value;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                int nx, ny;
-                if (!pm_receiver(k, x, y, a.w, a.h, nx, ny)) continue;
-                float h[R], out[R];
-                pm_h<R>(c[u], m, k, h);
-                pm_transform<SEG, R, EXACT>(h, s, f0, a.L, a.lambda, a.lt, a.near != 0, out);
-                const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
-                const uint32_t off = ((uint32_t)(k ^ 1) * a.blk + dj * lp + (uint32_t)f0) * S::bytes;
-                st_row<S, R>(rd, off, out);
-                if (a.ck) st_row<S, R>(rk, off, out);
-            }
+                for (int k = 0; k < 4; ++k) {
+                    int nx, ny;
+                    if (!pm_receiver(k, x, y, a.w, a.h, nx, ny)) continue;
+                    float h[R], out[R];
+                    pm_h<R>(c[u], m, k, h);
+                    pm_transform<SEG, R, EXACT, NEAR>(h, s, f0, a.L, a.lambda, a.lt, out);
+                    const uint32_t dj = (uint32_t)(ny * a.wh + (nx >> 1));
+                    const uint32_t off = ((uint32_t)(k ^ 1) * a.blk + dj * lp + (uint32_t)f0) * S::bytes;
+                    st_row<S, R>(rd, off, out);
+                    if (a.ck) st_row<S, R>(rk, off, out);
+                }
+            });
         }
     }
 }

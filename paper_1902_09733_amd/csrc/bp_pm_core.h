@@ -7,6 +7,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "bp_device.h"
 
 namespace bpk {
@@ -28,11 +30,21 @@ namespace bpk {
 // the calling kernel's loops, and two kernels running this transform on the
 // same data (one half-sweep per launch, or two) must agree bit for bit.
 //
-// When tau <= 2 (`near`) a label g two or more labels from f costs
+// When tau <= 2 (NEAR) a label g two or more labels from f costs
 // h(g) + lambda min(|f - g|, tau) = h(g) + lambda tau >= min h + lt, never less
 // than the truncation cap, so only f - 1, f and f + 1 remain:
 //   out(f) = min(h(f), h(f - 1) + lambda, h(f + 1) + lambda, min h + lt) - min h,
 // the same function without the passes and scans (pm_transform_near).
+// Calls f with std::integral_constant<bool, v> for a uniform run-time v: a
+// loop over a pixel's four messages is then compiled once per form of the
+// transform (a branch inside it would keep the messages' code apart).
+template <typename F>
+__device__ __forceinline__ void with_near(bool v, F &&f)
+{
+    if (v) f(std::true_type{});
+    else f(std::false_type{});
+}
+
 template <int SEG, int R, bool EXACT>
 __device__ __forceinline__ void pm_transform_near(float (&h)[R], int s, int f0, int L, float lam, float lt,
                                                   float (&out)[R])
@@ -64,12 +76,11 @@ __device__ __forceinline__ void pm_transform_near(float (&h)[R], int s, int f0, 
     }
 }
 
-template <int SEG, int R, bool EXACT>
-__device__ __forceinline__ void pm_transform(float (&h)[R], int s, int f0, int L, float lam, float lt, bool near,
-                                             float (&out)[R])
+template <int SEG, int R, bool EXACT, bool NEAR>
+__device__ __forceinline__ void pm_transform(float (&h)[R], int s, int f0, int L, float lam, float lt, float (&out)[R])
 {
 #pragma clang fp contract(off)
-    if (near) {
+    if constexpr (NEAR) {
         pm_transform_near<SEG, R, EXACT>(h, s, f0, L, lam, lt, out);
         return;
     }
