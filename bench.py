@@ -513,8 +513,9 @@ COPY_BYTES = 256 << 20
 # the committed file and the sources whose digest it was taken with.
 TRAFFIC = {
     "k_iter_pm2": ("traffic_k_iter_pm2_aerial676x380_L64_f32.txt",
-                   ["paper_1902_09733_amd/csrc/bp_iter_pm2.hip", "paper_1902_09733_amd/csrc/bp_pm_core.h",
-                    "paper_1902_09733_amd/csrc/bp_device.h", "paper_1902_09733_amd/csrc/bp_internal.h"]),
+                   ["paper_1902_09733_amd/csrc/bp_iter_pm2_impl.h", "paper_1902_09733_amd/csrc/bp_iter_pm2_f32.hip",
+                    "paper_1902_09733_amd/csrc/bp_pm_core.h", "paper_1902_09733_amd/csrc/bp_device.h",
+                    "paper_1902_09733_amd/csrc/bp_internal.h"]),
 }
 
 

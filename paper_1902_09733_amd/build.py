@@ -28,7 +28,9 @@ FLAGS = [
 # are finite or +inf), so they need no NaN-quieting of their operands.
 EXTRA = {
     "bp_iter_pm.hip": ["-fno-honor-nans"],
-    "bp_iter_pm2.hip": ["-fno-honor-nans"],
+    "bp_iter_pm2_f32.hip": ["-fno-honor-nans"],
+    "bp_iter_pm2_f16.hip": ["-fno-honor-nans"],
+    "bp_iter_pm2_bf16.hip": ["-fno-honor-nans"],
 }
 
 

@@ -489,7 +489,7 @@ IterArgs make_iter_args(const Plan &p, int l, int t, int src_mode, float lambda,
     a.ncomp = v.h * v.wh;
     a.lambda = lambda;
     a.lt = lambda * tau;
-    a.near = tau <= 2.0f;
+    a.near = tau <= 2.0f ? 1 : tau <= 3.0f ? 2 : 0;
     return a;
 }
 
@@ -548,7 +548,7 @@ PairArgs make_pair_args(const Plan &p, int l, int src_kind, size_t src_off, size
     a.L = p.L;
     a.lambda = lambda;
     a.lt = lambda * tau;
-    a.near = tau <= 2.0f;
+    a.near = tau <= 2.0f ? 1 : tau <= 3.0f ? 2 : 0;
     a.cost16 = v.cost16;
     pair_tile(v.lp, fmt_bytes(v.fmt), v.w, v.h, &a.tx, &a.ty);
     a.tiles_x = (v.w + a.tx - 1) / a.tx;

@@ -345,6 +345,43 @@ __device__ __forceinline__ void seg_near(float &first, float &last, float &m, fl
     }
 }
 
+// The five-label transform's exchanges over a whole 16-lane row: e[0] and
+// e[1] (the lane's first two labels) take the minimum with b0 and b1 of the
+// next lower lane, e[3] and e[2] (its last two) with a0 and a1 of the next
+// higher lane, and m becomes the row's minimum; the same wait-state reasoning
+// as row_scans16.
+__device__ __forceinline__ void row_near2_16(float (&e)[4], float &m, float b0, float b1, float a0, float a1)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_min_f32_dpp %4, %4, %4 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %0, %5, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %1, %6, %1 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %4, %4, %4 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %3, %7, %3 row_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %2, %8, %2 row_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_min_f32_dpp %4, %4, %4 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\t"
+                 "v_min_f32_dpp %4, %4, %4 row_mirror row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1"
+                 : "+v"(e[0]), "+v"(e[1]), "+v"(e[2]), "+v"(e[3]), "+v"(m)
+                 : "v"(b0), "v"(b1), "v"(a0), "v"(a1));
+}
+
+template <int SEG>
+__device__ __forceinline__ void seg_near2(float (&e)[4], float &m, float b0, float b1, float a0, float a1, int s)
+{
+    if constexpr (SEG == 16) {
+        row_near2_16(e, m, b0, b1, a0, a1);
+    } else {
+        const float inf = __builtin_huge_valf();
+        e[0] = fminf(e[0], seg_from_lower<SEG, 1>(b0, inf, s));
+        e[1] = fminf(e[1], seg_from_lower<SEG, 1>(b1, inf, s));
+        e[3] = fminf(e[3], seg_from_upper<SEG, 1>(a0, inf, s));
+        e[2] = fminf(e[2], seg_from_upper<SEG, 1>(a1, inf, s));
+        m = seg_allmin<SEG>(m);
+    }
+}
+
 // The transform's three segment reductions at once: p the inclusive prefix
 // minimum, q the inclusive suffix minimum, m the segment minimum.
 template <int SEG>

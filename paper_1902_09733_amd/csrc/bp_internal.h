@@ -53,7 +53,7 @@ struct Plan {
     int variant;          // half-sweep kernel variant (0 = default)
     Level lv[kMaxLevels];
     size_t pair_off;      // byte offset of the packed downsampled pair (cost from a pair)
-    bool pairs;           // pixel-major levels run fused pairs of half-sweeps (bp_iter_pm2.hip)
+    bool pairs;           // pixel-major levels run fused pairs of half-sweeps (bp_iter_pm2_impl.h)
     size_t y_off;         // second buffer of colour 0's incoming rows for the fused pairs
                           // (the finest pixel-major level's size; 0 when !pairs)
     bool zero_coarsest;   // the initialisation zeros the coarsest level's whole state
@@ -178,7 +178,7 @@ struct IterArgs {
     int L;                 // label count
     int ncomp;             // h * wh
     float lambda, lt;      // lambda and lambda * tau
-    int near;              // tau <= 2: the transform's three-label form
+    int near;              // window of the transform's near form: 1 (tau <= 2), 2 (tau <= 3), 0 (scans)
 };
 bp_status dispatch_iter_lm(const IterArgs &a, int fmt, int G, bool ro, hipStream_t s);
 
@@ -230,7 +230,7 @@ bp_status launch_bwd_finish(const float *partial, int n, float *grad_lambda, flo
 bp_status dispatch_iter_pm(const IterArgs &a, int fmt, int S, int R, bool ro, bool xchg, hipStream_t s);
 
 // Two half-sweeps (t, t + 1, t even) of a pixel-major level in one launch
-// (bp_iter_pm2.hip).  Phase 1 sends from colour 0, whose incoming rows are
+// (bp_iter_pm2_impl.h).  Phase 1 sends from colour 0, whose incoming rows are
 // read from `src` (a colour-0 block [slot][plane][lp] of the level, or the
 // parent level's whole state when src_parent, or all zero when src_zero);
 // phase 2 sends from colour 1 into `dst`, a colour-0 block of the level.
@@ -253,7 +253,7 @@ struct PairArgs {
     int src_parent, src_zero, write_c1;
     int L;
     float lambda, lt;
-    int near;              // tau <= 2: the transform's three-label form
+    int near;              // window of the transform's near form: 1 (tau <= 2), 2 (tau <= 3), 0 (scans)
     int cost16;            // the level's cost is stored as FP16 (selects the kernel)
     int tx, ty;            // tile (tx even)
     int tiles_x, ntiles, per_xcd;

@@ -82,8 +82,8 @@ __device__ __forceinline__ void pm_sweep4(const IterArgs &a, uint32_t block)
     constexpr bool H4 = R <= 8;
     float h4[H4 ? 4 : 1][R];
     if constexpr (H4) pm_h4<R>(c, m, h4);
-    with_near(a.near != 0, [&](auto near_form) {
-        constexpr bool NEAR = decltype(near_form)::value;
+    with_near<R>(a.near, [&](auto near_form) {
+        constexpr int NEAR = decltype(near_form)::value;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             float h[R], out[R];
@@ -184,8 +184,9 @@ __device__ __forceinline__ void pm_sweep(const IterArgs &a, uint32_t block)
     }
 
     float out[R];
-    if (a.near) pm_transform<SEG, R, EXACT, true>(h, s, f0, a.L, lam, a.lt, out);
-    else pm_transform<SEG, R, EXACT, false>(h, s, f0, a.L, lam, a.lt, out);
+    with_near<R>(a.near, [&](auto near_form) {
+        pm_transform<SEG, R, EXACT, decltype(near_form)::value>(h, s, f0, a.L, lam, a.lt, out);
+    });
 
     // Receiver of message k and its slot k^1.
     int nx = x, ny = y;

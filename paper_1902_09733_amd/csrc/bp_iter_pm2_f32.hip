@@ -1,0 +1,9 @@
+// The fused pair of half-sweeps (bp_iter_pm2_impl.h) with F32 message storage.
+#include "bp_iter_pm2_impl.h"
+
+namespace bpk {
+
+template bp_status pm2_single<StoreF32>(const PairArgs &, size_t, int, int, bool, hipStream_t);
+template bp_status pm2_batch<StoreF32>(const PairEntry *, int, int, size_t, int, int, bool, bool, bool, hipStream_t);
+
+}  // namespace bpk

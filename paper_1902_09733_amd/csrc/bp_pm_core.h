@@ -1,6 +1,6 @@
 // The per-message arithmetic of a pixel-major half-sweep, shared by the
 // one-half-sweep kernels (bp_iter_pm.hip) and the fused pair of half-sweeps
-// (bp_iter_pm2.hip): the distance transform of h over a message's SEG lanes
+// (bp_iter_pm2_impl.h): the distance transform of h over a message's SEG lanes
 // (R labels per lane), truncation and normalisation, and the readout of a
 // belief (argmin and soft-argmin, also used by the readout pass).  The identities behind the split scans are in bp_iter_pm.hip.
 #pragma once
@@ -30,27 +30,42 @@ namespace bpk {
 // the calling kernel's loops, and two kernels running this transform on the
 // same data (one half-sweep per launch, or two) must agree bit for bit.
 //
-// When tau <= 2 (NEAR) a label g two or more labels from f costs
+// With a truncation of at most 1 + W labels (W = 1 for tau <= 2, W = 2 for
+// tau <= 3) a label g more than W labels from f costs
 // h(g) + lambda min(|f - g|, tau) = h(g) + lambda tau >= min h + lt, never less
-// than the truncation cap, so only f - 1, f and f + 1 remain:
-//   out(f) = min(h(f), h(f - 1) + lambda, h(f + 1) + lambda, min h + lt) - min h,
+// than the truncation cap, so only the labels within W of f remain:
+//   out(f) = min(min_{|g - f| <= W} h(g) + lambda |f - g|, min h + lt) - min h,
 // the same function without the passes and scans (pm_transform_near).
-// Calls f with std::integral_constant<bool, v> for a uniform run-time v: a
-// loop over a pixel's four messages is then compiled once per form of the
-// transform (a branch inside it would keep the messages' code apart).
-template <typename F>
-__device__ __forceinline__ void with_near(bool v, F &&f)
+// Calls f with std::integral_constant<int, W> for a uniform run-time W (0 for
+// the two-pass transform): a loop over a pixel's four messages is then
+// compiled once per form of the transform (a branch inside it would keep the
+// messages' code apart).  The five-label form (W = 2) is used with four labels
+// per lane; with more, its extra rows of h + 2 lambda cost registers and
+// occupancy (at 128 labels, eight per lane, it was slower than the scans), so
+// those lanes keep the scans.
+template <int R, typename F>
+__device__ __forceinline__ void with_near(int w, F &&f)
 {
-    if (v) f(std::true_type{});
-    else f(std::false_type{});
+    if (w == 1) {
+        f(std::integral_constant<int, 1>{});
+    } else {
+        if constexpr (R <= 4) {
+            if (w == 2) {
+                f(std::integral_constant<int, 2>{});
+                return;
+            }
+        }
+        f(std::integral_constant<int, 0>{});
+    }
 }
 
-template <int SEG, int R, bool EXACT>
+template <int SEG, int R, bool EXACT, int W>
 __device__ __forceinline__ void pm_transform_near(float (&h)[R], int s, int f0, int L, float lam, float lt,
                                                   float (&out)[R])
 {
 #pragma clang fp contract(off)
-    static_assert(R >= 2, "a lane holds at least two labels");
+    static_assert(W == 1 || W == 2, "window of one or two labels");
+    static_assert(R >= 2 * W, "a lane holds at least 2W labels");
     const float inf = __builtin_huge_valf();
     float hmin = inf;
 #pragma unroll
@@ -58,30 +73,48 @@ __device__ __forceinline__ void pm_transform_near(float (&h)[R], int s, int f0, 
         if (!EXACT && f0 + r >= L) h[r] = inf;
         hmin = fminf(hmin, h[r]);
     }
-    float hp[R];
+    float hp[R];   // h + lambda
 #pragma unroll
     for (int r = 0; r < R; ++r) hp[r] = h[r] + lam;
-    // The lane's first label also sees the last label of the lane below, its
-    // last label the first of the lane above.
-    float first = h[0], last = h[R - 1];
-    seg_near<SEG>(first, last, hmin, hp[R - 1], hp[0], s);
+    float e[2 * W];   // the lane's first W and last W labels, with the neighbouring lanes' candidates
+    if constexpr (W == 1) {
+        e[0] = h[0];
+        e[1] = h[R - 1];
+        seg_near<SEG>(e[0], e[1], hmin, hp[R - 1], hp[0], s);
+    }
+    float hq[W == 2 ? R : 1];   // h + 2 lambda
+    if constexpr (W == 2) {
+        const float lam2 = lam + lam;
+#pragma unroll
+        for (int r = 0; r < R; ++r) hq[r] = h[r] + lam2;
+        // The lane below offers its last two labels to this lane's first two,
+        // the lane above its first two to this lane's last two.
+        e[0] = h[0];
+        e[1] = h[1];
+        e[2] = h[R - 2];
+        e[3] = h[R - 1];
+        seg_near2<SEG>(e, hmin, fminf(hp[R - 1], hq[R - 2]), hq[R - 1], fminf(hp[0], hq[1]), hq[0], s);
+    }
     const float cap = hmin + lt;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        float v;
-        if (r == 0) v = fminf(first, hp[1]);
-        else if (r == R - 1) v = fminf(last, hp[R - 2]);
-        else v = fminf(fminf(h[r], hp[r - 1]), hp[r + 1]);
+        float v = r < W ? e[r] : r >= R - W ? e[2 * W - R + r] : h[r];
+        if (r >= 1) v = fminf(v, hp[r - 1]);
+        if (r + 1 < R) v = fminf(v, hp[r + 1]);
+        if constexpr (W == 2) {
+            if (r >= 2) v = fminf(v, hq[r - 2]);
+            if (r + 2 < R) v = fminf(v, hq[r + 2]);
+        }
         out[r] = fminf(v, cap) - hmin;
     }
 }
 
-template <int SEG, int R, bool EXACT, bool NEAR>
+template <int SEG, int R, bool EXACT, int W>
 __device__ __forceinline__ void pm_transform(float (&h)[R], int s, int f0, int L, float lam, float lt, float (&out)[R])
 {
 #pragma clang fp contract(off)
-    if constexpr (NEAR) {
-        pm_transform_near<SEG, R, EXACT>(h, s, f0, L, lam, lt, out);
+    if constexpr (W > 0) {
+        pm_transform_near<SEG, R, EXACT, W>(h, s, f0, L, lam, lt, out);
         return;
     }
     const float inf = __builtin_huge_valf();
