@@ -152,6 +152,22 @@ def test_parameter_edges_exact(dev, lam, tau):
         assert_exact(g, o, f"lam {lam} tau {tau} pm_from {pm_from}")
 
 
+@pytest.mark.parametrize("L", [64, 128])
+@pytest.mark.parametrize("lam,tau", [(2.0, 1.0), (2.0, 1.5), (1.0, 2.0), (2.0, 2.5), (1.0, 3.0), (2.0, 3.5)])
+def test_transform_forms_exact(dev, L, lam, tau):
+    """The truncated-linear transform's forms at 16 lanes per pixel: three
+    labels (tau <= 2), five labels (2 < tau <= 3, four labels per lane) and the
+    two-pass scans (tau > 3, or eight labels per lane), on integer costs with
+    dyadic lambda and tau, where every form is exact: bit-exact against the
+    oracle's sequential two-pass transform."""
+    cost = int_cost(44, 30, L, 7)
+    o = oracle_run(cost, 2, 4, lam, tau)
+    g = gpu_run(cost, dev, levels=2, iters=4, lam=lam, tau=tau)
+    assert_exact(g, o, f"L {L} lam {lam} tau {tau}")
+    g1 = gpu_run(cost, dev, levels=2, iters=3, lam=lam, tau=tau)
+    assert_exact(g1, oracle_run(cost, 2, 3, lam, tau), f"L {L} lam {lam} tau {tau} K 3")
+
+
 # ---------------------------------------------------------------- real-valued inputs
 
 def real_case(w=96, h=64, L=64, seed=3):
