@@ -140,18 +140,25 @@ static bool fp16_exact(float t)
     return std::ldexp(std::nearbyint(std::ldexp(t, -lsb)), lsb) == t;
 }
 
-static bool pair_cost16(const bp_pair &pr, const Plan &pl, int K)
+static int pair_cost_fmt(const bp_pair &pr, const Plan &pl, int K)
 {
     if (!((pr.channels == 1 || pr.rgb_mode == 0) && fp16_exact(pr.data_trunc) && pl.levels >= 2 &&
           pl.lv[0].layout == PIXEL_MAJOR && pl.lv[1].layout == PIXEL_MAJOR))
-        return false;
+        return COST_F32;
     // Only the fused pairs and the readout read it: the finest level runs
     // pairs alone (K even, and no single half-sweeps ahead of the first pair
     // after a materialised parent copy).
-    if (!level_pairs(pl, 0, K) || (K & 1)) return false;
+    if (!level_pairs(pl, 0, K) || (K & 1)) return COST_F32;
     const Level &c = pl.lv[0], &pa = pl.lv[1];
     const bool fusable = K >= 2 && c.fmt == pa.fmt;
-    return fusable || ((K / 2) & 1) == 0;
+    if (!fusable && ((K / 2) & 1) != 0) return COST_F32;
+    // Bytes when the truncation is an integer of at most 255 (then every cost
+    // is one) and a lane's labels fill whole words.
+    int S, R;
+    pm_split(pl.L, &S, &R);
+    const float t = pr.data_trunc;
+    if (t <= 255.0f && t == std::floor(t) && R % 4 == 0) return COST_U8;
+    return COST_F16;
 }
 
 // Problem plans laid out back to back in the workspace.  With allow_pairs,
@@ -202,7 +209,7 @@ bool plan_all(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
         // reads zero messages in place of the state, so only the out-of-grid
         // slots need zeroing there.
         plans[i].zero_coarsest = !level_pairs(plans[i], plans[i].levels - 1, p->iters_per_level);
-        plans[i].lv[0].cost16 = !q.cost && pair_cost16(*q.pair, plans[i], p->iters_per_level);
+        plans[i].lv[0].cost_fmt = q.cost ? COST_F32 : pair_cost_fmt(*q.pair, plans[i], p->iters_per_level);
         off += plans[i].bytes;
     }
     *total = align_up(off);
@@ -240,7 +247,8 @@ double sweep_bytes(const Plan &pl, int l)
 double pair_bytes(const Plan &pl, int l, bool ends)
 {
     const double nl = (double)pl.lv[l].w * pl.lv[l].h * pl.L, mb = fmt_bytes(pl.lv[l].fmt);
-    const double cb = pl.lv[l].cost16 ? 2.0 : 4.0;   // both colours' costs
+    const int cf = pl.lv[l].cost_fmt;
+    const double cb = cf == COST_U8 ? 1.0 : cf == COST_F16 ? 2.0 : 4.0;   // both colours' costs
     return nl * (cb + 4.0 * mb + (ends ? 2.0 * mb : 0.0));
 }
 
@@ -484,11 +492,12 @@ bool plan_run(const bp_problem *probs, int32_t count, const bp_params *p, Plan *
         if (!pairs && !plan_all(probs, count, p, plans, total)) return false;
         if (table) *table = batch_table_bytes(count, p->levels, p->iters_per_level, pairs);
         // A batched launch covers several problems with one kernel, so their
-        // finest levels share the cost storage: FP16 only when every problem's
-        // allows it (and never for the one-half-sweep kernels).
-        bool all16 = pairs;
-        for (int i = 0; i < count; ++i) all16 = all16 && plans[i].lv[0].cost16;
-        for (int i = 0; i < count; ++i) plans[i].lv[0].cost16 = all16;
+        // finest levels share the cost storage: the narrowest every problem's
+        // costs allow (bytes are exact in FP16 too), and FP32 for the
+        // one-half-sweep kernels.
+        int cf = pairs ? COST_U8 : COST_F32;
+        for (int i = 0; i < count; ++i) cf = std::min(cf, plans[i].lv[0].cost_fmt);
+        for (int i = 0; i < count; ++i) plans[i].lv[0].cost_fmt = cf;
     }
     return true;
 }
@@ -675,7 +684,7 @@ bp_status run_batched_pairs(const bp_problem *probs, int32_t count, const Plan *
                     else
                         st = launch_iteration_pair_batch(dev + start[slot], num[slot], blocks[slot], lds[slot], fmt,
                                                          cls_S[c], cls_R[c], exact[slot], ro[slot],
-                                                         host[start[slot]].a.cost16 != 0, s);
+                                                         host[start[slot]].a.cost_fmt, s);
                 }
             // The group's readout and export while its state is in the cache.
             if (l == 0 && st == BP_OK) st = finish_batched(probs, count, plans, p, fuse, ws, s, grp, g);

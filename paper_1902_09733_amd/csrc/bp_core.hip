@@ -38,7 +38,7 @@ bool make_plan(int w, int h, int L, int levels, int msg_fmt, int pm_from, size_t
         v.plane = (int64_t)align_up((size_t)lh * v.wh, 64);
         v.fmt = (l == levels - 1) ? FMT_F32 : msg_fmt;
         v.layout = l >= pm_from ? PIXEL_MAJOR : LABEL_MAJOR;
-        v.cost16 = false;
+        v.cost_fmt = COST_F32;
         if (v.layout == PIXEL_MAJOR) {
             v.lp = S * R;
             v.blk = v.plane * v.lp;
@@ -549,7 +549,7 @@ PairArgs make_pair_args(const Plan &p, int l, int src_kind, size_t src_off, size
     a.lambda = lambda;
     a.lt = lambda * tau;
     a.near = tau <= 2.0f ? 1 : tau <= 3.0f ? 2 : 0;
-    a.cost16 = v.cost16;
+    a.cost_fmt = v.cost_fmt;
     pair_tile(v.lp, fmt_bytes(v.fmt), v.w, v.h, &a.tx, &a.ty);
     a.tiles_x = (v.w + a.tx - 1) / a.tx;
     a.ntiles = a.tiles_x * ((v.h + a.ty - 1) / a.ty);
@@ -645,7 +645,7 @@ __global__ void __launch_bounds__(256) k_readout_lm(const float *__restrict__ co
 // Pixel-major readout: SEG lanes per pixel, R labels per lane; a block
 // covers 256 / SEG pixels of one row of one colour.  grid (ceil(wh * SEG /
 // 256), h, colours), colour c0 + blockIdx.z.
-template <int SEG, int R, typename S, bool C16>
+template <int SEG, int R, typename S, int CF>
 __global__ void __launch_bounds__(256) k_readout_pm(const float *__restrict__ cost, uint32_t cost_bytes,
                                                    const uint8_t *__restrict__ msg, uint32_t msg_bytes, LevelDesc d,
                                                    int lp, int L, int c0, int32_t *__restrict__ disp,
@@ -661,7 +661,7 @@ __global__ void __launch_bounds__(256) k_readout_pm(const float *__restrict__ co
     const __amdgpu_buffer_rsrc_t rm = make_rsrc(msg, msg_bytes);
     const int f0 = s * R;
     float b[R], m[R];
-    ld_cost<R>(rc, (uint32_t)(c * d.blk) + (uint32_t)j * lp + f0, C16, b);
+    ld_cost<R, CF>(rc, (uint32_t)(c * d.blk) + (uint32_t)j * lp + f0, b);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         ld_row<S, R>(rm, ((uint32_t)((c * 4 + k) * d.blk) + (uint32_t)j * lp + f0) * S::bytes, m);
@@ -696,17 +696,16 @@ bp_status launch_readout(const Plan &p, int colour_mask, int32_t *disp, float *s
         pm_split(p.L, &SEGV, &R);
         // Colours 0 and 1, or just the one the mask names.
         const int c0 = colour_mask == 2 ? 1 : 0, nc = colour_mask == 3 ? 2 : 1;
+#define BP_RO_LAUNCH(SV, RV, CFV)                                                                              \
+    k_readout_pm<SV, RV, S, CFV><<<dim3(cdiv((int64_t)v.wh * SV, 256), v.h, nc), 256, 0, s>>>(                 \
+        cost, (uint32_t)v.cost_bytes, msg, (uint32_t)v.msg_bytes, desc(v), v.lp, p.L, c0, disp, soft, inv_t)
 #define BP_RO_CASE(SV, RV)                                                                                      \
     if (SEGV == SV && R == RV) {                                                                                \
-        const dim3 grid(cdiv((int64_t)v.wh * SV, 256), v.h, nc);                                                \
-        if (v.cost16)                                                                                           \
-            k_readout_pm<SV, RV, S, true><<<grid, 256, 0, s>>>(cost, (uint32_t)v.cost_bytes, msg,                \
-                                                               (uint32_t)v.msg_bytes, desc(v), v.lp, p.L, c0,  \
-                                                               disp, soft, inv_t);                             \
-        else                                                                                                    \
-            k_readout_pm<SV, RV, S, false><<<grid, 256, 0, s>>>(cost, (uint32_t)v.cost_bytes, msg,               \
-                                                                (uint32_t)v.msg_bytes, desc(v), v.lp, p.L, c0, \
-                                                                disp, soft, inv_t);                            \
+        if (v.cost_fmt == COST_F16) BP_RO_LAUNCH(SV, RV, COST_F16);                                             \
+        else if (v.cost_fmt == COST_U8) {                                                                       \
+            if constexpr (RV % 4 == 0) BP_RO_LAUNCH(SV, RV, COST_U8);                                           \
+            else return BP_ERR_UNSUPPORTED;                                                                     \
+        } else BP_RO_LAUNCH(SV, RV, COST_F32);                                                                  \
         return launch_status();                                                                                 \
     }
         BP_RO_CASE(4, 4)
@@ -717,6 +716,7 @@ bp_status launch_readout(const Plan &p, int colour_mask, int32_t *disp, float *s
         BP_RO_CASE(16, 12)
         BP_RO_CASE(16, 16)
 #undef BP_RO_CASE
+#undef BP_RO_LAUNCH
         return BP_ERR_UNSUPPORTED;
     });
 }

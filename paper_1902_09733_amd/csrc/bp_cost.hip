@@ -270,9 +270,10 @@ __global__ void __launch_bounds__(256) k_cost_level0(const uint32_t *__restrict_
 // vector, and stores their sum, added in the order (0,0), (1,0), (0,1), (1,1)
 // as the separate pyramid step does.  Labels past L (inside the level's
 // padded row) get the truncation value; no kernel reads them.
-// H16: level 0 is stored as FP16 (four labels in one 8-byte store; the plan
-// chooses it only where every value is exact in FP16).
-template <int C, bool H16>
+// CF: level 0's storage, FP32, FP16 (four labels in one 8-byte store) or bytes
+// (one 4-byte store); the plan chooses the narrow ones only where every value
+// is exact in them.
+template <int C, int CF>
 __global__ void __launch_bounds__(256) k_cost_level01(const uint32_t *__restrict__ packed, int w, int h, int L,
                                                      float trunc, int rgb_mode, int xb1, int q4, int wh0,
                                                      int64_t blk0, int64_t ps0, void *__restrict__ out0, int w1,
@@ -321,10 +322,13 @@ __global__ void __launch_bounds__(256) k_cost_level01(const uint32_t *__restrict
                     v[e] = (f < L && x - f >= 0) ? ad_cost<C>(lv, rpx[xl + (L - 1) - f], rgb_mode, trunc) : trunc;
                 }
                 const int64_t e0 = (int64_t)((x + y) & 1) * blk0 + (int64_t)(y * wh0 + (x >> 1)) * ps0 + f0;
-                if constexpr (H16) {
+                if constexpr (CF == COST_F16) {
                     typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
                     const h4_t hv = {(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
                     *(h4_t *)((_Float16 *)out0 + e0) = hv;
+                } else if constexpr (CF == COST_U8) {
+                    *(uint32_t *)((uint8_t *)out0 + e0) = (uint32_t)v[0] | ((uint32_t)v[1] << 8) |
+                                                          ((uint32_t)v[2] << 16) | ((uint32_t)v[3] << 24);
                 } else {
                     *(float4 *)((float *)out0 + e0) = make_float4(v[0], v[1], v[2], v[3]);
                 }
@@ -381,11 +385,13 @@ bp_status launch_pair_cost(const bp_pair &pr, const Plan &p, uint8_t *ws, hipStr
     k_cost_level01<CV, HV><<<grid1, 256, lds1, st>>>(packed, w, h, L, pr.data_trunc, pr.rgb_mode, xb1, q4, v.wh, \
                                                      v.blk, v.ps, out0, v1.w, v1.wh, v1.blk, v1.ps, out1)
         if (pr.channels == 1) {
-            if (v.cost16) BP_COST01(1, true);
-            else BP_COST01(1, false);
+            if (v.cost_fmt == COST_F16) BP_COST01(1, COST_F16);
+            else if (v.cost_fmt == COST_U8) BP_COST01(1, COST_U8);
+            else BP_COST01(1, COST_F32);
         } else {
-            if (v.cost16) BP_COST01(3, true);
-            else BP_COST01(3, false);
+            if (v.cost_fmt == COST_F16) BP_COST01(3, COST_F16);
+            else if (v.cost_fmt == COST_U8) BP_COST01(3, COST_U8);
+            else BP_COST01(3, COST_F32);
         }
 #undef BP_COST01
         *levels_done = 2;

@@ -145,13 +145,24 @@ __device__ __forceinline__ void ld_row(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
     }
 }
 
-// R cost values of a pixel-major level at element offset e: FP32, or FP16
-// where the level stores its cost in half precision (c16, uniform).
-template <int R>
-__device__ __forceinline__ void ld_cost(__amdgpu_buffer_rsrc_t r, uint32_t e, bool c16, float (&v)[R])
+// R cost values of a pixel-major level at element offset e, stored as FP32
+// (CF 0), FP16 (CF 1) or unsigned bytes (CF 2, R a multiple of 4).
+template <int R, int CF>
+__device__ __forceinline__ void ld_cost(__amdgpu_buffer_rsrc_t r, uint32_t e, float (&v)[R])
 {
-    if (c16) ld_row<StoreF16, R>(r, e * 2u, v);
-    else ld_row<StoreF32, R>(r, e * 4u, v);
+    if constexpr (CF == 1) {
+        ld_row<StoreF16, R>(r, e * 2u, v);
+    } else if constexpr (CF == 2) {
+        static_assert(R % 4 == 0, "byte cost rows are whole words per lane");
+        uint32_t w[R / 4];
+        ld_words<R / 4>(r, e, w);
+#pragma unroll
+        for (int i = 0; i < R / 4; ++i)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) v[4 * i + b] = (float)((w[i] >> (8 * b)) & 255u);
+    } else {
+        ld_row<StoreF32, R>(r, e * 4u, v);
+    }
 }
 
 template <typename S, int R>

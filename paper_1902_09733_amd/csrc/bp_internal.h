@@ -33,6 +33,10 @@ inline int fmt_bytes(int fmt) { return fmt == FMT_F32 ? 4 : 2; }
 //   msg(c, k, f, j) = (c * 4 + k) * blk + f * ls + j * ps
 enum Layout : int { LABEL_MAJOR = 0, PIXEL_MAJOR = 1 };
 
+// Cost storage of a level (Level::cost_fmt): FP32, or, for the finest level of
+// a pair whose costs are exact there, FP16 or unsigned bytes.
+enum { COST_F32 = 0, COST_F16 = 1, COST_U8 = 2 };
+
 struct Level {
     int w, h, wh;
     int64_t plane;        // compact pixel slots per colour (padded to 64)
@@ -41,8 +45,8 @@ struct Level {
     int64_t blk, ls, ps;  // element strides: per (colour[, slot]) block, per label, per pixel
     int fmt;              // message storage format at this level
     size_t cost_off;      // byte offset of this level's cost in the workspace
-    bool cost16;          // cost stored as FP16 at the same element offsets (level 0 of a pair whose
-                          // costs FP16 holds exactly); FP32 otherwise
+    int cost_fmt;         // cost storage at the same element offsets: COST_F32, or for level 0 of a
+                          // pair whose costs it holds exactly COST_F16 or COST_U8
     size_t msg_off;       // byte offset of this level's messages
     size_t cost_bytes, msg_bytes;
 };
@@ -254,7 +258,7 @@ struct PairArgs {
     int L;
     float lambda, lt;
     int near;              // window of the transform's near form: 1 (tau <= 2), 2 (tau <= 3), 0 (scans)
-    int cost16;            // the level's cost is stored as FP16 (selects the kernel)
+    int cost_fmt;          // the level's cost storage (COST_*; selects the kernel)
     int tx, ty;            // tile (tx even)
     int tiles_x, ntiles, per_xcd;
     uint8_t *ck;           // checkpoint state in the level's layout that also receives phase 2's rows,
@@ -291,7 +295,7 @@ int pair_blocks(const PairArgs &a);
 bp_status launch_write_pair_entries(PairEntry *dst, const PairEntry *src, int n, hipStream_t s);
 // exact: every entry's label count equals its lane split's S * R.
 bp_status launch_iteration_pair_batch(const PairEntry *tab, int n, int blocks, size_t lds, int fmt, int S, int R,
-                                      bool exact, bool ro, bool cost16, hipStream_t s);
+                                      bool exact, bool ro, int cost_fmt, hipStream_t s);
 
 // Pixel-major kernel variants (1 default split; 2 half the lanes per message,
 // twice the labels per lane; 3 and 4 the same with each lane group reading

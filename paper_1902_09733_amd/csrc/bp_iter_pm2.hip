@@ -14,7 +14,7 @@ template <typename S>
 bp_status pm2_single(const PairArgs &a, size_t lds, int SEGV, int R, bool ro, hipStream_t st);
 template <typename S>
 bp_status pm2_batch(const PairEntry *tab, int n, int blocks, size_t lds, int SEGV, int R, bool exact, bool ro,
-                    bool c16, hipStream_t st);
+                    int cf, hipStream_t st);
 
 // Table of batch entries written from kernel arguments (capture-safe).
 __global__ void k_write_pair_entries(PairEntry *__restrict__ dst, PairChunk c)
@@ -64,15 +64,15 @@ void pair_tile(int lp, int mb, int w, int h, int *tx, int *ty)
 
 size_t pair_lds_bytes(int tx, int ty, int lp, int mb) { return (size_t)tx * ty / 2 * 4 * lp * mb; }
 
-// Every entry of a launch has the same cost storage (c16).
+// Every entry of a launch has the same cost storage (cf).
 bp_status launch_iteration_pair_batch(const PairEntry *tab, int n, int blocks, size_t lds, int fmt, int SEGV, int R,
-                                      bool exact, bool ro, bool c16, hipStream_t st)
+                                      bool exact, bool ro, int cf, hipStream_t st)
 {
     if (lds > 65536) return BP_ERR_UNSUPPORTED;
     switch (fmt) {
-    case FMT_F16: return pm2_batch<StoreF16>(tab, n, blocks, lds, SEGV, R, exact, ro, c16, st);
-    case FMT_BF16: return pm2_batch<StoreBF16>(tab, n, blocks, lds, SEGV, R, exact, ro, c16, st);
-    default: return pm2_batch<StoreF32>(tab, n, blocks, lds, SEGV, R, exact, ro, c16, st);
+    case FMT_F16: return pm2_batch<StoreF16>(tab, n, blocks, lds, SEGV, R, exact, ro, cf, st);
+    case FMT_BF16: return pm2_batch<StoreBF16>(tab, n, blocks, lds, SEGV, R, exact, ro, cf, st);
+    default: return pm2_batch<StoreF32>(tab, n, blocks, lds, SEGV, R, exact, ro, cf, st);
     }
 }
 

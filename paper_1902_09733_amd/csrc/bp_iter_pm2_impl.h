@@ -36,8 +36,8 @@
 // state (`ck_c1`; the level's own colour-1 block then need not be written
 // when nothing else reads it).
 //
-// The level's cost is read as FP32, or as FP16 (C16) where the plan keeps the
-// finest level's cost in half precision (a pair's integer costs, exact there).
+// The level's cost is read as FP32, or as FP16 or bytes (CF) where the plan
+// keeps the finest level's cost narrower (a pair's integer costs, exact there).
 //
 // Per message the arithmetic is the one-half-sweep kernel's variant 1
 // (bp_pm_core.h: h summed in slot order, the same transform), so results
@@ -56,7 +56,7 @@ namespace bpk {
 // incoming rows, and computes its four outgoing messages in turn (as the
 // one-half-sweep kernel's variant 1).  U pixels per lane group are loaded
 // before any is computed, to keep more rows in flight per wave.
-template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U, bool C16>
+template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U, int CF>
 __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
 {
     // lds: [tile colour-1 pixel][slot][lp] in the storage format
@@ -101,7 +101,7 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
                 sc = (sx + sy) & 1;
                 sj = sy * a.src_wh + (sx >> 1);
             }
-            ld_cost<R>(rc, (uint32_t)j * lp + (uint32_t)f0, C16, c[u]);
+            ld_cost<R, CF>(rc, (uint32_t)j * lp + (uint32_t)f0, c[u]);
             const uint32_t base = (uint32_t)sj * a.sps + (uint32_t)f0;
             // Slots from outside the grid are zero; they are not read, since
             // the second buffer never holds them.
@@ -170,7 +170,7 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
             live[u] = i < n2 && x < a.w && y < a.h;
             if (!live[u]) continue;
             const int j = y * a.wh + (x >> 1);
-            ld_cost<R>(rc, (a.blk + (uint32_t)j * lp) + (uint32_t)f0, C16, c[u]);
+            ld_cost<R, CF>(rc, (a.blk + (uint32_t)j * lp) + (uint32_t)f0, c[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -223,18 +223,18 @@ __device__ __forceinline__ void pm2_tile(const PairArgs &a, int b, uint8_t *lds)
     }
 }
 
-template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U, bool C16>
+template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U, int CF>
 __global__ void __launch_bounds__(NT) k_iter_pm2(const PairArgs a)
 {
     extern __shared__ uint8_t lds[];
-    pm2_tile<SEG, R, S, EXACT, RO, NT, U, C16>(a, (int)blockIdx.x, lds);
+    pm2_tile<SEG, R, S, EXACT, RO, NT, U, CF>(a, (int)blockIdx.x, lds);
 }
 
 // Batched fused pair: block b belongs to the last table entry whose first
 // block is <= b; every entry's first block is a multiple of 8, so the XCD
 // grouping of tiles holds within each problem.  EXACT: every entry's label
 // count fills its lane split.
-template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U, bool C16>
+template <int SEG, int R, typename S, bool EXACT, bool RO, int NT, int U, int CF>
 __global__ void __launch_bounds__(NT) k_iter_pm2_batch(const PairEntry *__restrict__ tab, int n)
 {
     extern __shared__ uint8_t lds[];
@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(NT) k_iter_pm2_batch(const PairEntry *__restri
         else hi = mid - 1;
     }
     const PairArgs a = tab[lo].a;
-    pm2_tile<SEG, R, S, EXACT, RO, NT, U, C16>(a, (int)blockIdx.x - tab[lo].block0, lds);
+    pm2_tile<SEG, R, S, EXACT, RO, NT, U, CF>(a, (int)blockIdx.x - tab[lo].block0, lds);
 }
 
 constexpr int kPairThreads = 512;
@@ -254,19 +254,26 @@ template <int SEG, int R, typename S, bool EXACT, bool RO>
 static bp_status launch_pm2(const PairArgs &a, size_t lds, hipStream_t st)
 {
     const unsigned grid = (unsigned)pair_blocks(a);
-    if (a.cost16) k_iter_pm2<SEG, R, S, EXACT, RO, kPairThreads, 1, true><<<grid, kPairThreads, lds, st>>>(a);
-    else k_iter_pm2<SEG, R, S, EXACT, RO, kPairThreads, 1, false><<<grid, kPairThreads, lds, st>>>(a);
+    if (a.cost_fmt == COST_F16) {
+        k_iter_pm2<SEG, R, S, EXACT, RO, kPairThreads, 1, COST_F16><<<grid, kPairThreads, lds, st>>>(a);
+    } else if (a.cost_fmt == COST_U8) {
+        if constexpr (R % 4 == 0) k_iter_pm2<SEG, R, S, EXACT, RO, kPairThreads, 1, COST_U8><<<grid, kPairThreads, lds, st>>>(a);
+        else return BP_ERR_UNSUPPORTED;
+    } else {
+        k_iter_pm2<SEG, R, S, EXACT, RO, kPairThreads, 1, COST_F32><<<grid, kPairThreads, lds, st>>>(a);
+    }
     return launch_status();
 }
 
-template <typename S, bool EXACT, bool C16>
+template <typename S, bool EXACT, int CF>
 static bp_status dispatch_pm2_batch(const PairEntry *tab, int n, int blocks, size_t lds, int SEGV, int R, bool ro,
                                     hipStream_t st)
 {
 #define BP_PM2B(SV, RV)                                                                                          \
     if (SEGV == SV && R == RV) {                                                                                 \
-        if (ro) k_iter_pm2_batch<SV, RV, S, EXACT, true, kPairThreads, 1, C16><<<blocks, kPairThreads, lds, st>>>(tab, n); \
-        else k_iter_pm2_batch<SV, RV, S, EXACT, false, kPairThreads, 1, C16><<<blocks, kPairThreads, lds, st>>>(tab, n);  \
+        if constexpr (CF == COST_U8 && RV % 4 != 0) return BP_ERR_UNSUPPORTED;                                  \
+        else if (ro) k_iter_pm2_batch<SV, RV, S, EXACT, true, kPairThreads, 1, CF><<<blocks, kPairThreads, lds, st>>>(tab, n); \
+        else k_iter_pm2_batch<SV, RV, S, EXACT, false, kPairThreads, 1, CF><<<blocks, kPairThreads, lds, st>>>(tab, n);  \
         return launch_status();                                                                                  \
     }
     BP_PM2B(4, 4) BP_PM2B(8, 4) BP_PM2B(16, 4) BP_PM2B(16, 6) BP_PM2B(16, 8) BP_PM2B(16, 12) BP_PM2B(16, 16)
@@ -276,13 +283,16 @@ static bp_status dispatch_pm2_batch(const PairEntry *tab, int n, int blocks, siz
 
 template <typename S>
 static bp_status dispatch_pm2_batch_exact(const PairEntry *tab, int n, int blocks, size_t lds, int SEGV, int R,
-                                          bool exact, bool ro, bool c16, hipStream_t st)
+                                          bool exact, bool ro, int cf, hipStream_t st)
 {
-    if (c16)
-        return exact ? dispatch_pm2_batch<S, true, true>(tab, n, blocks, lds, SEGV, R, ro, st)
-                     : dispatch_pm2_batch<S, false, true>(tab, n, blocks, lds, SEGV, R, ro, st);
-    return exact ? dispatch_pm2_batch<S, true, false>(tab, n, blocks, lds, SEGV, R, ro, st)
-                 : dispatch_pm2_batch<S, false, false>(tab, n, blocks, lds, SEGV, R, ro, st);
+    if (cf == COST_F16)
+        return exact ? dispatch_pm2_batch<S, true, COST_F16>(tab, n, blocks, lds, SEGV, R, ro, st)
+                     : dispatch_pm2_batch<S, false, COST_F16>(tab, n, blocks, lds, SEGV, R, ro, st);
+    if (cf == COST_U8)
+        return exact ? dispatch_pm2_batch<S, true, COST_U8>(tab, n, blocks, lds, SEGV, R, ro, st)
+                     : dispatch_pm2_batch<S, false, COST_U8>(tab, n, blocks, lds, SEGV, R, ro, st);
+    return exact ? dispatch_pm2_batch<S, true, COST_F32>(tab, n, blocks, lds, SEGV, R, ro, st)
+                 : dispatch_pm2_batch<S, false, COST_F32>(tab, n, blocks, lds, SEGV, R, ro, st);
 }
 
 template <int SEG, int R, typename S>
@@ -314,9 +324,9 @@ bp_status pm2_single(const PairArgs &a, size_t lds, int SEGV, int R, bool ro, hi
 
 template <typename S>
 bp_status pm2_batch(const PairEntry *tab, int n, int blocks, size_t lds, int SEGV, int R, bool exact, bool ro,
-                    bool c16, hipStream_t st)
+                    int cf, hipStream_t st)
 {
-    return dispatch_pm2_batch_exact<S>(tab, n, blocks, lds, SEGV, R, exact, ro, c16, st);
+    return dispatch_pm2_batch_exact<S>(tab, n, blocks, lds, SEGV, R, exact, ro, cf, st);
 }
 
 }  // namespace bpk

@@ -399,14 +399,16 @@ def test_pair_input_truncations(dev, trunc, levels):
 
 
 @pytest.mark.parametrize("trunc", [20.0, 20.5, 20.3, 300.0, 65504.0, 70000.0, 0.0])
-@pytest.mark.parametrize("ch,mode", [(1, 0), (3, 0), (3, 1)])
-def test_pair_cost_storage_invisible(dev, trunc, ch, mode):
-    """On the pair route the finest level may keep its cost in FP16 (integer
-    costs and a truncation FP16 holds exactly: 20, 20.5, 300, 65504, 0) or in
-    FP32 (20.3, 70000, or the exact RGB mean); either way the messages and
-    labels equal the volume route's, which is always FP32, bit for bit."""
+@pytest.mark.parametrize("ch,mode,L", [(1, 0, 24), (3, 0, 24), (3, 1, 24), (3, 0, 96)])
+def test_pair_cost_storage_invisible(dev, trunc, ch, mode, L):
+    """On the pair route the finest level may keep its integer costs in bytes
+    (an integral truncation of at most 255: 20, 0; four labels per lane), in
+    FP16 (a truncation FP16 holds exactly: 20.5, 300, 65504, or 20 and 0 at 96
+    labels, six per lane) or in FP32 (20.3, 70000, or the exact RGB mean);
+    either way the messages and labels equal the volume route's, which is
+    always FP32, bit for bit."""
     bp = bp_mod()
-    w, h, s, L = 58, 34, 2, 24
+    w, h, s = 58, 34, 2
     rng = np.random.default_rng(int(trunc * 10) + 7 * ch + mode)
     shp = (h * s, w * s) + ((3,) if ch == 3 else ())
     left_np = rng.integers(0, 256, size=shp, dtype=np.uint8)
