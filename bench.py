@@ -174,10 +174,10 @@ def main():
             # them: a single half-sweep's active half reads its cost and four
             # incoming rows and writes four outgoing ones (18 B per pixel and
             # label in FP32); a fused pair reads both colours' costs (4 B per
-            # pixel and label, 2 B where the finest level keeps its integer
-            # costs in FP16) and colour 0's rows and writes colour 0's rows
-            # (10 or 9 B per pixel, label and half-sweep in FP32), colour 1's
-            # rows also at the level's end.
+            # pixel and label; 2 B or 1 B where the finest level keeps its
+            # integer costs in FP16 or bytes) and colour 0's rows and writes
+            # colour 0's rows (10, 9 or 8.5 B per pixel, label and half-sweep
+            # in FP32), colour 1's rows also at the level's end.
             lv_ms.setdefault(r.level, []).append(r.ms / r.launches)
             lv_bytes[r.level] = r.bytes / r.launches
             lv_units[r.level] = r.units / r.launches
