@@ -465,6 +465,35 @@ def test_pair_and_volume_problems_batched(dev):
         assert_exact({k: v.cpu().numpy() for k, v in og.items()}, o, f"batched item {i}")
 
 
+@pytest.mark.parametrize("truncs", [(20.0, 20.0, 20.0), (20.0, 300.0, 20.0), (20.0, 20.3, 20.0)])
+def test_batched_pairs_cost_storage(dev, truncs):
+    """A batched call of pair-sourced problems (fused pairs at every level)
+    whose finest levels share the narrowest cost storage all of them allow:
+    bytes (every truncation an integer <= 255, labels 32 / 64 / 128, four or
+    eight per lane), FP16 (one truncation of 300) or FP32 (one of 20.3).  Each
+    problem equals its own run on the FP32 volume route bit for bit, labels
+    and messages, with an even and an odd number of pairs per level."""
+    bp = bp_mod()
+    shapes = [(60, 40, 32), (90, 50, 64), (47, 29, 128)]
+    items, vols = [], []
+    for i, ((w, h, L), t) in enumerate(zip(shapes, truncs)):
+        left_np, right_np, _ = aerial(2 * w, 2 * h, 2 * L, 60 + i, channels=3)
+        left, right = torch.from_numpy(left_np).to(dev), torch.from_numpy(right_np).to(dev)
+        items.append(bp.Pair(left, right, L, t, downsample=2))
+        vols.append(bp.cost_volume(left, right, L, t, downsample=2))
+    for K in (4, 6):
+        p = bp.BPParams(levels=3, iters=K, lam=10.0, tau=2.0)
+        outs = bp.run(items, p, want_msgs=True)
+        torch.cuda.synchronize()
+        for i, v in enumerate(vols):
+            ref = bp.run(v, p, want_msgs=True)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(outs[i]["disp"].cpu().numpy(), ref["disp"].cpu().numpy(),
+                                          err_msg=f"problem {i} K {K}")
+            np.testing.assert_array_equal(outs[i]["msgs"].cpu().numpy(), ref["msgs"].cpu().numpy(),
+                                          err_msg=f"problem {i} K {K}")
+
+
 # ---------------------------------------------------------------- batched form, kernel variants
 
 BATCH_SHAPES = [(60, 40, 32), (90, 50, 64), (33, 21, 96), (120, 70, 128), (45, 35, 64), (17, 9, 16), (71, 45, 100)]
