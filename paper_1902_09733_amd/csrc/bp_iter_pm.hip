@@ -25,7 +25,8 @@
 //   out(f)    = min(b(f), below + lambda (f - sR + 1), above + lambda (sR + R - f),
 //                   min h + lambda tau) - min h   (DPP min-reduction for min h).
 // The two scans and the reduction are independent and run interleaved.  When
-// tau <= 2 the transform reduces to its three-label form (bp_pm_core.h).
+// tau <= 2 (or tau <= 3 with four labels per lane) the transform reduces to
+// its three- (five-) label form (bp_pm_core.h).
 // With integer-valued data every step is exact, so the result equals the
 // sequential two-pass transform bit for bit.  Labels past L are +inf in h and
 // never influence real labels.
