@@ -405,8 +405,8 @@ def test_pair_cost_storage_invisible(dev, trunc, ch, mode, L):
     (an integral truncation of at most 255: 20, 0; four labels per lane), in
     FP16 (a truncation FP16 holds exactly: 20.5, 300, 65504, or 20 and 0 at 96
     labels, six per lane) or in FP32 (20.3, 70000, or the exact RGB mean);
-    either way the messages and labels equal the volume route's, which is
-    always FP32, bit for bit."""
+    either way the messages, labels and soft-argmin disparities equal the
+    volume route's, which is always FP32, bit for bit."""
     bp = bp_mod()
     w, h, s = 58, 34, 2
     rng = np.random.default_rng(int(trunc * 10) + 7 * ch + mode)
@@ -416,10 +416,12 @@ def test_pair_cost_storage_invisible(dev, trunc, ch, mode, L):
     left, right = torch.from_numpy(left_np).to(dev), torch.from_numpy(right_np).to(dev)
     for levels, K in ((3, 4), (2, 5)):
         p = bp.BPParams(levels=levels, iters=K, lam=3.5, tau=1.5)
-        a = bp.run(bp.cost_volume(left, right, L, trunc, downsample=s, rgb_mode=mode), p, want_msgs=True)
-        b = bp.run(bp.Pair(left, right, L, trunc, downsample=s, rgb_mode=mode), p, want_msgs=True)
+        a = bp.run(bp.cost_volume(left, right, L, trunc, downsample=s, rgb_mode=mode), p, want_msgs=True,
+                   want_soft=True)
+        b = bp.run(bp.Pair(left, right, L, trunc, downsample=s, rgb_mode=mode), p, want_msgs=True, want_soft=True)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(b["disp"].cpu().numpy(), a["disp"].cpu().numpy())
+        np.testing.assert_array_equal(b["soft"].cpu().numpy(), a["soft"].cpu().numpy())
         np.testing.assert_array_equal(b["msgs"].cpu().numpy(), a["msgs"].cpu().numpy())
 
 
